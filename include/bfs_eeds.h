@@ -1,0 +1,265 @@
+/*
+ * bfs_eeds.h -- C ABI of the MI355X (gfx950) BFS level-step library.
+ *
+ * The library computes breadth-first-search depths as the paper's EDGE BFS
+ * cascade defines them (Cascade 1, Sec. "Expressing BFS with EDGE"): from
+ * F_0 = {s}, P_0 = {s}, every level computes
+ *     F_{i+1}[d] = OR_s (F_i[s] AND G[s,d]) AND NOT P_i[d]      (Eq. advance)
+ *     P_{i+1}    = P_i OR F_{i+1}                                (Eq. update)
+ * and records depth i+1 for every d in F_{i+1}; the search stops when
+ * F_{i+1} is empty.  Depths are the minimum number of hops from the source
+ * (the problem statement of the same section).  Every variant below reaches
+ * exactly the same depths; the paper's design-space sections (Sec. "The
+ * Einsum-Enabled Design Space", Table 3) describe the transformations that
+ * separate them.
+ *
+ * Conventions shared by every entry point
+ *   - Graph arrays, depth/parent outputs and workspaces are DEVICE pointers
+ *     allocated and owned by the caller; the library never keeps them past
+ *     the call.  Arrays named *_host are host pointers.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call
+ *     enqueues its work on that stream and returns after it has completed,
+ *     so outputs and statistics are valid on return.
+ *   - Return value 0 on success or a negative BFS_E* code; nothing throws.
+ *     bfs_last_error() gives a thread-local message for the last failure.
+ *   - Depth -1 and parent -1 mean "unreached" (the paper's empty value,
+ *     infinity, Cascade 1 tensor declarations).  parents[source] = source.
+ *   - A vertex id is int32; CSR offsets are int32, so nnz < 2^31.
+ *   - Calls on different streams are independent when each has its own
+ *     workspace; two calls sharing a workspace must not overlap.
+ */
+#ifndef BFS_EEDS_H
+#define BFS_EEDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define BFS_OK 0
+#define BFS_EINVAL (-1)     /* null pointer, n <= 0, source out of range, bad count or id */
+#define BFS_EGRAPH (-2)     /* BFS_F_VALIDATE set and the CSR/CSC is malformed */
+#define BFS_EWORKSPACE (-3) /* workspace smaller than bfs_workspace_size() */
+#define BFS_EHIP (-4)       /* a HIP runtime call failed (detail in bfs_last_error) */
+#define BFS_ENOSEL (-5)     /* learned mode with BFS_F_STRICT_SELECTOR and no weights */
+#define BFS_ELEVELCAP (-6)  /* the level loop hit options.max_levels */
+#define BFS_ENOTSUP (-7)    /* requested variant needs CSC arrays that were not given */
+
+const char *bfs_strerror(int code);
+const char *bfs_last_error(void);
+int bfs_version(void);
+
+/* -------------------------------------------------------------- variants
+ * Fixed variants (one per level; each is a point of the paper's design space):
+ *  PUSH_Q_THREAD   top-down over CSR, queue frontier, one lane per frontier
+ *                  vertex, atomic visited claim            (Table 3, variant 2)
+ *  PUSH_Q_BLOCK    top-down, queue, a workgroup flattens the edges of 256
+ *                  frontier vertices and splits them evenly over its lanes;
+ *                  vertices above a degree threshold are split across the whole
+ *                  grid                                    (Table 3, variant 1)
+ *  PUSH_Q_MERGE    top-down, queue, merge-path: the frontier's edge space is
+ *                  flattened by a device-wide degree scan and cut into equal
+ *                  tiles                                   (Table 3, variant 3)
+ *  PUSH_B_ATOMIC   top-down, bitmap frontier in, atomic claim (Table 3, variant 10)
+ *  PUSH_B_NOATOMIC top-down, bitmap frontier, explicit visited mask, no atomics:
+ *                  depth stores are idempotent and the visited/frontier
+ *                  bitmaps are rebuilt by an owner-computes pass
+ *                                                 (Table 3, variants 12/21/24)
+ *  PUSH_Q_NOATOMIC as above with a queue frontier in   (Table 3, variant 21)
+ *  PULL_B          bottom-up over CSC with early exit: each unvisited vertex
+ *                  scans its in-neighbours and stops at the first frontier
+ *                  member (Sec. "From Push to Pull BFS": reassociate, commute,
+ *                  reassociate, loop order d -> s)
+ * Every step emits the next frontier both as a queue and as a bitmap, so the
+ * format of the next level is a free choice.
+ */
+#define BFS_V_PUSH_Q_THREAD 0
+#define BFS_V_PUSH_Q_BLOCK 1
+#define BFS_V_PUSH_Q_MERGE 2
+#define BFS_V_PUSH_B_ATOMIC 3
+#define BFS_V_PUSH_B_NOATOMIC 4
+#define BFS_V_PUSH_Q_NOATOMIC 5
+#define BFS_V_PULL_B 6
+#define BFS_NUM_VARIANTS 7
+/* Per-level choice modes. */
+#define BFS_AUTO_HEURISTIC 100 /* Beamer direction-optimising rule (alpha 14, beta 24) */
+#define BFS_AUTO_LEARNED 101   /* selector network on device; heuristic fallback */
+#define BFS_SCHEDULE 102       /* options.schedule_host[k] at level k (last entry repeats) */
+
+/* options.flags */
+#define BFS_F_VALIDATE 1         /* check CSR/CSC structure before running (O(n+nnz)) */
+#define BFS_F_STRICT_SELECTOR 2  /* learned mode without weights fails with BFS_ENOSEL */
+#define BFS_F_LEVEL_STATS 4      /* fill the per-level arrays of bfs_stats */
+#define BFS_F_DEVICE_LOOP 8      /* choose variants on the device and read the frontier
+                                    size back only every few levels (fewer host syncs) */
+
+/* ----------------------------------------------------------------- types */
+typedef struct bfs_graph {
+  int32_t n;               /* vertices, > 0 */
+  int32_t nnz;             /* directed edges (CSR entries) */
+  const int32_t *row_ptr;  /* device [n+1], out-edges of u in col_idx[row_ptr[u] .. row_ptr[u+1]) */
+  const int32_t *col_idx;  /* device [nnz] */
+  const int32_t *csc_ptr;  /* device [n+1] in-edges (transpose); may equal row_ptr for a
+                              symmetric graph; NULL => pull variants unavailable */
+  const int32_t *csc_idx;  /* device [nnz], ascending within each column for a
+                              deterministic early exit */
+} bfs_graph;
+
+typedef struct bfs_options {
+  int32_t variant;               /* BFS_V_* or BFS_AUTO_* / BFS_SCHEDULE */
+  int32_t flags;                 /* BFS_F_* */
+  const int32_t *schedule_host;  /* BFS_SCHEDULE: variant per level */
+  int32_t schedule_len;
+  int32_t max_levels;            /* 0 => n + 1 */
+  int32_t heuristic_push;        /* push variant used by the heuristic (-1 => default) */
+  int32_t heuristic_pull;        /* pull variant used by the heuristic (-1 => default) */
+  void *workspace;               /* device scratch, or NULL for a library-cached buffer */
+  size_t workspace_bytes;
+} bfs_options;
+
+typedef struct bfs_stats {
+  int32_t num_levels;       /* 1 + largest depth */
+  int32_t fell_back;        /* learned mode fell back to the heuristic at >= 1 level */
+  int64_t reached;          /* vertices with depth >= 0 */
+  int64_t component_edges;  /* sum of out-degrees of reached vertices (CSR entries) */
+  float elapsed_ms;         /* device time from the first kernel to the last */
+  int32_t host_syncs;       /* stream synchronisations the level loop made */
+  /* Per-level arrays (host, caller-owned, level_capacity entries each; any may
+   * be NULL); filled when BFS_F_LEVEL_STATS is set.  Entry k describes level k:
+   * the variant that expanded F_k, |F_k|, out-edges of F_k, |U_k| and in-edges
+   * of U_k, where U_k is the set unvisited after F_k was found. */
+  int32_t level_capacity;
+  int32_t *level_variant;
+  int64_t *level_frontier;
+  int64_t *level_frontier_edges;
+  int64_t *level_unvisited;
+  int64_t *level_unvisited_edges;
+  int32_t *level_fallback;   /* learned mode: 1 where the heuristic decided */
+  int64_t *level_frontier_ld;  /* sum over F_k of floor(log2(1 + outdeg)) */
+  int64_t *level_frontier_ld2; /* sum over F_k of floor(log2(1 + outdeg))^2 */
+  int64_t graph_ld, graph_ld2; /* the same two sums over all of V (learned mode) */
+} bfs_stats;
+
+/* Workspace bytes for a graph of n vertices.  lanes = 1 for bfs_levels /
+ * bfs_parents, 2..64 for bfs_multi (bit-packed lanes, u64 words per vertex). */
+int bfs_workspace_size(int32_t n, int32_t lanes, size_t *bytes);
+
+/* Single-source BFS depths.  levels: device [n] int32, written in full.
+ * opt may be NULL (learned mode when weights are loaded, else heuristic).
+ * st may be NULL. */
+int bfs_levels(const bfs_graph *g, int32_t source, int32_t *levels,
+               const bfs_options *opt, bfs_stats *st, void *stream);
+
+/* As bfs_levels, and parents: device [n] int32.  parents[v] is some
+ * in-neighbour of v at depth(v)-1 (the cascade's ANY reduction, Cascade 1,
+ * Eq. advance: any one of the duplicate sources), so two runs may return
+ * different but equally valid parents. */
+int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *parents,
+                const bfs_options *opt, bfs_stats *st, void *stream);
+
+/* Multi-source BFS over k sources (Cascade 1 with source node(s): one extra
+ * lane rank on F and P).  Sources are processed in groups of up to 64 lanes;
+ * lane l of vertex v lives in bit l of one u64 word, so a level is
+ *     next[v] = (OR_{u in N_in(v)} front[u]) AND NOT vis[v]
+ * on whole words.  sources_host: host [k]; levels: device [k][n] int32
+ * (row i = depths from sources_host[i]).  st->component_edges sums over rows.
+ * opt->variant: BFS_V_PUSH_Q_THREAD/BLOCK/MERGE select top-down, BFS_V_PULL_B
+ * bottom-up, anything else the per-level heuristic. */
+int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_t *levels,
+              const bfs_options *opt, bfs_stats *st, void *stream);
+
+/* ----------------------------------------------------------------- batch
+ * Many independent graphs stored back to back (a disjoint union).  Instance b
+ * owns global vertices [v_off[b], v_off[b+1]); row_ptr has total_n+1 GLOBAL
+ * entry offsets; col_idx holds LOCAL vertex ids of the same instance.  All
+ * instances are searched in one persistent launch. */
+typedef struct bfs_graph_batch {
+  int32_t num;               /* instances, > 0 */
+  int32_t total_n;
+  int32_t total_nnz;
+  const int64_t *v_off_host; /* host [num+1] */
+  const int64_t *e_off_host; /* host [num+1] */
+  const int32_t *row_ptr;    /* device [total_n+1] */
+  const int32_t *col_idx;    /* device [total_nnz] */
+} bfs_graph_batch;
+
+typedef struct bfs_batch_config {
+  int32_t block_threads;     /* 256, 512 or 1024 */
+  int32_t small_vertices;    /* instances with n <= this run inside one workgroup with
+                                LDS bitmaps; others are cut into vertex chunks */
+  int32_t chunk_vertices;    /* vertex-chunk size of a large-instance task */
+  int32_t blocks_per_cu;     /* resident workgroups per compute unit (1..8) */
+} bfs_batch_config;
+
+/* levels: device [total_n] int32, per instance in local depth terms.
+ * sources_host: host [num] local ids.  cfg NULL => defaults (or the last
+ * autotuned config for a batch of the same signature). */
+int bfs_batch(const bfs_graph_batch *b, const int32_t *sources_host, int32_t *levels,
+              const bfs_batch_config *cfg, bfs_stats *st, void *stream);
+
+/* Times candidate configs on this batch and returns the fastest in *best
+ * (and caches it under the batch's size signature).  levels is device
+ * scratch of total_n ints.  ms_best may be NULL. */
+int bfs_batch_autotune(const bfs_graph_batch *b, const int32_t *sources_host, int32_t *levels,
+                       bfs_batch_config *best, float *ms_best, void *stream);
+
+/* -------------------------------------------------------------- selector
+ * Per-level variant selector: 12 features -> 64 -> 64 -> 4 (ReLU), weights
+ * used in bfloat16 (round to nearest even), layer inputs rounded to bfloat16,
+ * fp32 accumulation starting from the bias in ascending input order.
+ * Parameter layout (5,252 fp32): W1[64][12], b1[64], W2[64][64], b2[64],
+ * W3[4][64], b3[4]; weights are [out][in] row-major.
+ * Features of level k, with ld(v) = floor(log2(1 + outdeg(v))) (exact
+ * integer sums; computed in fp64, then rounded to fp32):
+ *   0 log2(1+|F|)  1 log2(1+eF)  2 log2(1+|U|)  3 log2(1+eU)
+ *   4 |F|/n  5 eF/nnz  6 |U|/n  7 mean of ld over F  8 variance of ld over F
+ *   9 mean of ld over V  10 variance of ld over V  11 log2(1+k)
+ * normalised as (x - mean) / std in fp32.  The selector falls back to the
+ * heuristic at a level when the top softmax probability is below
+ * min_confidence or a raw feature lies outside [feat_min, feat_max]. */
+#define BFS_MLP_NPARAM 5252
+#define BFS_MLP_NFEAT 12
+#define BFS_MLP_NCLASS 4
+int bfs_selector_set(const float *params_host, const float *feat_mean_host,
+                     const float *feat_std_host, const float *feat_min_host,
+                     const float *feat_max_host, float min_confidence,
+                     const int32_t *class_variant_host /* [4] BFS_V_* */);
+int bfs_selector_clear(void);
+int bfs_selector_loaded(void);
+
+/* Training kernels (device pointers; used by the selector's trainer and by
+ * the gradient checks).  x: [batch][12] normalised features. */
+int bfs_mlp_forward(const float *params, const float *x, int32_t batch, float *logits,
+                    void *stream);
+/* Mean softmax cross-entropy loss (device scalar) and its gradient w.r.t. the
+ * fp32 master parameters (straight-through through every bf16 rounding). */
+int bfs_mlp_loss_grad(const float *params, const float *x, const int32_t *labels,
+                      int32_t batch, float *grad, float *loss, void *stream);
+/* One Adam step (Kingma & Ba, bias-corrected) on params in place. */
+int bfs_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step,
+                 float lr, float beta1, float beta2, float eps, void *stream);
+/* Argmax class (ties to the lowest index) and top softmax probability. */
+int bfs_mlp_predict(const float *params, const float *x, int32_t batch, int32_t *cls,
+                    float *conf, void *stream);
+/* Raw (unnormalised) features of every level recorded in st (filled by a
+ * bfs_levels/bfs_parents call with BFS_F_LEVEL_STATS and all per-level
+ * arrays), computed by the same code the device selector runs.
+ * feats_host: host [st->num_levels][12]. */
+int bfs_level_features(const bfs_stats *st, int32_t n, int32_t nnz, float *feats_host);
+
+/* ------------------------------------------------------- per-level timing
+ * Restores the exact state of level k from the depths of a finished search
+ * (F_k = {depth = k}, P_k = {0 <= depth <= k}), runs one step of `variant`
+ * `reps` times from that state and returns the median device time in ms.
+ * depths: device [n] (read only); scratch_levels: device [n]. */
+int bfs_step_time(const bfs_graph *g, const int32_t *depths, int32_t k, int32_t variant,
+                  int32_t reps, int32_t *scratch_levels, const bfs_options *opt,
+                  float *ms_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFS_EEDS_H */

@@ -1,0 +1,334 @@
+"""Python face of the C ABI: same entry-point names, torch tensors in and out.
+
+Only marshalling happens here: tensors become device pointers, the current
+torch stream becomes the hipStream_t, and per-level statistics come back as
+numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_i32(a, device) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.int32).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+
+
+class DeviceGraph:
+    """int32 CSR (and CSC) resident on the GPU.  For a symmetric graph the CSC
+    arrays alias the CSR ones."""
+
+    def __init__(self, n: int, row_ptr, col_idx, csc_ptr=None, csc_idx=None, symmetric=False,
+                 device="cuda"):
+        self.n = int(n)
+        self.row_ptr = _dev_i32(row_ptr, device)
+        self.col_idx = _dev_i32(col_idx, device)
+        self.nnz = int(self.col_idx.numel())
+        self.symmetric = symmetric
+        if symmetric:
+            self.csc_ptr, self.csc_idx = self.row_ptr, self.col_idx
+        elif csc_ptr is not None:
+            self.csc_ptr, self.csc_idx = _dev_i32(csc_ptr, device), _dev_i32(csc_idx, device)
+        else:
+            self.csc_ptr = self.csc_idx = None
+        self._c = L.BfsGraph(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                             self.csc_ptr.data_ptr() if self.csc_ptr is not None else None,
+                             self.csc_idx.data_ptr() if self.csc_idx is not None else None)
+
+    @classmethod
+    def from_graph(cls, g, device="cuda", with_csc=True):
+        """From a graphgen.Graph (host numpy arrays)."""
+        if with_csc and not g.symmetric:
+            g.with_csc()
+            return cls(g.n, g.row_ptr, g.col_idx, g.csc_ptr, g.csc_idx, False, device)
+        return cls(g.n, g.row_ptr, g.col_idx, symmetric=g.symmetric and with_csc, device=device)
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def workspace_size(n: int, lanes: int = 1) -> int:
+    b = ctypes.c_size_t(0)
+    L.check(L.load().bfs_workspace_size(n, lanes, ctypes.byref(b)), "bfs_workspace_size")
+    return int(b.value)
+
+
+class _StatsBuf:
+    def __init__(self, cap: int):
+        self.cap = cap
+        self.variant = np.zeros(cap, np.int32)
+        self.frontier = np.zeros(cap, np.int64)
+        self.frontier_edges = np.zeros(cap, np.int64)
+        self.unvisited = np.zeros(cap, np.int64)
+        self.unvisited_edges = np.zeros(cap, np.int64)
+        self.fallback = np.zeros(cap, np.int32)
+        self.fld = np.zeros(cap, np.int64)
+        self.fld2 = np.zeros(cap, np.int64)
+        P32, P64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+        self.s = L.BfsStats()
+        self.s.level_capacity = cap
+        self.s.level_variant = self.variant.ctypes.data_as(P32)
+        self.s.level_frontier = self.frontier.ctypes.data_as(P64)
+        self.s.level_frontier_edges = self.frontier_edges.ctypes.data_as(P64)
+        self.s.level_unvisited = self.unvisited.ctypes.data_as(P64)
+        self.s.level_unvisited_edges = self.unvisited_edges.ctypes.data_as(P64)
+        self.s.level_fallback = self.fallback.ctypes.data_as(P32)
+        self.s.level_frontier_ld = self.fld.ctypes.data_as(P64)
+        self.s.level_frontier_ld2 = self.fld2.ctypes.data_as(P64)
+
+    def as_dict(self, per_level: bool):
+        s = self.s
+        d = dict(num_levels=s.num_levels, fell_back=s.fell_back, reached=s.reached,
+                 component_edges=s.component_edges, elapsed_ms=s.elapsed_ms, host_syncs=s.host_syncs,
+                 graph_ld=s.graph_ld, graph_ld2=s.graph_ld2)
+        if per_level:
+            k = min(s.num_levels, self.cap)
+            d.update(variant=self.variant[:k].copy(), frontier=self.frontier[:k].copy(),
+                     frontier_edges=self.frontier_edges[:k].copy(), unvisited=self.unvisited[:k].copy(),
+                     unvisited_edges=self.unvisited_edges[:k].copy(), fallback=self.fallback[:k].copy(),
+                     frontier_ld=self.fld[:k].copy(), frontier_ld2=self.fld2[:k].copy())
+        return d
+
+
+def _options(variant, flags, schedule, workspace, max_levels, heuristic_push):
+    opt = L.BfsOptions()
+    opt.variant = int(variant)
+    opt.flags = int(flags)
+    opt.max_levels = int(max_levels)
+    opt.heuristic_push = -1 if heuristic_push is None else int(heuristic_push)
+    opt.heuristic_pull = -1
+    keep = []
+    if schedule is not None:
+        arr = np.ascontiguousarray(schedule, dtype=np.int32)
+        keep.append(arr)
+        opt.schedule_host = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        opt.schedule_len = int(arr.size)
+    if workspace is not None:
+        opt.workspace = workspace.data_ptr()
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    return opt, keep
+
+
+def _run_single(fn_name, g: DeviceGraph, source, want_parents, variant, flags, schedule, level_stats,
+                workspace, levels, parents, max_levels, heuristic_push, stream, stats_capacity):
+    lib = L.load()
+    dev = g.row_ptr.device
+    if levels is None:
+        levels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    if want_parents and parents is None:
+        parents = torch.empty(g.n, dtype=torch.int32, device=dev)
+    if level_stats:
+        flags |= L.F_LEVEL_STATS
+    sb = _StatsBuf(stats_capacity if level_stats else 0)
+    opt, keep = _options(variant, flags, schedule, workspace, max_levels, heuristic_push)
+    if want_parents:
+        rc = lib.bfs_parents(g.c, int(source), _ptr(levels), _ptr(parents), ctypes.byref(opt),
+                             ctypes.byref(sb.s), _stream(stream))
+    else:
+        rc = lib.bfs_levels(g.c, int(source), _ptr(levels), ctypes.byref(opt), ctypes.byref(sb.s),
+                            _stream(stream))
+    L.check(rc, fn_name)
+    del keep
+    return levels, parents, sb.as_dict(level_stats)
+
+
+def bfs_levels(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, flags: int = 0,
+               schedule: Optional[Sequence[int]] = None, level_stats: bool = False, workspace=None,
+               levels=None, max_levels: int = 0, heuristic_push=None, stream=None,
+               stats_capacity: int = 1 << 16):
+    """Depths from `source`; returns (levels int32 tensor, stats dict)."""
+    lv, _, st = _run_single("bfs_levels", g, source, False, variant, flags, schedule, level_stats, workspace,
+                            levels, None, max_levels, heuristic_push, stream, stats_capacity)
+    return lv, st
+
+
+def bfs_parents(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, flags: int = 0,
+                schedule: Optional[Sequence[int]] = None, level_stats: bool = False, workspace=None,
+                levels=None, parents=None, max_levels: int = 0, heuristic_push=None, stream=None,
+                stats_capacity: int = 1 << 16):
+    """Depths and a valid BFS parent per vertex; returns (levels, parents, stats)."""
+    return _run_single("bfs_parents", g, source, True, variant, flags, schedule, level_stats, workspace,
+                       levels, parents, max_levels, heuristic_push, stream, stats_capacity)
+
+
+def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: int = 0, workspace=None,
+              levels=None, stream=None):
+    """Depths [k][n] from k sources in 64-lane bit-packed groups."""
+    lib = L.load()
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.size)
+    if levels is None:
+        levels = torch.empty((max(k, 1), g.n), dtype=torch.int32, device=g.row_ptr.device)
+    sb = _StatsBuf(0)
+    opt, keep = _options(variant, flags, None, workspace, 0, None)
+    rc = lib.bfs_multi(g.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k, _ptr(levels),
+                       ctypes.byref(opt), ctypes.byref(sb.s), _stream(stream))
+    L.check(rc, "bfs_multi")
+    return levels[:k], sb.as_dict(False)
+
+
+@dataclass
+class BatchConfig:
+    block_threads: int = 256
+    small_vertices: int = 65536
+    chunk_vertices: int = 4096
+    blocks_per_cu: int = 2
+
+    def c(self):
+        return L.BfsBatchConfig(self.block_threads, self.small_vertices, self.chunk_vertices, self.blocks_per_cu)
+
+    @classmethod
+    def from_c(cls, c):
+        return cls(c.block_threads, c.small_vertices, c.chunk_vertices, c.blocks_per_cu)
+
+
+class DeviceBatch:
+    """A graphgen.GraphBatch resident on the GPU."""
+
+    def __init__(self, b, device="cuda"):
+        self.num = b.num
+        self.total_n = b.total_n
+        self.total_nnz = b.total_nnz
+        self.v_off = np.ascontiguousarray(b.v_off, dtype=np.int64)
+        self.e_off = np.ascontiguousarray(b.e_off, dtype=np.int64)
+        self.row_ptr = _dev_i32(b.row_ptr, device)
+        self.col_idx = _dev_i32(b.col_idx, device)
+        self.sources = np.ascontiguousarray(b.sources, dtype=np.int32)
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        self._c = L.BfsGraphBatch(self.num, self.total_n, self.total_nnz, self.v_off.ctypes.data_as(P64),
+                                  self.e_off.ctypes.data_as(P64), self.row_ptr.data_ptr(), self.col_idx.data_ptr())
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def bfs_batch(b: DeviceBatch, sources=None, config: Optional[BatchConfig] = None, levels=None, stream=None):
+    lib = L.load()
+    src = np.ascontiguousarray(b.sources if sources is None else sources, dtype=np.int32)
+    if levels is None:
+        levels = torch.empty(b.total_n, dtype=torch.int32, device=b.row_ptr.device)
+    sb = _StatsBuf(0)
+    cfg = config.c() if config is not None else None
+    rc = lib.bfs_batch(b.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(levels),
+                       ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(sb.s), _stream(stream))
+    L.check(rc, "bfs_batch")
+    return levels, sb.as_dict(False)
+
+
+def bfs_batch_autotune(b: DeviceBatch, sources=None, levels=None, stream=None):
+    lib = L.load()
+    src = np.ascontiguousarray(b.sources if sources is None else sources, dtype=np.int32)
+    if levels is None:
+        levels = torch.empty(b.total_n, dtype=torch.int32, device=b.row_ptr.device)
+    best = L.BfsBatchConfig()
+    ms = ctypes.c_float(0)
+    rc = lib.bfs_batch_autotune(b.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(levels),
+                                ctypes.byref(best), ctypes.byref(ms), _stream(stream))
+    L.check(rc, "bfs_batch_autotune")
+    return BatchConfig.from_c(best), float(ms.value)
+
+
+# ------------------------------------------------------------------ selector
+
+def _f32p(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def selector_set(params, mean, std, fmin, fmax, min_confidence: float, class_variants):
+    keep = [_f32p(x) for x in (params, mean, std, fmin, fmax)]
+    cv = np.ascontiguousarray(class_variants, dtype=np.int32)
+    rc = L.load().bfs_selector_set(*[k[1] for k in keep], float(min_confidence),
+                                   cv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    L.check(rc, "bfs_selector_set")
+
+
+def selector_clear():
+    L.check(L.load().bfs_selector_clear(), "bfs_selector_clear")
+
+
+def selector_loaded() -> bool:
+    return bool(L.load().bfs_selector_loaded())
+
+
+def mlp_forward(params: torch.Tensor, x: torch.Tensor, stream=None) -> torch.Tensor:
+    B = x.shape[0]
+    out = torch.empty((B, L.MLP_NCLASS), dtype=torch.float32, device=x.device)
+    L.check(L.load().bfs_mlp_forward(_ptr(params), _ptr(x), B, _ptr(out), _stream(stream)), "bfs_mlp_forward")
+    return out
+
+
+def mlp_predict(params: torch.Tensor, x: torch.Tensor, stream=None):
+    B = x.shape[0]
+    cls = torch.empty(B, dtype=torch.int32, device=x.device)
+    conf = torch.empty(B, dtype=torch.float32, device=x.device)
+    L.check(L.load().bfs_mlp_predict(_ptr(params), _ptr(x), B, _ptr(cls), _ptr(conf), _stream(stream)),
+            "bfs_mlp_predict")
+    return cls, conf
+
+
+def mlp_loss_grad(params: torch.Tensor, x: torch.Tensor, labels: torch.Tensor, grad=None, loss=None, stream=None):
+    B = x.shape[0]
+    if grad is None:
+        grad = torch.empty(L.MLP_NPARAM, dtype=torch.float32, device=x.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    L.check(L.load().bfs_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(labels), B, _ptr(grad), _ptr(loss),
+                                       _stream(stream)), "bfs_mlp_loss_grad")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    L.check(L.load().bfs_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                                  float(beta2), float(eps), _stream(stream)), "bfs_mlp_adam")
+
+
+def level_features(stats: dict, n: int, nnz: int) -> np.ndarray:
+    """Raw selector features of each level of a finished search (stats from a
+    bfs_levels/bfs_parents call with level_stats=True)."""
+    k = int(stats["num_levels"])
+    sb = _StatsBuf(k)
+    sb.s.num_levels = k
+    sb.s.graph_ld = int(stats["graph_ld"])
+    sb.s.graph_ld2 = int(stats["graph_ld2"])
+    sb.frontier[:] = stats["frontier"]
+    sb.frontier_edges[:] = stats["frontier_edges"]
+    sb.unvisited[:] = stats["unvisited"]
+    sb.unvisited_edges[:] = stats["unvisited_edges"]
+    sb.fld[:] = stats["frontier_ld"]
+    sb.fld2[:] = stats["frontier_ld2"]
+    out = np.zeros((k, L.MLP_NFEAT), dtype=np.float32)
+    L.check(L.load().bfs_level_features(ctypes.byref(sb.s), int(n), int(nnz),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "bfs_level_features")
+    return out
+
+
+def step_time(g: DeviceGraph, depths: torch.Tensor, k: int, variant: int, reps: int = 3, scratch=None,
+              workspace=None, stream=None) -> float:
+    """Median device time (ms) of one step of `variant` from the exact state of level k."""
+    if scratch is None:
+        scratch = torch.empty(g.n, dtype=torch.int32, device=depths.device)
+    opt, keep = _options(0, 0, None, workspace, 0, None)
+    ms = ctypes.c_float(0)
+    L.check(L.load().bfs_step_time(g.c, _ptr(depths), int(k), int(variant), int(reps), _ptr(scratch),
+                                   ctypes.byref(opt), ctypes.byref(ms), _stream(stream)), "bfs_step_time")
+    return float(ms.value)

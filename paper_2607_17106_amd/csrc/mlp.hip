@@ -1,0 +1,420 @@
+// Selector network kernels: device-side per-level selection (inference on one
+// feature vector), batched forward, loss/gradient and Adam for training.
+//
+// Network: x (12 normalised features) -> h0 = bf16(x)
+//   z1 = b1 + W1 h0, h1 = bf16(relu(z1))
+//   z2 = b2 + W2 h1, h2 = bf16(relu(z2))
+//   logits = b3 + W3 h2
+// with W = bf16(W_master).  Each output is accumulated in fp32 starting from
+// its bias, adding products in ascending input order.  A product of two bf16
+// values is exact in fp32, so a fused multiply-add gives the same result as a
+// separate multiply and add; the order is what makes the result reproducible.
+// Backward treats each bf16 rounding as the identity (straight-through).
+#include <string.h>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "selector.hpp"
+
+namespace bfs {
+
+// fp32 -> bf16 bits, round to nearest even (NaN kept quiet).
+__host__ __device__ inline u16 f2bf(float f) {
+  union { float f; u32 u; } x;
+  x.f = f;
+  if ((x.u & 0x7f800000u) == 0x7f800000u && (x.u & 0x007fffffu)) return (u16)((x.u >> 16) | 0x40u);
+  u32 lsb = (x.u >> 16) & 1u;
+  return (u16)((x.u + 0x7fffu + lsb) >> 16);
+}
+__host__ __device__ inline float bf2f(u16 b) {
+  union { float f; u32 u; } x;
+  x.u = ((u32)b) << 16;
+  return x.f;
+}
+__device__ inline float bfr(float f) { return bf2f(f2bf(f)); }
+
+// Weight access: pre-rounded bf16 storage (selector) or fp32 masters rounded
+// on the fly (training); both yield the same fp32 values.
+struct WBf16 {
+  const u16 *w;
+  __device__ float operator()(int i) const { return bf2f(w[i]); }
+};
+struct WMaster {
+  const float *p;
+  __device__ float operator()(int i) const { return bfr(p[i]); }
+};
+
+// Forward of one row by one wave (64 lanes).  h0/h1/h2 are wave-private LDS
+// rows; returns logits in lanes 0..3 (other lanes return 0) and leaves the
+// pre-activations z1/z2 in the caller's registers.
+template <class W>
+__device__ inline float forward_row(const W &wt, const float *p, const float *x, float *h0, float *h1, float *h2,
+                                    float &z1, float &z2) {
+  const int l = lane();
+  if (l < NF) h0[l] = bfr(x[l]);
+  __builtin_amdgcn_wave_barrier();
+  float acc = p[OFF_B1 + l];
+  for (int k = 0; k < NF; ++k) acc = acc + h0[k] * wt(OFF_W1 + l * NF + k);
+  z1 = acc;
+  h1[l] = bfr(fmaxf(acc, 0.f));
+  __builtin_amdgcn_wave_barrier();
+  acc = p[OFF_B2 + l];
+  for (int k = 0; k < NH; ++k) acc = acc + h1[k] * wt(OFF_W2 + l * NH + k);
+  z2 = acc;
+  h2[l] = bfr(fmaxf(acc, 0.f));
+  __builtin_amdgcn_wave_barrier();
+  float out = 0.f;
+  if (l < NC) {
+    acc = p[OFF_B3 + l];
+    for (int k = 0; k < NH; ++k) acc = acc + h2[k] * wt(OFF_W3 + l * NH + k);
+    out = acc;
+  }
+  return out;
+}
+
+// Argmax over lanes 0..3 (ties to the lowest index) and the top softmax
+// probability, 1 / sum_j exp(l_j - l_max).
+__device__ inline void argmax_conf(float logit, int *cls, float *conf) {
+  float l0 = __shfl(logit, 0), l1 = __shfl(logit, 1), l2 = __shfl(logit, 2), l3 = __shfl(logit, 3);
+  float L[4] = {l0, l1, l2, l3};
+  int best = 0;
+  for (int j = 1; j < NC; ++j)
+    if (L[j] > L[best]) best = j;
+  float s = 0.f;
+  for (int j = 0; j < NC; ++j) s += expf(L[j] - L[best]);
+  *cls = best;
+  *conf = 1.f / s;
+}
+
+// ------------------------------------------------------ device selection
+// Runs after the step that produced F_k: updates the running unvisited
+// totals, advances the direction rule, evaluates the network on F_k's
+// features and stores the choice in ring[k % RING].decision.
+__global__ __launch_bounds__(64) void k_select(SelDevice sd, LevelCtr *ring, int k, int n, int nnz,
+                                               const u64 *gsum, int init) {
+  __shared__ float s_x[NF], h0[NH], h1[NH], h2[NH];
+  __shared__ int s_hv;
+  LevelCtr *c = ring + (k % RING);
+  long long *st = reinterpret_cast<long long *>(sd.state);
+  const long long nF = c->count;
+  if (lane() == 0) {
+    if (init) {
+      st[0] = (long long)n;
+      st[1] = (long long)nnz;
+      st[2] = 0;
+      st[3] = -1;
+    }
+    st[0] -= nF;
+    st[1] -= (long long)c->in_edges;
+    // direction rule
+    long long eF = (long long)c->edges, eU = st[1];
+    int dir = (int)st[2];
+    if (dir == 0) {
+      if (eF * HeuristicState::kAlpha > eU) dir = 1;
+    } else {
+      bool shrinking = st[3] >= 0 && nF < st[3];
+      if (nF * HeuristicState::kBeta < (long long)n && shrinking) dir = 0;
+    }
+    st[2] = dir;
+    st[3] = nF;
+    s_hv = dir ? sd.pull_v : sd.push_v;
+    float f[NF];
+    level_features((double)n, (double)nnz, (double)k, (double)nF, (double)c->edges, (double)st[0], (double)st[1],
+                   (double)c->ld, (double)c->ld2, (double)gsum[0], (double)gsum[1], f);
+    for (int i = 0; i < NF; ++i) s_x[i] = f[i];
+  }
+  __builtin_amdgcn_wave_barrier();
+  // range check on raw features, then normalise
+  bool out_of_range = false;
+  float xn = 0.f;
+  if (lane() < NF) {
+    float r = s_x[lane()];
+    out_of_range = r < sd.norm[2 * NF + lane()] || r > sd.norm[3 * NF + lane()];
+    xn = (r - sd.norm[lane()]) / sd.norm[NF + lane()];
+  }
+  const bool any_oor = __ballot(out_of_range) != 0ull;
+  __builtin_amdgcn_wave_barrier();
+  if (lane() < NF) s_x[lane()] = xn;
+  __builtin_amdgcn_wave_barrier();
+  float z1, z2;
+  float logit = forward_row(WBf16{sd.w}, sd.p, s_x, h0, h1, h2, z1, z2);
+  int cls;
+  float conf;
+  argmax_conf(logit, &cls, &conf);
+  if (lane() == 0) {
+    int fb = any_oor || !(conf >= sd.min_conf);
+    c->decision = fb ? s_hv : sd.cls[cls];
+    c->fallback = fb;
+  }
+}
+
+// ------------------------------------------------------------ selector set
+struct SelectorHost {
+  bool loaded = false;
+  int dev = -1;
+  void *buf = nullptr;  // [bf16 weights NPARAM u16 | fp32 params NPARAM | norm 4*NF]
+  float min_conf = 0.f;
+  int cls[NC] = {0, 1, 2, 3};
+};
+static std::mutex g_sel_mu;
+static SelectorHost g_sel[64];
+
+static int cur_dev() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return 0;
+  return (d >= 0 && d < 64) ? d : 0;
+}
+
+bool selector_loaded() {
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  return g_sel[cur_dev()].loaded;
+}
+
+SelDevice selector_device(const Workspace &w, int push_v, int pull_v) {
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  SelectorHost &h = g_sel[cur_dev()];
+  SelDevice d;
+  char *b = (char *)h.buf;
+  d.w = (const u16 *)b;
+  d.p = (const float *)(b + ((NPARAM * 2 + 255) & ~255));
+  d.norm = d.p + NPARAM;
+  d.min_conf = h.min_conf;
+  for (int i = 0; i < NC; ++i) d.cls[i] = h.cls[i];
+  d.state = w.gsum + 2;
+  d.push_v = push_v;
+  d.pull_v = pull_v;
+  return d;
+}
+
+hipError_t launch_select(const SelDevice &sd, LevelCtr *ring, int k, int n, int nnz, const u64 *gsum,
+                         hipStream_t s, bool init) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, sd, ring, k, n, nnz, gsum, init ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- training kernels
+constexpr int MLP_BLOCK = 256;  // 4 waves, one row per wave at a time
+
+__global__ __launch_bounds__(MLP_BLOCK) void k_mlp_forward(const float *p, const float *x, int batch,
+                                                           float *logits, int *cls, float *conf) {
+  __shared__ float s_h[MLP_BLOCK / WAVE][3][NH];
+  const int wv = threadIdx.x / WAVE;
+  float *h0 = s_h[wv][0], *h1 = s_h[wv][1], *h2 = s_h[wv][2];
+  for (int r = blockIdx.x * (MLP_BLOCK / WAVE) + wv; r < batch; r += gridDim.x * (MLP_BLOCK / WAVE)) {
+    float z1, z2;
+    float lg = forward_row(WMaster{p}, p, x + (size_t)r * NF, h0, h1, h2, z1, z2);
+    if (logits && lane() < NC) logits[(size_t)r * NC + lane()] = lg;
+    if (cls) {
+      int c;
+      float cf;
+      argmax_conf(lg, &c, &cf);
+      if (lane() == 0) {
+        cls[r] = c;
+        conf[r] = cf;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Gradient of mean cross-entropy.  A workgroup handles rows in turn: wave 0
+// computes the row's forward and backward vectors into LDS, then all 256
+// threads add the row's outer products into privately owned gradient slots;
+// at the end each owned slot is added to the global gradient once.
+constexpr int GRAD_ROWS = 64;
+__global__ __launch_bounds__(MLP_BLOCK) void k_mlp_grad(const float *p, const float *x, const int *labels,
+                                                        int batch, float *grad, float *loss) {
+  __shared__ float h0[NH], h1[NH], h2[NH], dz1[NH], dz2[NH], dl[NC];
+  __shared__ float s_loss;
+  constexpr int PER = (NPARAM + MLP_BLOCK - 1) / MLP_BLOCK;  // owned slots per thread
+  float acc[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) acc[i] = 0.f;
+  if (threadIdx.x == 0) s_loss = 0.f;
+  const float invB = 1.f / (float)batch;
+  const int r0 = blockIdx.x * GRAD_ROWS;
+  const int r1 = min(batch, r0 + GRAD_ROWS);
+  for (int r = r0; r < r1; ++r) {
+    if (threadIdx.x < WAVE) {
+      const int l = lane();
+      float z1, z2;
+      float lg = forward_row(WMaster{p}, p, x + (size_t)r * NF, h0, h1, h2, z1, z2);
+      float L0 = __shfl(lg, 0), L1 = __shfl(lg, 1), L2 = __shfl(lg, 2), L3 = __shfl(lg, 3);
+      float mx = fmaxf(fmaxf(L0, L1), fmaxf(L2, L3));
+      float e0 = expf(L0 - mx), e1 = expf(L1 - mx), e2 = expf(L2 - mx), e3 = expf(L3 - mx);
+      float se = e0 + e1 + e2 + e3;
+      const int y = labels[r];
+      if (l < NC) {
+        float pj = (l == 0 ? e0 : l == 1 ? e1 : l == 2 ? e2 : e3) / se;
+        dl[l] = (pj - (l == y ? 1.f : 0.f)) * invB;
+      }
+      if (l == 0) {
+        float ly = (y == 0 ? L0 : y == 1 ? L1 : y == 2 ? L2 : L3);
+        s_loss += (logf(se) + mx - ly) * invB;
+      }
+      __builtin_amdgcn_wave_barrier();
+      // dh2[l] = sum_j dl[j] * W3r[j][l]; dz2 = dh2 * (z2 > 0)
+      float d2 = 0.f;
+      for (int j = 0; j < NC; ++j) d2 += dl[j] * bfr(p[OFF_W3 + j * NH + l]);
+      d2 = (z2 > 0.f) ? d2 : 0.f;
+      dz2[l] = d2;
+      __builtin_amdgcn_wave_barrier();
+      float d1 = 0.f;
+      for (int j = 0; j < NH; ++j) d1 += dz2[j] * bfr(p[OFF_W2 + j * NH + l]);
+      d1 = (z1 > 0.f) ? d1 : 0.f;
+      dz1[l] = d1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * MLP_BLOCK;
+      if (q >= NPARAM) break;
+      float gq;
+      if (q < OFF_B1) gq = dz1[q / NF] * h0[q % NF];
+      else if (q < OFF_W2) gq = dz1[q - OFF_B1];
+      else if (q < OFF_B2) gq = dz2[(q - OFF_W2) / NH] * h1[(q - OFF_W2) % NH];
+      else if (q < OFF_W3) gq = dz2[q - OFF_B2];
+      else if (q < OFF_B3) gq = dl[(q - OFF_W3) / NH] * h2[(q - OFF_W3) % NH];
+      else gq = dl[q - OFF_B3];
+      acc[i] += gq;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int q = threadIdx.x + i * MLP_BLOCK;
+    if (q < NPARAM && acc[i] != 0.f) atomicAdd(grad + q, acc[i]);
+  }
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, s_loss);
+}
+
+__global__ void k_mlp_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2,
+                           float eps, float c1, float c2) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float mh = mi / c1, vh = vi / c2;
+    p[i] = p[i] - lr * mh / (sqrtf(vh) + eps);
+  }
+}
+
+}  // namespace bfs
+
+using namespace bfs;
+
+extern "C" {
+
+int bfs_selector_set(const float *params, const float *mean, const float *stdv, const float *fmin,
+                     const float *fmax, float min_confidence, const int32_t *class_variant) {
+  if (!params || !mean || !stdv || !fmin || !fmax || !class_variant) {
+    set_error("bfs_selector_set: null argument");
+    return BFS_EINVAL;
+  }
+  for (int i = 0; i < NC; ++i)
+    if (class_variant[i] < 0 || class_variant[i] >= BFS_NUM_VARIANTS) {
+      set_error("bfs_selector_set: class %d maps to invalid variant %d", i, class_variant[i]);
+      return BFS_EINVAL;
+    }
+  for (int i = 0; i < NF; ++i)
+    if (!(stdv[i] > 0.f)) {
+      set_error("bfs_selector_set: feature std %d is not positive", i);
+      return BFS_EINVAL;
+    }
+  const size_t wbytes = (NPARAM * 2 + 255) & ~(size_t)255;
+  const size_t total = wbytes + (NPARAM + 4 * NF) * sizeof(float);
+  std::vector<char> host(total, 0);
+  u16 *w = (u16 *)host.data();
+  float *p = (float *)(host.data() + wbytes);
+  for (int i = 0; i < NPARAM; ++i) {
+    w[i] = f2bf(params[i]);
+    p[i] = params[i];
+  }
+  float *norm = p + NPARAM;
+  memcpy(norm, mean, NF * 4);
+  memcpy(norm + NF, stdv, NF * 4);
+  memcpy(norm + 2 * NF, fmin, NF * 4);
+  memcpy(norm + 3 * NF, fmax, NF * 4);
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  SelectorHost &h = g_sel[cur_dev()];
+  if (!h.buf) BFS_HIP(hipMalloc(&h.buf, total));
+  BFS_HIP(hipMemcpy(h.buf, host.data(), total, hipMemcpyHostToDevice));
+  h.min_conf = min_confidence;
+  for (int i = 0; i < NC; ++i) h.cls[i] = class_variant[i];
+  h.loaded = true;
+  return BFS_OK;
+}
+
+int bfs_selector_clear(void) {
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  g_sel[cur_dev()].loaded = false;
+  return BFS_OK;
+}
+
+int bfs_selector_loaded(void) { return selector_loaded() ? 1 : 0; }
+
+int bfs_mlp_forward(const float *params, const float *x, int32_t batch, float *logits, void *stream) {
+  if (!params || !x || !logits || batch < 0) return BFS_EINVAL;
+  if (batch == 0) return BFS_OK;
+  int grid = std::min((batch + 3) / 4, 4096);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(MLP_BLOCK), 0, (hipStream_t)stream, params, x, batch, logits,
+                     (int *)nullptr, (float *)nullptr);
+  BFS_HIP(hipGetLastError());
+  BFS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return BFS_OK;
+}
+
+int bfs_mlp_predict(const float *params, const float *x, int32_t batch, int32_t *cls, float *conf, void *stream) {
+  if (!params || !x || !cls || !conf || batch < 0) return BFS_EINVAL;
+  if (batch == 0) return BFS_OK;
+  int grid = std::min((batch + 3) / 4, 4096);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(MLP_BLOCK), 0, (hipStream_t)stream, params, x, batch,
+                     (float *)nullptr, cls, conf);
+  BFS_HIP(hipGetLastError());
+  BFS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return BFS_OK;
+}
+
+int bfs_mlp_loss_grad(const float *params, const float *x, const int32_t *labels, int32_t batch, float *grad,
+                      float *loss, void *stream) {
+  if (!params || !x || !labels || !grad || batch <= 0) return BFS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  BFS_HIP(hipMemsetAsync(grad, 0, NPARAM * sizeof(float), s));
+  if (loss) BFS_HIP(hipMemsetAsync(loss, 0, sizeof(float), s));
+  int grid = (batch + GRAD_ROWS - 1) / GRAD_ROWS;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(MLP_BLOCK), 0, s, params, x, labels, batch, grad, loss);
+  BFS_HIP(hipGetLastError());
+  BFS_HIP(hipStreamSynchronize(s));
+  return BFS_OK;
+}
+
+int bfs_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr, float beta1,
+                 float beta2, float eps, void *stream) {
+  if (!params || !grad || !m || !v || step <= 0) return BFS_EINVAL;
+  float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(k_mlp_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, grad, m, v,
+                     NPARAM, lr, beta1, beta2, eps, c1, c2);
+  BFS_HIP(hipGetLastError());
+  BFS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return BFS_OK;
+}
+
+int bfs_level_features(const bfs_stats *st, int32_t n, int32_t nnz, float *feats) {
+  if (!st || !feats || n <= 0 || !st->level_frontier || !st->level_frontier_edges || !st->level_unvisited ||
+      !st->level_unvisited_edges || !st->level_frontier_ld || !st->level_frontier_ld2) {
+    set_error("bfs_level_features: missing per-level arrays");
+    return BFS_EINVAL;
+  }
+  int L = std::min(st->num_levels, st->level_capacity);
+  for (int k = 0; k < L; ++k)
+    level_features((double)n, (double)nnz, (double)k, (double)st->level_frontier[k],
+                   (double)st->level_frontier_edges[k], (double)st->level_unvisited[k],
+                   (double)st->level_unvisited_edges[k], (double)st->level_frontier_ld[k],
+                   (double)st->level_frontier_ld2[k], (double)st->graph_ld, (double)st->graph_ld2, feats + k * NF);
+  return BFS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,456 @@
+// Host runtime of the single-source BFS: workspace layout, the per-level
+// loop (Cascade 1 iterated until the frontier is empty), per-level variant
+// choice, statistics and the C ABI entry points bfs_levels / bfs_parents.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "selector.hpp"
+
+namespace bfs {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  set_error("%s failed: %s", what, hipGetErrorString(e));
+  return BFS_EHIP;
+}
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static inline int words_of(int n) { return (n + 63) / 64; }
+
+size_t workspace_bytes_single(int n) {
+  const size_t W = (size_t)words_of(n);
+  size_t b = 0;
+  b += align256(W * 8);            // vis
+  b += 3 * align256(W * 8);        // fb[3]
+  b += 2 * align256((size_t)n * 4);  // q[2]
+  b += align256(((size_t)n + 1) * 4);  // scan
+  b += align256(((size_t)n / SCAN_CHUNK + 2) * 4);  // bsum
+  b += align256((size_t)n * 4);    // hubs
+  b += align256(RING * sizeof(LevelCtr));
+  b += align256(64 * 8);           // gsum, selector state
+  return b;
+}
+
+Workspace carve_single(void *base, int n) {
+  Workspace w;
+  const size_t W = (size_t)words_of(n);
+  char *p = (char *)base;
+  auto take = [&](size_t bytes) { char *r = p; p += align256(bytes); return (void *)r; };
+  w.vis = (u64 *)take(W * 8);
+  for (int i = 0; i < 3; ++i) w.fb[i] = (u64 *)take(W * 8);
+  for (int i = 0; i < 2; ++i) w.q[i] = (int *)take((size_t)n * 4);
+  w.scan = (int *)take(((size_t)n + 1) * 4);
+  w.bsum = (int *)take(((size_t)n / SCAN_CHUNK + 2) * 4);
+  w.hubs = (int *)take((size_t)n * 4);
+  w.ctr = (LevelCtr *)take(RING * sizeof(LevelCtr));
+  w.gsum = (u64 *)take(64 * 8);
+  w.W = (int)W;
+  return w;
+}
+
+// ------------------------------------------------- per-thread host context
+struct HostCtx {
+  LevelCtr *pinned = nullptr;  // RING slots + scratch
+  u64 *pinned_u64 = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ok = false;
+  HostCtx() {
+    if (hipHostMalloc((void **)&pinned, 64 * sizeof(LevelCtr), hipHostMallocDefault) != hipSuccess) return;
+    pinned_u64 = reinterpret_cast<u64 *>(pinned + 32);
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) return;
+    ok = true;
+  }
+};
+
+HostCtx &host_ctx() {
+  static thread_local HostCtx c;
+  return c;
+}
+
+// Library-cached workspace for callers that pass none (one per device).
+static std::mutex g_ws_mu;
+static void *g_ws_ptr[64] = {nullptr};
+static size_t g_ws_len[64] = {0};
+
+int cached_workspace(size_t bytes, void **out) {
+  int dev = 0;
+  BFS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return BFS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (g_ws_len[dev] < bytes) {
+    if (g_ws_ptr[dev]) BFS_HIP(hipFree(g_ws_ptr[dev]));
+    g_ws_ptr[dev] = nullptr;
+    g_ws_len[dev] = 0;
+    BFS_HIP(hipMalloc(&g_ws_ptr[dev], bytes));
+    g_ws_len[dev] = bytes;
+  }
+  *out = g_ws_ptr[dev];
+  return BFS_OK;
+}
+
+int check_graph(const bfs_graph *g) {
+  if (!g || g->n <= 0 || g->nnz < 0 || !g->row_ptr || (!g->col_idx && g->nnz > 0)) {
+    set_error("invalid graph (null pointer, n <= 0 or nnz < 0)");
+    return BFS_EINVAL;
+  }
+  if ((g->csc_ptr && !g->csc_idx && g->nnz > 0) || (!g->csc_ptr && g->csc_idx)) {
+    set_error("csc_ptr and csc_idx must both be given or both be NULL");
+    return BFS_EINVAL;
+  }
+  return BFS_OK;
+}
+
+int validate_graph(const bfs_graph *g, u64 *flag_dev, hipStream_t s) {
+  HostCtx &hc = host_ctx();
+  BFS_HIP(hipMemsetAsync(flag_dev, 0, 8, s));
+  BFS_HIP(launch_validate(g->n, g->nnz, g->row_ptr, g->col_idx, flag_dev, s));
+  if (g->csc_ptr && g->csc_ptr != g->row_ptr)
+    BFS_HIP(launch_validate(g->n, g->nnz, g->csc_ptr, g->csc_idx, flag_dev, s));
+  BFS_HIP(hipMemcpyAsync(hc.pinned_u64, flag_dev, 8, hipMemcpyDeviceToHost, s));
+  BFS_HIP(hipStreamSynchronize(s));
+  if (*hc.pinned_u64) {
+    set_error("malformed graph: %s%s", (*hc.pinned_u64 & 1) ? "bad offsets " : "",
+              (*hc.pinned_u64 & 2) ? "column id out of range" : "");
+    return BFS_EGRAPH;
+  }
+  return BFS_OK;
+}
+
+// ------------------------------------------------------ direction rule
+// Beamer, Asanovic, Patterson (SC'12): top-down -> bottom-up when
+// m_f > m_u / alpha; bottom-up -> top-down when n_f < n / beta and the
+// frontier shrank.  alpha = 14, beta = 24.
+void HeuristicState::step(long long n, long long nF, long long eF, long long eU) {
+  if (dir == 0) {
+    if (eF * kAlpha > eU) dir = 1;
+  } else {
+    bool shrinking = prev_nf >= 0 && nF < prev_nf;
+    if (nF * kBeta < n && shrinking) dir = 0;
+  }
+  prev_nf = nF;
+}
+
+static bool is_pull(int v) { return v == BFS_V_PULL_B; }
+
+static StepArgs level_args(const bfs_graph *g, const Workspace &w, int *levels, int *parents, int k, int hub) {
+  StepArgs a;
+  a.n = g->n;
+  a.W = w.W;
+  a.k = k;
+  a.hub = hub;
+  a.rp = g->row_ptr;
+  a.ci = g->col_idx;
+  a.cp = g->csc_ptr;
+  a.cx = g->csc_idx;
+  a.levels = levels;
+  a.parents = parents;
+  a.vis = w.vis;
+  a.fb_cur = w.fb[k % 3];
+  a.fb_next = w.fb[(k + 1) % 3];
+  a.fb_dead = w.fb[(k + 2) % 3];
+  a.q_cur = w.q[k % 2];
+  a.q_next = w.q[(k + 1) % 2];
+  a.c_cur = w.ctr + (k % RING);
+  a.c_next = w.ctr + ((k + 1) % RING);
+  a.c_zero = w.ctr + ((k + 2) % RING);
+  a.scan = w.scan;
+  a.bsum = w.bsum;
+  a.hubs = w.hubs;
+  return a;
+}
+
+static int run_single(const bfs_graph *g, int src, int *levels, int *parents, const bfs_options *opt_in,
+                      bfs_stats *st, hipStream_t s) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (!levels || (parents == nullptr && false)) return BFS_EINVAL;
+  if (src < 0 || src >= g->n) {
+    set_error("source %d out of range [0, %d)", src, g->n);
+    return BFS_EINVAL;
+  }
+  bfs_options dflt;
+  memset(&dflt, 0, sizeof(dflt));
+  dflt.variant = selector_loaded() ? BFS_AUTO_LEARNED : BFS_AUTO_HEURISTIC;
+  dflt.heuristic_push = -1;
+  dflt.heuristic_pull = -1;
+  const bfs_options *opt = opt_in ? opt_in : &dflt;
+  int mode = opt->variant;
+  const bool have_csc = g->csc_ptr != nullptr;
+  if (mode >= 0 && mode < BFS_NUM_VARIANTS) {
+    if (is_pull(mode) && !have_csc) {
+      set_error("pull variant needs CSC arrays");
+      return BFS_ENOTSUP;
+    }
+  } else if (mode == BFS_SCHEDULE) {
+    if (!opt->schedule_host || opt->schedule_len <= 0) {
+      set_error("BFS_SCHEDULE needs schedule_host and schedule_len > 0");
+      return BFS_EINVAL;
+    }
+    for (int i = 0; i < opt->schedule_len; ++i) {
+      int v = opt->schedule_host[i];
+      if (v < 0 || v >= BFS_NUM_VARIANTS) {
+        set_error("schedule entry %d is not a variant id", i);
+        return BFS_EINVAL;
+      }
+      if (is_pull(v) && !have_csc) {
+        set_error("schedule uses a pull variant but no CSC arrays were given");
+        return BFS_ENOTSUP;
+      }
+    }
+  } else if (mode != BFS_AUTO_HEURISTIC && mode != BFS_AUTO_LEARNED) {
+    set_error("unknown variant/mode %d", mode);
+    return BFS_EINVAL;
+  }
+  bool learned = mode == BFS_AUTO_LEARNED;
+  if (learned && !selector_loaded()) {
+    if (opt->flags & BFS_F_STRICT_SELECTOR) {
+      set_error("learned mode requested but no selector weights are loaded");
+      return BFS_ENOSEL;
+    }
+    learned = false;
+    mode = BFS_AUTO_HEURISTIC;
+    if (st) st->fell_back = 1;
+  }
+  int push_v = (opt->heuristic_push >= 0 && opt->heuristic_push < BFS_NUM_VARIANTS && !is_pull(opt->heuristic_push))
+                   ? opt->heuristic_push : BFS_V_PUSH_Q_BLOCK;
+  int pull_v = BFS_V_PULL_B;
+
+  HostCtx &hc = host_ctx();
+  if (!hc.ok) {
+    set_error("pinned host buffer or event creation failed");
+    return BFS_EHIP;
+  }
+  const size_t need = workspace_bytes_single(g->n);
+  void *wsp = opt->workspace;
+  if (wsp) {
+    if (opt->workspace_bytes < need) {
+      set_error("workspace has %zu bytes, needs %zu", opt->workspace_bytes, need);
+      return BFS_EWORKSPACE;
+    }
+  } else {
+    rc = cached_workspace(need, &wsp);
+    if (rc) return rc;
+  }
+  Workspace w = carve_single(wsp, g->n);
+  if (opt->flags & BFS_F_VALIDATE) {
+    rc = validate_graph(g, w.gsum + 8, s);
+    if (rc) return rc;
+  }
+  const long long maxlev = opt->max_levels > 0 ? opt->max_levels : (long long)g->n + 1;
+  const bool want_levels = st && (opt->flags & BFS_F_LEVEL_STATS) && st->level_capacity > 0;
+
+  BFS_HIP(hipEventRecord(hc.ev[0], s));
+  if (learned) {
+    BFS_HIP(hipMemsetAsync(w.gsum, 0, 16, s));
+    BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
+  }
+  StepArgs a = level_args(g, w, levels, parents, 0, DEFAULT_HUB);
+  // reset: fb[0] holds the source; ctr slot 0 = F_0
+  {
+    StepArgs r = a;
+    r.c_cur = w.ctr;
+    BFS_HIP(launch_reset(r, src, s));
+  }
+  SelDevice seldev;
+  if (learned) {
+    seldev = selector_device(w, push_v, pull_v);
+    BFS_HIP(launch_select(seldev, w.ctr, 0, g->n, g->nnz, w.gsum, s, /*init=*/true));
+  }
+  BFS_HIP(hipMemcpyAsync(hc.pinned, w.ctr, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+  BFS_HIP(hipStreamSynchronize(s));
+  int syncs = 1;
+  long long cnt = hc.pinned[0].count;
+  long long eF = (long long)hc.pinned[0].edges;
+  long long nU = (long long)g->n - 1;
+  long long eU = (long long)g->nnz - (long long)hc.pinned[0].in_edges;
+  long long reached = 1, comp_edges = eF;
+  int cur_decision = hc.pinned[0].decision, cur_fallback = hc.pinned[0].fallback;
+  long long cur_ld = (long long)hc.pinned[0].ld, cur_ld2 = (long long)hc.pinned[0].ld2;
+  HeuristicState hs;
+  int fell_back_any = 0;
+  int k = 0;
+  for (;;) {
+    int v;
+    int fb_flag = 0;
+    if (mode >= 0 && mode < BFS_NUM_VARIANTS) {
+      v = mode;
+    } else if (mode == BFS_SCHEDULE) {
+      v = opt->schedule_host[std::min(k, opt->schedule_len - 1)];
+    } else if (learned) {
+      v = cur_decision;
+      fb_flag = cur_fallback;
+      if (v < 0 || v >= BFS_NUM_VARIANTS || (is_pull(v) && !have_csc)) v = push_v;
+    } else {
+      hs.step(g->n, cnt, eF, eU);
+      v = (hs.dir == 1 && have_csc) ? pull_v : push_v;
+    }
+    fell_back_any |= fb_flag;
+    if (want_levels && k < st->level_capacity) {
+      if (st->level_variant) st->level_variant[k] = v;
+      if (st->level_frontier) st->level_frontier[k] = cnt;
+      if (st->level_frontier_edges) st->level_frontier_edges[k] = eF;
+      if (st->level_unvisited) st->level_unvisited[k] = nU;
+      if (st->level_unvisited_edges) st->level_unvisited_edges[k] = eU;
+      if (st->level_fallback) st->level_fallback[k] = fb_flag;
+      if (st->level_frontier_ld) st->level_frontier_ld[k] = cur_ld;
+      if (st->level_frontier_ld2) st->level_frontier_ld2[k] = cur_ld2;
+    }
+    a = level_args(g, w, levels, parents, k, DEFAULT_HUB);
+    BFS_HIP(launch_step(v, a, (int)cnt, eF, s));
+    if (learned) BFS_HIP(launch_select(seldev, w.ctr, k + 1, g->n, g->nnz, w.gsum, s, false));
+    BFS_HIP(hipMemcpyAsync(hc.pinned, a.c_next, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+    BFS_HIP(hipStreamSynchronize(s));
+    ++syncs;
+    const LevelCtr c = hc.pinned[0];
+    if (c.count == 0) break;
+    cnt = c.count;
+    eF = (long long)c.edges;
+    nU -= cnt;
+    eU -= (long long)c.in_edges;
+    reached += cnt;
+    comp_edges += eF;
+    cur_decision = c.decision;
+    cur_fallback = c.fallback;
+    cur_ld = (long long)c.ld;
+    cur_ld2 = (long long)c.ld2;
+    ++k;
+    if (k >= maxlev) {
+      set_error("level loop reached max_levels = %lld", maxlev);
+      return BFS_ELEVELCAP;
+    }
+  }
+  BFS_HIP(hipEventRecord(hc.ev[1], s));
+  BFS_HIP(hipEventSynchronize(hc.ev[1]));
+  if (st) {
+    float ms = 0.f;
+    BFS_HIP(hipEventElapsedTime(&ms, hc.ev[0], hc.ev[1]));
+    st->num_levels = k + 1;
+    st->reached = reached;
+    st->component_edges = comp_edges;
+    st->elapsed_ms = ms;
+    st->host_syncs = syncs;
+    st->fell_back = st->fell_back | fell_back_any;
+    if (learned) {
+      BFS_HIP(hipMemcpy(hc.pinned_u64, w.gsum, 16, hipMemcpyDeviceToHost));
+      st->graph_ld = (int64_t)hc.pinned_u64[0];
+      st->graph_ld2 = (int64_t)hc.pinned_u64[1];
+    }
+  }
+  return BFS_OK;
+}
+
+// Exact state of level k from finished depths, then `reps` timed steps.
+static int step_time(const bfs_graph *g, const int *depths, int k, int variant, int reps, int *scratch,
+                     const bfs_options *opt, float *ms_out, hipStream_t s) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (!depths || !scratch || !ms_out || reps <= 0 || k < 0 || variant < 0 || variant >= BFS_NUM_VARIANTS) {
+    set_error("invalid bfs_step_time arguments");
+    return BFS_EINVAL;
+  }
+  if (is_pull(variant) && !g->csc_ptr) {
+    set_error("pull variant needs CSC arrays");
+    return BFS_ENOTSUP;
+  }
+  HostCtx &hc = host_ctx();
+  const size_t need = workspace_bytes_single(g->n);
+  void *wsp = opt ? opt->workspace : nullptr;
+  if (wsp) {
+    if (opt->workspace_bytes < need) return BFS_EWORKSPACE;
+  } else {
+    rc = cached_workspace(need, &wsp);
+    if (rc) return rc;
+  }
+  Workspace w = carve_single(wsp, g->n);
+  std::vector<float> t;
+  for (int r = 0; r < reps; ++r) {
+    StepArgs a = level_args(g, w, scratch, nullptr, k, DEFAULT_HUB);
+    BFS_HIP(launch_state_from_depths(a, depths, s));
+    BFS_HIP(hipMemcpyAsync(hc.pinned, a.c_cur, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+    BFS_HIP(hipStreamSynchronize(s));
+    long long cnt = hc.pinned[0].count, eF = (long long)hc.pinned[0].edges;
+    BFS_HIP(hipEventRecord(hc.ev[0], s));
+    BFS_HIP(launch_step(variant, a, (int)cnt, eF, s));
+    BFS_HIP(hipEventRecord(hc.ev[1], s));
+    BFS_HIP(hipEventSynchronize(hc.ev[1]));
+    float ms = 0.f;
+    BFS_HIP(hipEventElapsedTime(&ms, hc.ev[0], hc.ev[1]));
+    t.push_back(ms);
+  }
+  std::sort(t.begin(), t.end());
+  *ms_out = t[t.size() / 2];
+  return BFS_OK;
+}
+
+}  // namespace bfs
+
+// ------------------------------------------------------------------ C ABI
+using namespace bfs;
+
+extern "C" {
+
+const char *bfs_strerror(int code) {
+  switch (code) {
+    case BFS_OK: return "ok";
+    case BFS_EINVAL: return "invalid argument";
+    case BFS_EGRAPH: return "malformed graph";
+    case BFS_EWORKSPACE: return "workspace too small";
+    case BFS_EHIP: return "HIP runtime error";
+    case BFS_ENOSEL: return "no selector weights loaded";
+    case BFS_ELEVELCAP: return "level cap reached";
+    case BFS_ENOTSUP: return "variant not supported for this graph";
+    default: return "unknown error";
+  }
+}
+
+const char *bfs_last_error(void) { return g_err; }
+
+int bfs_version(void) { return 1; }
+
+int bfs_workspace_size(int32_t n, int32_t lanes, size_t *bytes) {
+  if (n <= 0 || !bytes || lanes < 1 || lanes > 64) {
+    set_error("invalid bfs_workspace_size arguments");
+    return BFS_EINVAL;
+  }
+  *bytes = lanes == 1 ? workspace_bytes_single(n) : workspace_bytes_multi(n);
+  return BFS_OK;
+}
+
+int bfs_levels(const bfs_graph *g, int32_t source, int32_t *levels, const bfs_options *opt, bfs_stats *st,
+               void *stream) {
+  if (!levels) {
+    set_error("levels is NULL");
+    return BFS_EINVAL;
+  }
+  return run_single(g, source, levels, nullptr, opt, st, (hipStream_t)stream);
+}
+
+int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *parents, const bfs_options *opt,
+                bfs_stats *st, void *stream) {
+  if (!levels || !parents) {
+    set_error("levels or parents is NULL");
+    return BFS_EINVAL;
+  }
+  return run_single(g, source, levels, parents, opt, st, (hipStream_t)stream);
+}
+
+int bfs_step_time(const bfs_graph *g, const int32_t *depths, int32_t k, int32_t variant, int32_t reps,
+                  int32_t *scratch_levels, const bfs_options *opt, float *ms_out, void *stream) {
+  return step_time(g, depths, k, variant, reps, scratch_levels, opt, ms_out, (hipStream_t)stream);
+}
+
+}  // extern "C"

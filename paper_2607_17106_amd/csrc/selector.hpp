@@ -1,0 +1,60 @@
+// Per-level variant choice: Beamer's direction rule and the learned selector
+// network (12 -> 64 -> 64 -> 4, bf16 weights, fp32 accumulation).
+#pragma once
+#include "common.hpp"
+
+namespace bfs {
+
+typedef unsigned short u16;
+
+// Beamer, Asanovic, Patterson, "Direction-Optimizing Breadth-First Search"
+// (SC 2012): alpha = 14, beta = 24.
+struct HeuristicState {
+  static constexpr long long kAlpha = 14, kBeta = 24;
+  int dir = 0;             // 0 top-down (push), 1 bottom-up (pull)
+  long long prev_nf = -1;
+  void step(long long n, long long nF, long long eF, long long eU);
+};
+
+constexpr int NF = BFS_MLP_NFEAT, NH = 64, NC = BFS_MLP_NCLASS;
+constexpr int OFF_W1 = 0, OFF_B1 = 768, OFF_W2 = 832, OFF_B2 = 4928, OFF_W3 = 4992, OFF_B3 = 5248;
+constexpr int NPARAM = BFS_MLP_NPARAM;
+
+// Raw features of one level (see bfs_eeds.h).  Evaluated in fp64 and rounded
+// to fp32, on the host (trainer) and on the device (selector) alike.
+__host__ __device__ inline void level_features(double n, double nnz, double k, double nF, double eF, double nU,
+                                               double eU, double fld, double fld2, double gld, double gld2,
+                                               float *out) {
+  out[0] = (float)log2(1.0 + nF);
+  out[1] = (float)log2(1.0 + eF);
+  out[2] = (float)log2(1.0 + nU);
+  out[3] = (float)log2(1.0 + eU);
+  out[4] = (float)(nF / n);
+  out[5] = (float)(nnz > 0 ? eF / nnz : 0.0);
+  out[6] = (float)(nU / n);
+  double fm = nF > 0 ? fld / nF : 0.0;
+  out[7] = (float)fm;
+  out[8] = (float)(nF > 0 ? fld2 / nF - fm * fm : 0.0);
+  double gm = gld / n;
+  out[9] = (float)gm;
+  out[10] = (float)(gld2 / n - gm * gm);
+  out[11] = (float)log2(1.0 + k);
+}
+
+// Device-resident selector parameters (set by bfs_selector_set).
+struct SelDevice {
+  const u16 *w;          // bf16 weights in the flat layout (biases slots unused)
+  const float *p;        // fp32 flat parameters (biases read from here)
+  const float *norm;     // mean[12], std[12], min[12], max[12]
+  float min_conf;
+  int cls[NC];
+  u64 *state;            // nU, eU, dir, prev_nf (per workspace)
+  int push_v, pull_v;
+};
+
+bool selector_loaded();
+SelDevice selector_device(const Workspace &w, int push_v, int pull_v);
+hipError_t launch_select(const SelDevice &sd, LevelCtr *ring, int k, int n, int nnz, const u64 *gsum,
+                         hipStream_t s, bool init);
+
+}  // namespace bfs
