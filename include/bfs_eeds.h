@@ -95,6 +95,8 @@ int bfs_version(void);
 #define BFS_F_LEVEL_STATS 4      /* fill the per-level arrays of bfs_stats */
 #define BFS_F_DEVICE_LOOP 8      /* choose variants on the device and read the frontier
                                     size back only every few levels (fewer host syncs) */
+#define BFS_F_LEVEL_TIMING 16    /* time each level's step with HIP events on the stream
+                                    (fills level_ms; implies BFS_F_LEVEL_STATS) */
 
 /* ----------------------------------------------------------------- types */
 typedef struct bfs_graph {
@@ -141,6 +143,9 @@ typedef struct bfs_stats {
   int64_t *level_frontier_ld;  /* sum over F_k of floor(log2(1 + outdeg)) */
   int64_t *level_frontier_ld2; /* sum over F_k of floor(log2(1 + outdeg))^2 */
   int64_t graph_ld, graph_ld2; /* the same two sums over all of V (learned mode) */
+  int64_t *level_scanned;      /* edges examined by the step that expanded F_k */
+  int64_t *level_next;         /* |F_{k+1}| found by that step */
+  float *level_ms;             /* BFS_F_LEVEL_TIMING: device time of that step */
 } bfs_stats;
 
 /* Workspace bytes for a graph of n vertices.  lanes = 1 for bfs_levels /

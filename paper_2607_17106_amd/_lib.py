@@ -42,6 +42,7 @@ F_VALIDATE = 1
 F_STRICT_SELECTOR = 2
 F_LEVEL_STATS = 4
 F_DEVICE_LOOP = 8
+F_LEVEL_TIMING = 16
 
 MLP_NPARAM = 5252
 MLP_NFEAT = 12
@@ -66,7 +67,9 @@ class BfsStats(ctypes.Structure):
                 ("level_frontier", POINTER(c_int64)), ("level_frontier_edges", POINTER(c_int64)),
                 ("level_unvisited", POINTER(c_int64)), ("level_unvisited_edges", POINTER(c_int64)),
                 ("level_fallback", POINTER(c_int32)), ("level_frontier_ld", POINTER(c_int64)),
-                ("level_frontier_ld2", POINTER(c_int64)), ("graph_ld", c_int64), ("graph_ld2", c_int64)]
+                ("level_frontier_ld2", POINTER(c_int64)), ("graph_ld", c_int64), ("graph_ld2", c_int64),
+                ("level_scanned", POINTER(c_int64)), ("level_next", POINTER(c_int64)),
+                ("level_ms", POINTER(c_float))]
 
 
 class BfsGraphBatch(ctypes.Structure):

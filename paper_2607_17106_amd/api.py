@@ -82,6 +82,9 @@ class _StatsBuf:
         self.fallback = np.zeros(cap, np.int32)
         self.fld = np.zeros(cap, np.int64)
         self.fld2 = np.zeros(cap, np.int64)
+        self.scanned = np.zeros(cap, np.int64)
+        self.nxt = np.zeros(cap, np.int64)
+        self.ms = np.zeros(cap, np.float32)
         P32, P64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
         self.s = L.BfsStats()
         self.s.level_capacity = cap
@@ -93,6 +96,9 @@ class _StatsBuf:
         self.s.level_fallback = self.fallback.ctypes.data_as(P32)
         self.s.level_frontier_ld = self.fld.ctypes.data_as(P64)
         self.s.level_frontier_ld2 = self.fld2.ctypes.data_as(P64)
+        self.s.level_scanned = self.scanned.ctypes.data_as(P64)
+        self.s.level_next = self.nxt.ctypes.data_as(P64)
+        self.s.level_ms = self.ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
     def as_dict(self, per_level: bool):
         s = self.s
@@ -104,7 +110,8 @@ class _StatsBuf:
             d.update(variant=self.variant[:k].copy(), frontier=self.frontier[:k].copy(),
                      frontier_edges=self.frontier_edges[:k].copy(), unvisited=self.unvisited[:k].copy(),
                      unvisited_edges=self.unvisited_edges[:k].copy(), fallback=self.fallback[:k].copy(),
-                     frontier_ld=self.fld[:k].copy(), frontier_ld2=self.fld2[:k].copy())
+                     frontier_ld=self.fld[:k].copy(), frontier_ld2=self.fld2[:k].copy(),
+                     scanned=self.scanned[:k].copy(), next=self.nxt[:k].copy(), ms=self.ms[:k].copy())
         return d
 
 
@@ -135,6 +142,8 @@ def _run_single(fn_name, g: DeviceGraph, source, want_parents, variant, flags, s
         levels = torch.empty(g.n, dtype=torch.int32, device=dev)
     if want_parents and parents is None:
         parents = torch.empty(g.n, dtype=torch.int32, device=dev)
+    if flags & L.F_LEVEL_TIMING:
+        level_stats = True
     if level_stats:
         flags |= L.F_LEVEL_STATS
     sb = _StatsBuf(stats_capacity if level_stats else 0)

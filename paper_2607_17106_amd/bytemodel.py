@@ -1,0 +1,58 @@
+"""Algorithmic HBM bytes of one level step, per variant.
+
+These are the bytes the method itself must move, not what the hardware
+fetches: a status lookup in a bitmap counts 1/8 byte, a CSR offset pair 8
+bytes, a column id 4 bytes.  Inputs are the per-level counts the library
+reports (bfs_stats per-level arrays):
+
+  nF   |F_k|              eF   out-edges of F_k
+  nU   |U_{k-1}|, the unvisited set the step searches (before F_{k+1})
+  nN   |F_{k+1}|          scan edges the step examined (pull: early-exit scan)
+  n    vertices
+
+Per variant (p = 4 when parents are written, else 0):
+  push, queue in (thread/block)   4nF + 8nF + 4eF + eF/8 + (8+p)nN + nN/8
+  push, merge path                as above + 8nF (degree scan written and read)
+  push, bitmap in, atomic         n/8 + 8nF + 4eF + eF/8 + (8+p)nN + nN/8
+  push, atomic-free (q or b in)   [4nF | n/8] + 8nF + 4eF + eF/8 + (4+p)nN
+                                  + update pass: n/8 + 4nU + 2n/8 + 4nN
+  pull, bitmap                    n/8 + 8nU + 4scan + scan/8 + 2n/8 + (8+p)nN
+"""
+from __future__ import annotations
+
+from . import _lib as L
+
+
+def step_bytes(variant: int, n: int, nF: int, eF: int, nU: int, nN: int, scan: int, parents: bool = False) -> float:
+    p = 4 if parents else 0
+    bm = n / 8.0
+    if variant in (L.PUSH_Q_THREAD, L.PUSH_Q_BLOCK, L.PUSH_Q_MERGE):
+        b = 12.0 * nF + 4.0 * eF + eF / 8.0 + (8 + p) * nN + nN / 8.0
+        if variant == L.PUSH_Q_MERGE:
+            b += 8.0 * nF
+        return b
+    if variant == L.PUSH_B_ATOMIC:
+        return bm + 8.0 * nF + 4.0 * eF + eF / 8.0 + (8 + p) * nN + nN / 8.0
+    if variant in (L.PUSH_B_NOATOMIC, L.PUSH_Q_NOATOMIC):
+        head = bm if variant == L.PUSH_B_NOATOMIC else 4.0 * nF
+        return head + 8.0 * nF + 4.0 * eF + eF / 8.0 + (4 + p) * nN + bm + 4.0 * nU + 2 * bm + 4.0 * nN
+    if variant == L.PULL_B:
+        return bm + 8.0 * nU + 4.0 * scan + scan / 8.0 + 2 * bm + (8 + p) * nN
+    raise ValueError(variant)
+
+
+def reset_bytes(n: int, parents: bool = False) -> float:
+    return 4.0 * n * (2 if parents else 1) + 4 * n / 8.0
+
+
+def level_bytes(stats: dict, n: int, parents: bool = False):
+    """Per-level algorithmic bytes of a finished search (stats with per-level
+    arrays, as returned by bfs_levels(..., level_stats=True))."""
+    out = []
+    k = int(stats["num_levels"])
+    for i in range(k):
+        nU_before = int(stats["unvisited"][i])  # unvisited after F_i was found = searched by step i
+        out.append(step_bytes(int(stats["variant"][i]), n, int(stats["frontier"][i]),
+                              int(stats["frontier_edges"][i]), nU_before, int(stats["next"][i]),
+                              int(stats["scanned"][i]), parents))
+    return out

@@ -21,9 +21,12 @@ constexpr int MERGE_TILE = 2048;         // merge path: edges per tile
 constexpr int MERGE_STAGE = 2304;        // merge path: frontier entries staged per tile
 constexpr int DEFAULT_HUB = 2048;        // block variant: degree above which a vertex is split grid-wide
 
-// Counters of one frontier F_k, accumulated by the step that produced it.
+// Counters of one frontier F_k.  Producers add into one of NSH shards (chosen
+// by workgroup id), each on its own 64-byte line: same-address device-scope
+// atomics serialise across the XCDs, shards do not.  k_finish reduces the
+// shards into the slot's total and the queue segment offsets.
 struct alignas(64) LevelCtr {
-  u32 count;        // |F_k| (also the queue length)
+  u32 count;        // |F_k|: raw reservations in the shard's queue segment
   u32 nhub;         // block variant: hub list length while F_k is expanded
   u64 edges;        // sum over F_k of out-degree
   u64 in_edges;     // sum over F_k of in-degree
@@ -37,17 +40,35 @@ struct alignas(64) LevelCtr {
 };
 static_assert(sizeof(LevelCtr) == 64, "LevelCtr must stay one 64-byte line");
 
+constexpr int NSH = 256;  // counter shards / queue segments per level
+
+// One ring slot: NSH producer shards + the overflow queue counter, the
+// reduced total, and the queue segment prefix (seg[s] = entries before
+// segment s; seg[NSH] = start of the overflow area; seg[NSH+1] = |F_k|).
+struct RingSlot {
+  LevelCtr sh[NSH + 1];
+  LevelCtr tot;
+  int seg[NSH + 2];
+  int pad[30];
+};
+static_assert(sizeof(RingSlot) % 256 == 0, "RingSlot must keep 256-byte alignment");
+
+// Frontier queue: NSH segments of qcap entries, then an overflow area of n.
+inline int queue_cap(int n) { return (n + NSH - 1) / NSH; }
+inline size_t queue_entries(int n) { return (size_t)queue_cap(n) * NSH + (size_t)n; }
+
 // Single-source workspace, carved from one caller buffer.
 struct Workspace {
-  u64 *vis;            // P: visited bitmap, bits >= n pre-set
+  u64 *vis;            // P: visited bitmap, bits >= n and never-reachable bits pre-set
   u64 *fb[3];          // frontier bitmaps (current, next, dead) rotating by level
-  int *q[2];           // frontier queues (current, next)
+  int *q[2];           // frontier queues (current, next), segmented
   int *scan;           // merge path: per-chunk inclusive degree scan
   int *bsum;           // merge path: chunk totals -> exclusive prefix
   int *hubs;           // block variant: deferred high-degree vertices
-  LevelCtr *ctr;       // RING slots
-  u64 *gsum;           // graph-level sums (ld, ld2) and validation flag
+  RingSlot *ring;      // RING slots
+  u64 *gsum;           // graph-level sums (ld, ld2), selector state, validation flag
   int W;               // bitmap words = ceil(n/64)
+  int qcap;
 };
 
 size_t workspace_bytes_single(int n);
@@ -57,7 +78,7 @@ Workspace carve_single(void *base, int n);
 // Arguments of one level step.  k is the level being expanded: vertices it
 // discovers get depth k+1.
 struct StepArgs {
-  int n, W, k, hub;
+  int n, W, k, hub, qcap;
   const int *rp, *ci;          // CSR
   const int *cp, *cx;          // CSC (may alias CSR)
   int *levels, *parents;       // parents may be null
@@ -66,7 +87,10 @@ struct StepArgs {
   u64 *fb_next, *fb_dead;
   const int *q_cur;
   int *q_next;
-  LevelCtr *c_cur, *c_next, *c_zero;
+  LevelCtr *c_cur;             // totals of F_k (consumers add nhub/ntiles/total_e)
+  const int *seg_cur;          // queue segment prefix of F_k
+  LevelCtr *sh_next;           // shards of F_{k+1} (producers add)
+  LevelCtr *sh_zero;           // shards of F_{k+2} (cleared by the first kernel)
   int *scan, *bsum, *hubs;
 };
 
@@ -117,9 +141,8 @@ __device__ __forceinline__ int block_excl_scan(int x, int *total, int *s_w) {
   return off + incl - x;
 }
 
-// Wave-aggregated append: lanes with pred get consecutive slots from one
-// atomicAdd on *counter; returns the slot or -1.  Works in divergent code
-// (only the lanes active at the call take part).
+// Wave-aggregated append to the counter `*counter` (used for the hub list,
+// which stays short).  Works in divergent code.
 __device__ __forceinline__ int wave_append(bool pred, u32 *counter) {
   u64 m = __ballot(pred);
   if (m == 0) return -1;
@@ -128,6 +151,45 @@ __device__ __forceinline__ int wave_append(bool pred, u32 *counter) {
   if (lane() == leader) base = atomicAdd(counter, (u32)__popcll(m));
   base = __shfl(base, leader);
   return pred ? (int)(base + (u32)__popcll(m & __lanemask_lt())) : -1;
+}
+
+// Appends v (lanes with pred) to the next frontier queue: one reservation per
+// wave in the workgroup's segment; the part that does not fit goes to the
+// overflow area.  Works in divergent code.
+__device__ __forceinline__ void queue_push(bool pred, int v, const StepArgs &a) {
+  const u64 m = __ballot(pred);
+  if (m == 0) return;
+  const int s = blockIdx.x % NSH;
+  const int leader = __ffsll((long long)m) - 1;
+  u32 pos = 0;
+  if (lane() == leader) pos = atomicAdd(&a.sh_next[s].count, (u32)__popcll(m));
+  pos = __shfl(pos, leader);
+  const int my = (int)pos + __popcll(m & __lanemask_lt());
+  const bool over = pred && my >= a.qcap;
+  if (pred && !over) a.q_next[(size_t)s * a.qcap + my] = v;
+  const u64 mo = __ballot(over);
+  if (mo) {
+    const int l2 = __ffsll((long long)mo) - 1;
+    u32 p2 = 0;
+    if (lane() == l2) p2 = atomicAdd(&a.sh_next[NSH].count, (u32)__popcll(mo));
+    p2 = __shfl(p2, l2);
+    if (over) a.q_next[(size_t)NSH * a.qcap + p2 + __popcll(mo & __lanemask_lt())] = v;
+  }
+}
+
+// Queue position of frontier entry i, given the segment prefix staged in LDS.
+__device__ __forceinline__ int queue_slot(const int *seg, int qcap, int i) {
+  int lo = 0, hi = NSH;  // last s in [0, NSH] with seg[s] <= i
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (seg[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo * qcap + (i - seg[lo]);
+}
+
+__device__ __forceinline__ void stage_seg(int *s_seg, const int *seg) {
+  for (int i = threadIdx.x; i < NSH + 2; i += blockDim.x) s_seg[i] = seg[i];
+  __syncthreads();
 }
 
 __device__ __forceinline__ bool test_bit(const u64 *bm, int v) {
@@ -155,8 +217,10 @@ struct NewStats {
     ld += (u64)l;
     ld2 += (u64)(l * l);
   }
-  // Must be called by all lanes of the wave (convergent point).
-  __device__ __forceinline__ void flush(LevelCtr *c) {
+  // Must be called by all lanes of the wave (convergent point).  Adds into
+  // the workgroup's shard.
+  __device__ __forceinline__ void flush(LevelCtr *sh) {
+    LevelCtr *c = sh + (blockIdx.x % NSH);
     u64 e = wave_sum_u64(edges), ie = wave_sum_u64(in_edges), a = wave_sum_u64(ld),
         b = wave_sum_u64(ld2), s = wave_sum_u64(scanned);
     if (lane() == 0) {
@@ -170,19 +234,22 @@ struct NewStats {
 };
 
 // Zeroes the dead frontier bitmap (it receives F_{k+2} at the next level)
-// and the counter slot of level k+2.  Called by the first kernel of a step.
+// and the counter shards of level k+2.  Called by the first kernel of a step.
 __device__ __forceinline__ void clear_dead(const StepArgs &a) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nthr = gridDim.x * blockDim.x;
   for (int i = tid; i < a.W; i += nthr) a.fb_dead[i] = 0ull;
-  if (tid < (int)(sizeof(LevelCtr) / sizeof(u32))) reinterpret_cast<u32 *>(a.c_zero)[tid] = 0u;
+  u32 *z = reinterpret_cast<u32 *>(a.sh_zero);
+  const int nz = (NSH + 1) * (int)(sizeof(LevelCtr) / sizeof(u32));
+  for (int i = tid; i < nz; i += nthr) z[i] = 0u;
 }
 
 // ---------------------------------------------------------------- launch
 // Launchers (defined in the .hip files).  All enqueue on `s`.
-hipError_t launch_reset(const StepArgs &a, int src, hipStream_t s);
+hipError_t launch_reset(const StepArgs &a, int src, RingSlot *ring, hipStream_t s);
 hipError_t launch_step(int variant, const StepArgs &a, int count, long long edges, hipStream_t s);
-hipError_t launch_state_from_depths(const StepArgs &a, const int *depths, hipStream_t s);
+hipError_t launch_finish(RingSlot *slot, int qcap, hipStream_t s);
+hipError_t launch_state_from_depths(const StepArgs &a, const int *depths, RingSlot *ring, hipStream_t s);
 hipError_t launch_graph_ld(int n, const int *rp, u64 *gsum, hipStream_t s);
 hipError_t launch_validate(int n, int nnz, const int *ptr, const int *idx, u64 *flag, hipStream_t s);
 int min_first_grid(int W);

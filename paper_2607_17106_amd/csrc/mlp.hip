@@ -91,11 +91,11 @@ __device__ inline void argmax_conf(float logit, int *cls, float *conf) {
 // Runs after the step that produced F_k: updates the running unvisited
 // totals, advances the direction rule, evaluates the network on F_k's
 // features and stores the choice in ring[k % RING].decision.
-__global__ __launch_bounds__(64) void k_select(SelDevice sd, LevelCtr *ring, int k, int n, int nnz,
+__global__ __launch_bounds__(64) void k_select(SelDevice sd, RingSlot *ring, int k, int n, int nnz,
                                                const u64 *gsum, int init) {
   __shared__ float s_x[NF], h0[NH], h1[NH], h2[NH];
   __shared__ int s_hv;
-  LevelCtr *c = ring + (k % RING);
+  LevelCtr *c = &ring[k % RING].tot;
   long long *st = reinterpret_cast<long long *>(sd.state);
   const long long nF = c->count;
   if (lane() == 0) {
@@ -187,7 +187,7 @@ SelDevice selector_device(const Workspace &w, int push_v, int pull_v) {
   return d;
 }
 
-hipError_t launch_select(const SelDevice &sd, LevelCtr *ring, int k, int n, int nnz, const u64 *gsum,
+hipError_t launch_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, const u64 *gsum,
                          hipStream_t s, bool init) {
   hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, sd, ring, k, n, nnz, gsum, init ? 1 : 0);
   return hipGetLastError();

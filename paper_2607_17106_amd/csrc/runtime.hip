@@ -31,17 +31,19 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static inline int words_of(int n) { return (n + 63) / 64; }
 
+constexpr int GSUM_WORDS = 1280;  // graph sums, selector state, flag, 64 partial lines
+
 size_t workspace_bytes_single(int n) {
   const size_t W = (size_t)words_of(n);
   size_t b = 0;
-  b += align256(W * 8);            // vis
-  b += 3 * align256(W * 8);        // fb[3]
-  b += 2 * align256((size_t)n * 4);  // q[2]
-  b += align256(((size_t)n + 1) * 4);  // scan
-  b += align256(((size_t)n / SCAN_CHUNK + 2) * 4);  // bsum
-  b += align256((size_t)n * 4);    // hubs
-  b += align256(RING * sizeof(LevelCtr));
-  b += align256(64 * 8);           // gsum, selector state
+  b += align256(W * 8);                              // vis
+  b += 3 * align256(W * 8);                          // fb[3]
+  b += 2 * align256(queue_entries(n) * 4);           // q[2]
+  b += align256(((size_t)n + 1) * 4);                // scan
+  b += align256(((size_t)n / SCAN_CHUNK + 2) * 4);   // bsum
+  b += align256((size_t)n * 4);                      // hubs
+  b += align256(RING * sizeof(RingSlot));            // ring
+  b += align256(GSUM_WORDS * 8);                     // gsum
   return b;
 }
 
@@ -52,26 +54,28 @@ Workspace carve_single(void *base, int n) {
   auto take = [&](size_t bytes) { char *r = p; p += align256(bytes); return (void *)r; };
   w.vis = (u64 *)take(W * 8);
   for (int i = 0; i < 3; ++i) w.fb[i] = (u64 *)take(W * 8);
-  for (int i = 0; i < 2; ++i) w.q[i] = (int *)take((size_t)n * 4);
+  for (int i = 0; i < 2; ++i) w.q[i] = (int *)take(queue_entries(n) * 4);
   w.scan = (int *)take(((size_t)n + 1) * 4);
   w.bsum = (int *)take(((size_t)n / SCAN_CHUNK + 2) * 4);
   w.hubs = (int *)take((size_t)n * 4);
-  w.ctr = (LevelCtr *)take(RING * sizeof(LevelCtr));
-  w.gsum = (u64 *)take(64 * 8);
+  w.ring = (RingSlot *)take(RING * sizeof(RingSlot));
+  w.gsum = (u64 *)take(GSUM_WORDS * 8);
   w.W = (int)W;
+  w.qcap = queue_cap(n);
   return w;
 }
 
 // ------------------------------------------------- per-thread host context
 struct HostCtx {
-  LevelCtr *pinned = nullptr;  // RING slots + scratch
+  LevelCtr *pinned = nullptr;  // read-back of one slot total + scratch
   u64 *pinned_u64 = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool ok = false;
   HostCtx() {
     if (hipHostMalloc((void **)&pinned, 64 * sizeof(LevelCtr), hipHostMallocDefault) != hipSuccess) return;
     pinned_u64 = reinterpret_cast<u64 *>(pinned + 32);
-    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) return;
+    for (int i = 0; i < 4; ++i)
+      if (hipEventCreate(&ev[i]) != hipSuccess) return;
     ok = true;
   }
 };
@@ -152,6 +156,7 @@ static StepArgs level_args(const bfs_graph *g, const Workspace &w, int *levels, 
   a.W = w.W;
   a.k = k;
   a.hub = hub;
+  a.qcap = w.qcap;
   a.rp = g->row_ptr;
   a.ci = g->col_idx;
   a.cp = g->csc_ptr;
@@ -164,9 +169,10 @@ static StepArgs level_args(const bfs_graph *g, const Workspace &w, int *levels, 
   a.fb_dead = w.fb[(k + 2) % 3];
   a.q_cur = w.q[k % 2];
   a.q_next = w.q[(k + 1) % 2];
-  a.c_cur = w.ctr + (k % RING);
-  a.c_next = w.ctr + ((k + 1) % RING);
-  a.c_zero = w.ctr + ((k + 2) % RING);
+  a.c_cur = &w.ring[k % RING].tot;
+  a.seg_cur = w.ring[k % RING].seg;
+  a.sh_next = w.ring[(k + 1) % RING].sh;
+  a.sh_zero = w.ring[(k + 2) % RING].sh;
   a.scan = w.scan;
   a.bsum = w.bsum;
   a.hubs = w.hubs;
@@ -251,7 +257,9 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     if (rc) return rc;
   }
   const long long maxlev = opt->max_levels > 0 ? opt->max_levels : (long long)g->n + 1;
-  const bool want_levels = st && (opt->flags & BFS_F_LEVEL_STATS) && st->level_capacity > 0;
+  const bool want_levels =
+      st && (opt->flags & (BFS_F_LEVEL_STATS | BFS_F_LEVEL_TIMING)) && st->level_capacity > 0;
+  const bool timing = want_levels && (opt->flags & BFS_F_LEVEL_TIMING);
 
   BFS_HIP(hipEventRecord(hc.ev[0], s));
   if (learned) {
@@ -259,18 +267,14 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
   }
   StepArgs a = level_args(g, w, levels, parents, 0, DEFAULT_HUB);
-  // reset: fb[0] holds the source; ctr slot 0 = F_0
-  {
-    StepArgs r = a;
-    r.c_cur = w.ctr;
-    BFS_HIP(launch_reset(r, src, s));
-  }
+  // reset: fb[0] holds the source; ring slot 0 = F_0
+  BFS_HIP(launch_reset(a, src, w.ring, s));
   SelDevice seldev;
   if (learned) {
     seldev = selector_device(w, push_v, pull_v);
-    BFS_HIP(launch_select(seldev, w.ctr, 0, g->n, g->nnz, w.gsum, s, /*init=*/true));
+    BFS_HIP(launch_select(seldev, w.ring, 0, g->n, g->nnz, w.gsum, s, /*init=*/true));
   }
-  BFS_HIP(hipMemcpyAsync(hc.pinned, w.ctr, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+  BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[0].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
   BFS_HIP(hipStreamSynchronize(s));
   int syncs = 1;
   long long cnt = hc.pinned[0].count;
@@ -310,12 +314,24 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
       if (st->level_frontier_ld2) st->level_frontier_ld2[k] = cur_ld2;
     }
     a = level_args(g, w, levels, parents, k, DEFAULT_HUB);
+    if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
     BFS_HIP(launch_step(v, a, (int)cnt, eF, s));
-    if (learned) BFS_HIP(launch_select(seldev, w.ctr, k + 1, g->n, g->nnz, w.gsum, s, false));
-    BFS_HIP(hipMemcpyAsync(hc.pinned, a.c_next, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+    if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));
+    BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, s));
+    if (learned) BFS_HIP(launch_select(seldev, w.ring, k + 1, g->n, g->nnz, w.gsum, s, false));
+    BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[(k + 1) % RING].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
     BFS_HIP(hipStreamSynchronize(s));
     ++syncs;
     const LevelCtr c = hc.pinned[0];
+    if (want_levels && k < st->level_capacity) {
+      if (st->level_scanned) st->level_scanned[k] = (int64_t)c.scanned;
+      if (st->level_next) st->level_next[k] = (int64_t)c.count;
+      if (timing && st->level_ms) {
+        float ms = 0.f;
+        BFS_HIP(hipEventElapsedTime(&ms, hc.ev[2], hc.ev[3]));
+        st->level_ms[k] = ms;
+      }
+    }
     if (c.count == 0) break;
     cnt = c.count;
     eF = (long long)c.edges;
@@ -379,7 +395,7 @@ static int step_time(const bfs_graph *g, const int *depths, int k, int variant, 
   std::vector<float> t;
   for (int r = 0; r < reps; ++r) {
     StepArgs a = level_args(g, w, scratch, nullptr, k, DEFAULT_HUB);
-    BFS_HIP(launch_state_from_depths(a, depths, s));
+    BFS_HIP(launch_state_from_depths(a, depths, w.ring, s));
     BFS_HIP(hipMemcpyAsync(hc.pinned, a.c_cur, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
     BFS_HIP(hipStreamSynchronize(s));
     long long cnt = hc.pinned[0].count, eF = (long long)hc.pinned[0].edges;

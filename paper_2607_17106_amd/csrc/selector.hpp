@@ -54,7 +54,7 @@ struct SelDevice {
 
 bool selector_loaded();
 SelDevice selector_device(const Workspace &w, int push_v, int pull_v);
-hipError_t launch_select(const SelDevice &sd, LevelCtr *ring, int k, int n, int nnz, const u64 *gsum,
+hipError_t launch_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, const u64 *gsum,
                          hipStream_t s, bool init);
 
 }  // namespace bfs

@@ -191,3 +191,32 @@ def test_error_codes():
     lv, st = B.bfs_levels(dg, int(s), variant=B.AUTO_LEARNED)
     assert st["fell_back"] == 1
     np.testing.assert_array_equal(lv.cpu().numpy(), oracle.bfs(g.row_ptr, g.col_idx, int(s))[0])
+
+
+def test_pull_scan_length_and_first_parent():
+    """Bottom-up steps examine exactly the sequential early-exit scan length
+    (oracle eScan) and pick the first frontier in-neighbour in CSC order."""
+    for g in (gg.workload("rmat14"), gg.directed_random(3000, 40000, seed=12)):
+        g.with_csc()
+        dg = B.DeviceGraph.from_graph(g)
+        (s,) = gg.pick_sources(g, 1, 21)
+        ref, _, nl = oracle.bfs(g.row_ptr, g.col_idx, int(s))
+        prof = oracle.level_profile(g.row_ptr, g.csc_ptr, g.csc_idx, ref)
+        lv, par, st = _run(dg, g, s, B.PULL_B, level_stats=True)
+        np.testing.assert_array_equal(lv, ref)
+        np.testing.assert_array_equal(st["scanned"], prof["eScan"])
+        for v in np.nonzero(ref > 0)[0][:2000]:
+            ins = g.csc_idx[g.csc_ptr[v]:g.csc_ptr[v + 1]]
+            first = ins[ref[ins] == ref[v] - 1][0]
+            assert par[v] == first
+
+
+def test_push_scanned_equals_frontier_edges():
+    g = gg.workload("rmat14")
+    dg = B.DeviceGraph.from_graph(g)
+    (s,) = gg.pick_sources(g, 1, 1402)
+    for v in (B.PUSH_Q_THREAD, B.PUSH_Q_BLOCK, B.PUSH_Q_MERGE, B.PUSH_B_ATOMIC, B.PUSH_B_NOATOMIC):
+        _, _, st = _run(dg, g, s, v, level_stats=True)
+        np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
+        np.testing.assert_array_equal(st["next"][:-1], st["frontier"][1:])
+        assert st["next"][-1] == 0
