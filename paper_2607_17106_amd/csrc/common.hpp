@@ -94,6 +94,18 @@ struct StepArgs {
   int *scan, *bsum, *hubs;
 };
 
+// ------------------------------------------------- per-thread host context
+struct HostCtx {
+  LevelCtr *pinned = nullptr;  // read-back of one slot total + scratch
+  u64 *pinned_u64 = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ok = false;
+  HostCtx();
+};
+HostCtx &host_ctx();
+// Library-cached device workspace for callers that pass none (one per device).
+int cached_workspace(size_t bytes, void **out);
+
 // ---------------------------------------------------------------- errors
 void set_error(const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);

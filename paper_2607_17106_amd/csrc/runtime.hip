@@ -66,19 +66,13 @@ Workspace carve_single(void *base, int n) {
 }
 
 // ------------------------------------------------- per-thread host context
-struct HostCtx {
-  LevelCtr *pinned = nullptr;  // read-back of one slot total + scratch
-  u64 *pinned_u64 = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool ok = false;
-  HostCtx() {
-    if (hipHostMalloc((void **)&pinned, 64 * sizeof(LevelCtr), hipHostMallocDefault) != hipSuccess) return;
-    pinned_u64 = reinterpret_cast<u64 *>(pinned + 32);
-    for (int i = 0; i < 4; ++i)
-      if (hipEventCreate(&ev[i]) != hipSuccess) return;
-    ok = true;
-  }
-};
+HostCtx::HostCtx() {
+  if (hipHostMalloc((void **)&pinned, 64 * sizeof(LevelCtr), hipHostMallocDefault) != hipSuccess) return;
+  pinned_u64 = reinterpret_cast<u64 *>(pinned + 32);
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) return;
+  ok = true;
+}
 
 HostCtx &host_ctx() {
   static thread_local HostCtx c;
