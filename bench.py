@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the fixed-variant comparison")
     ap.add_argument("--sweep-sources", type=int, default=16)
+    ap.add_argument("--device-loop", action="store_true",
+                    help="persistent whole-search kernel instead of the host-driven level loop")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; runs on more than one GPU are not part of this build "
@@ -110,11 +112,20 @@ def main():
         inv = {v: k for k, v in B.VARIANT_NAMES.items()}
         variant = inv[mode]
 
-    def one_pass(var, srcs, timing=True):
-        flags = B.F_LEVEL_TIMING if timing else 0
+    loop_flag = B.F_DEVICE_LOOP if args.device_loop else 0
+
+    def one_pass(var, srcs, timing=True, events=None):
+        flags = (B.F_LEVEL_TIMING if timing else 0) | loop_flag
         sts = []
+        stream = torch.cuda.current_stream()
         for s in srcs:
+            if events is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
             _, st = B.bfs_levels(dg, int(s), variant=var, flags=flags, workspace=ws, levels=levels)
+            if events is not None:
+                e1.record(stream)
+                events.append((e0, e1))
             sts.append(st)
         return sts
 
@@ -122,9 +133,10 @@ def main():
         one_pass(variant, sources, timing=False)
     torch.cuda.synchronize()
     all_stats = []
+    call_events = []
     t_start = time.perf_counter()
     for step in range(args.steps):
-        all_stats.extend(one_pass(variant, sources))
+        all_stats.extend(one_pass(variant, sources, events=call_events))
         log(f"[bench] step {step + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -132,7 +144,7 @@ def main():
     gteps = teps_edges / elapsed / 1e9
     ms_per_step = elapsed * 1e3 / args.steps
 
-    # roofline of the dominant step kernel over the timed region
+    # roofline of the dominant kernel over the timed region
     per_var_t, per_var_b, per_var_n = {}, {}, {}
     for st in all_stats:
         bts = bytemodel.level_bytes(st, g.n)
@@ -146,17 +158,31 @@ def main():
         log(f"[bench] level {k}: {B.VARIANT_NAMES[int(st0['variant'][k])]:>16} nF={st0['frontier'][k]} "
             f"eF={st0['frontier_edges'][k]} nU={st0['unvisited'][k]} scan={st0['scanned'][k]} "
             f"next={st0['next'][k]} ms={st0['ms'][k]:.4f}")
-    dom = max(per_var_t, key=per_var_t.get)
-    achieved = per_var_b[dom] / (per_var_t[dom] * 1e-3) / 1e9
     dev_ms = sum(st["elapsed_ms"] for st in all_stats) / len(all_stats)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": B.VARIANT_NAMES[dom], "launches": per_var_n[dom],
-            "avg_launch_us": round(per_var_t[dom] * 1e3 / per_var_n[dom], 2),
-            "bytes_per_launch": round(per_var_b[dom] / per_var_n[dom]),
-            "time_share": round(per_var_t[dom] / sum(per_var_t.values()), 3),
-            "per_variant_gbs": {B.VARIANT_NAMES[v]: round(per_var_b[v] / (per_var_t[v] * 1e-3) / 1e9, 1)
-                                for v in per_var_t}}
+    per_variant_gbs = {B.VARIANT_NAMES[v]: round(per_var_b[v] / (per_var_t[v] * 1e-3) / 1e9, 1)
+                       for v in per_var_t if per_var_t[v] > 0}
+    if args.device_loop:
+        # one persistent kernel per search: price the whole search per launch
+        call_ms = [e0.elapsed_time(e1) for e0, e1 in call_events]
+        bytes_per = [sum(bytemodel.level_bytes(st, g.n)) + bytemodel.reset_bytes(g.n) for st in all_stats]
+        avg_ms = sum(call_ms) / len(call_ms)
+        avg_b = sum(bytes_per) / len(bytes_per)
+        achieved = avg_b / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_bfs_persistent (whole search)", "launches": len(call_ms),
+                "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": round(avg_b),
+                "per_level_variant_gbs": per_variant_gbs}
+    else:
+        dom = max(per_var_t, key=per_var_t.get)
+        achieved = per_var_b[dom] / (per_var_t[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": B.VARIANT_NAMES[dom], "launches": per_var_n[dom],
+                "avg_launch_us": round(per_var_t[dom] * 1e3 / per_var_n[dom], 2),
+                "bytes_per_launch": round(per_var_b[dom] / per_var_n[dom]),
+                "time_share": round(per_var_t[dom] / sum(per_var_t.values()), 3),
+                "per_variant_gbs": per_variant_gbs}
 
     extra = {"bfs_device_ms_mean": round(dev_ms, 4),
              "levels_mean": round(float(np.mean([st["num_levels"] for st in all_stats])), 2)}
@@ -198,7 +224,8 @@ def main():
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
            "config": {"workload": f"{args.workload}-{len(sources)}src", "graph": g.name, "n": g.n, "nnz": g.nnz,
-                      "sources": len(sources), "mode": mode, "output": "depths"},
+                      "sources": len(sources), "mode": mode, "output": "depths",
+                      "level_loop": "device" if args.device_loop else "host"},
            "roofline": roof}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, list(sources), args.cpu_seconds)

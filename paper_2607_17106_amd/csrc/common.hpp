@@ -53,6 +53,27 @@ struct RingSlot {
 };
 static_assert(sizeof(RingSlot) % 256 == 0, "RingSlot must keep 256-byte alignment");
 
+// Per-level log written by k_finish (entry k describes F_k) and loop control.
+struct alignas(64) LevelLog {
+  u32 count;       // |F_k|
+  int variant;     // variant that expanded F_k (device-chosen modes)
+  u64 edges, in_edges, ld, ld2;
+  u64 scanned;     // edges examined by the step that produced F_k
+  int fallback;
+  int pad;
+  u64 t;           // persistent kernel: device wall clock when F_k was complete
+};
+static_assert(sizeof(LevelLog) == 64, "LevelLog is one line");
+constexpr int LOGCAP = 16384;
+
+struct alignas(64) LoopCtl {
+  u64 done;        // 1 once a level produced an empty frontier
+  u64 levels;      // number of non-empty levels seen (1 + largest depth)
+  u64 reached;     // sum of |F_k|
+  u64 comp_edges;  // sum of out-edges of F_k
+  u64 pad[4];
+};
+
 // Frontier queue: NSH segments of qcap entries, then an overflow area of n.
 inline int queue_cap(int n) { return (n + NSH - 1) / NSH; }
 inline size_t queue_entries(int n) { return (size_t)queue_cap(n) * NSH + (size_t)n; }
@@ -66,6 +87,10 @@ struct Workspace {
   int *bsum;           // merge path: chunk totals -> exclusive prefix
   int *hubs;           // block variant: deferred high-degree vertices
   RingSlot *ring;      // RING slots
+  LevelLog *log;       // LOGCAP entries
+  LoopCtl *ctl;
+  void *bar;           // grid barrier of the persistent kernel
+  int *sched;          // device copy of a host schedule (LOGCAP entries)
   u64 *gsum;           // graph-level sums (ld, ld2), selector state, validation flag
   int W;               // bitmap words = ceil(n/64)
   int qcap;
@@ -79,6 +104,8 @@ Workspace carve_single(void *base, int n);
 // discovers get depth k+1.
 struct StepArgs {
   int n, W, k, hub, qcap;
+  int gate;                    // -1: always run (host loop); -2: run while F_k is non-empty;
+                               // >= 0: run only if F_k is non-empty and its device decision is `gate`
   const int *rp, *ci;          // CSR
   const int *cp, *cx;          // CSC (may alias CSR)
   int *levels, *parents;       // parents may be null
@@ -99,6 +126,7 @@ struct HostCtx {
   LevelCtr *pinned = nullptr;  // read-back of one slot total + scratch
   u64 *pinned_u64 = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t lev_ev[64] = {};  // per-level timing in the device loop (2 per level)
   bool ok = false;
   HostCtx();
 };
@@ -256,11 +284,20 @@ __device__ __forceinline__ void clear_dead(const StepArgs &a) {
   for (int i = tid; i < nz; i += nthr) z[i] = 0u;
 }
 
+// Device-loop gate: true when this launch should not run level k (another
+// variant was chosen, or the search has finished).  Uniform per kernel.
+__device__ __forceinline__ bool gated_off(const StepArgs &a) {
+  if (a.gate == -1) return false;
+  if (a.c_cur->count == 0u) return true;
+  return a.gate >= 0 && a.c_cur->decision != a.gate;
+}
+
 // ---------------------------------------------------------------- launch
 // Launchers (defined in the .hip files).  All enqueue on `s`.
 hipError_t launch_reset(const StepArgs &a, int src, RingSlot *ring, hipStream_t s);
+// count < 0: sizes unknown on the host (device loop); fixed grids are used.
 hipError_t launch_step(int variant, const StepArgs &a, int count, long long edges, hipStream_t s);
-hipError_t launch_finish(RingSlot *slot, int qcap, hipStream_t s);
+hipError_t launch_finish(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl, hipStream_t s);
 hipError_t launch_state_from_depths(const StepArgs &a, const int *depths, RingSlot *ring, hipStream_t s);
 hipError_t launch_graph_ld(int n, const int *rp, u64 *gsum, hipStream_t s);
 hipError_t launch_validate(int n, int nnz, const int *ptr, const int *idx, u64 *flag, hipStream_t s);

@@ -10,6 +10,7 @@
 
 #include "common.hpp"
 #include "selector.hpp"
+#include "persist.hpp"
 
 namespace bfs {
 
@@ -43,6 +44,10 @@ size_t workspace_bytes_single(int n) {
   b += align256(((size_t)n / SCAN_CHUNK + 2) * 4);   // bsum
   b += align256((size_t)n * 4);                      // hubs
   b += align256(RING * sizeof(RingSlot));            // ring
+  b += align256(LOGCAP * sizeof(LevelLog));          // log
+  b += align256(sizeof(LoopCtl));                    // ctl
+  b += align256(sizeof(GridBar));                    // bar
+  b += align256(LOGCAP * sizeof(int));               // sched
   b += align256(GSUM_WORDS * 8);                     // gsum
   return b;
 }
@@ -59,6 +64,10 @@ Workspace carve_single(void *base, int n) {
   w.bsum = (int *)take(((size_t)n / SCAN_CHUNK + 2) * 4);
   w.hubs = (int *)take((size_t)n * 4);
   w.ring = (RingSlot *)take(RING * sizeof(RingSlot));
+  w.log = (LevelLog *)take(LOGCAP * sizeof(LevelLog));
+  w.ctl = (LoopCtl *)take(sizeof(LoopCtl));
+  w.bar = take(sizeof(GridBar));
+  w.sched = (int *)take(LOGCAP * sizeof(int));
   w.gsum = (u64 *)take(GSUM_WORDS * 8);
   w.W = (int)W;
   w.qcap = queue_cap(n);
@@ -71,6 +80,8 @@ HostCtx::HostCtx() {
   pinned_u64 = reinterpret_cast<u64 *>(pinned + 32);
   for (int i = 0; i < 4; ++i)
     if (hipEventCreate(&ev[i]) != hipSuccess) return;
+  for (int i = 0; i < 64; ++i)
+    if (hipEventCreate(&lev_ev[i]) != hipSuccess) return;
   ok = true;
 }
 
@@ -144,8 +155,27 @@ void HeuristicState::step(long long n, long long nF, long long eF, long long eU)
 
 static bool is_pull(int v) { return v == BFS_V_PULL_B; }
 
+// Device wall-clock rate in kHz (ticks per millisecond).
+static double wall_khz() {
+  static double khz = 0.0;
+  if (khz == 0.0) {
+    int dev = 0, r = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&r, hipDeviceAttributeWallClockRate, dev) == hipSuccess && r > 0)
+      khz = (double)r;
+    else
+      khz = 100000.0;
+  }
+  return khz;
+}
+
+hipError_t launch_log_f0(RingSlot *slot0, LevelLog *log, LoopCtl *ctl, hipStream_t s);
+static hipError_t launch_finish_f0(const Workspace &w, hipStream_t s) {
+  return launch_log_f0(w.ring, w.log, w.ctl, s);
+}
+
 static StepArgs level_args(const bfs_graph *g, const Workspace &w, int *levels, int *parents, int k, int hub) {
   StepArgs a;
+  a.gate = -1;
   a.n = g->n;
   a.W = w.W;
   a.k = k;
@@ -177,7 +207,6 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
                       bfs_stats *st, hipStream_t s) {
   int rc = check_graph(g);
   if (rc) return rc;
-  if (!levels || (parents == nullptr && false)) return BFS_EINVAL;
   if (src < 0 || src >= g->n) {
     set_error("source %d out of range [0, %d)", src, g->n);
     return BFS_EINVAL;
@@ -216,6 +245,7 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     return BFS_EINVAL;
   }
   bool learned = mode == BFS_AUTO_LEARNED;
+  int fell_back_all = 0;
   if (learned && !selector_loaded()) {
     if (opt->flags & BFS_F_STRICT_SELECTOR) {
       set_error("learned mode requested but no selector weights are loaded");
@@ -223,11 +253,12 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     }
     learned = false;
     mode = BFS_AUTO_HEURISTIC;
-    if (st) st->fell_back = 1;
+    fell_back_all = 1;
   }
+  const bool device_decides = (mode == BFS_AUTO_HEURISTIC || mode == BFS_AUTO_LEARNED);
   int push_v = (opt->heuristic_push >= 0 && opt->heuristic_push < BFS_NUM_VARIANTS && !is_pull(opt->heuristic_push))
                    ? opt->heuristic_push : BFS_V_PUSH_Q_BLOCK;
-  int pull_v = BFS_V_PULL_B;
+  int pull_v = have_csc ? BFS_V_PULL_B : push_v;
 
   HostCtx &hc = host_ctx();
   if (!hc.ok) {
@@ -254,111 +285,233 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   const bool want_levels =
       st && (opt->flags & (BFS_F_LEVEL_STATS | BFS_F_LEVEL_TIMING)) && st->level_capacity > 0;
   const bool timing = want_levels && (opt->flags & BFS_F_LEVEL_TIMING);
-
-  BFS_HIP(hipEventRecord(hc.ev[0], s));
-  if (learned) {
-    BFS_HIP(hipMemsetAsync(w.gsum, 0, 16, s));
-    BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
-  }
-  StepArgs a = level_args(g, w, levels, parents, 0, DEFAULT_HUB);
-  // reset: fb[0] holds the source; ring slot 0 = F_0
-  BFS_HIP(launch_reset(a, src, w.ring, s));
-  SelDevice seldev;
-  if (learned) {
-    seldev = selector_device(w, push_v, pull_v);
-    BFS_HIP(launch_select(seldev, w.ring, 0, g->n, g->nnz, w.gsum, s, /*init=*/true));
-  }
-  BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[0].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
-  BFS_HIP(hipStreamSynchronize(s));
-  int syncs = 1;
-  long long cnt = hc.pinned[0].count;
-  long long eF = (long long)hc.pinned[0].edges;
-  long long nU = (long long)g->n - 1;
-  long long eU = (long long)g->nnz - (long long)hc.pinned[0].in_edges;
-  long long reached = 1, comp_edges = eF;
-  int cur_decision = hc.pinned[0].decision, cur_fallback = hc.pinned[0].fallback;
-  long long cur_ld = (long long)hc.pinned[0].ld, cur_ld2 = (long long)hc.pinned[0].ld2;
-  HeuristicState hs;
-  int fell_back_any = 0;
-  int k = 0;
-  for (;;) {
-    int v;
-    int fb_flag = 0;
-    if (mode >= 0 && mode < BFS_NUM_VARIANTS) {
-      v = mode;
-    } else if (mode == BFS_SCHEDULE) {
-      v = opt->schedule_host[std::min(k, opt->schedule_len - 1)];
-    } else if (learned) {
-      v = cur_decision;
-      fb_flag = cur_fallback;
-      if (v < 0 || v >= BFS_NUM_VARIANTS || (is_pull(v) && !have_csc)) v = push_v;
-    } else {
-      hs.step(g->n, cnt, eF, eU);
-      v = (hs.dir == 1 && have_csc) ? pull_v : push_v;
-    }
-    fell_back_any |= fb_flag;
-    if (want_levels && k < st->level_capacity) {
-      if (st->level_variant) st->level_variant[k] = v;
-      if (st->level_frontier) st->level_frontier[k] = cnt;
-      if (st->level_frontier_edges) st->level_frontier_edges[k] = eF;
-      if (st->level_unvisited) st->level_unvisited[k] = nU;
-      if (st->level_unvisited_edges) st->level_unvisited_edges[k] = eU;
-      if (st->level_fallback) st->level_fallback[k] = fb_flag;
-      if (st->level_frontier_ld) st->level_frontier_ld[k] = cur_ld;
-      if (st->level_frontier_ld2) st->level_frontier_ld2[k] = cur_ld2;
-    }
-    a = level_args(g, w, levels, parents, k, DEFAULT_HUB);
-    if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
-    BFS_HIP(launch_step(v, a, (int)cnt, eF, s));
-    if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));
-    BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, s));
-    if (learned) BFS_HIP(launch_select(seldev, w.ring, k + 1, g->n, g->nnz, w.gsum, s, false));
-    BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[(k + 1) % RING].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
-    BFS_HIP(hipStreamSynchronize(s));
-    ++syncs;
-    const LevelCtr c = hc.pinned[0];
-    if (want_levels && k < st->level_capacity) {
-      if (st->level_scanned) st->level_scanned[k] = (int64_t)c.scanned;
-      if (st->level_next) st->level_next[k] = (int64_t)c.count;
-      if (timing && st->level_ms) {
-        float ms = 0.f;
-        BFS_HIP(hipEventElapsedTime(&ms, hc.ev[2], hc.ev[3]));
-        st->level_ms[k] = ms;
+  const bool device_loop = (opt->flags & BFS_F_DEVICE_LOOP) != 0;
+  // variants a device-decided level may pick
+  std::vector<int> cands;
+  if (device_decides) {
+    cands.push_back(push_v);
+    if (pull_v != push_v) cands.push_back(pull_v);
+    if (learned) {
+      SelDevice probe = selector_device(w, push_v, pull_v);
+      for (int c = 0; c < NC; ++c) {
+        int v = probe.cls[c];
+        if (is_pull(v) && !have_csc) continue;
+        if (std::find(cands.begin(), cands.end(), v) == cands.end()) cands.push_back(v);
       }
     }
-    if (c.count == 0) break;
-    cnt = c.count;
-    eF = (long long)c.edges;
-    nU -= cnt;
-    eU -= (long long)c.in_edges;
-    reached += cnt;
-    comp_edges += eF;
-    cur_decision = c.decision;
-    cur_fallback = c.fallback;
-    cur_ld = (long long)c.ld;
-    cur_ld2 = (long long)c.ld2;
-    ++k;
-    if (k >= maxlev) {
-      set_error("level loop reached max_levels = %lld", maxlev);
-      return BFS_ELEVELCAP;
+  }
+  auto fixed_variant = [&](int k) -> int {
+    if (mode >= 0 && mode < BFS_NUM_VARIANTS) return mode;
+    return opt->schedule_host[std::min(k, opt->schedule_len - 1)];
+  };
+
+  BFS_HIP(hipEventRecord(hc.ev[0], s));
+  BFS_HIP(hipMemsetAsync(w.ctl, 0, sizeof(LoopCtl), s));
+  if (learned) BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
+  StepArgs a = level_args(g, w, levels, parents, 0, DEFAULT_HUB);
+  SelDevice seldev = selector_device(w, push_v, pull_v);
+  bool persistent = device_loop;
+  if (persistent) {
+    PersistArgs P;
+    P.base = a;
+    for (int i = 0; i < 3; ++i) P.fb[i] = w.fb[i];
+    for (int i = 0; i < 2; ++i) P.q[i] = w.q[i];
+    P.ring = w.ring;
+    P.log = w.log;
+    P.ctl = w.ctl;
+    P.gsum = w.gsum;
+    P.bar = reinterpret_cast<GridBar *>(w.bar);
+    P.decide = device_decides ? 1 : 0;
+    P.use_net = learned ? 1 : 0;
+    P.maxlev = (int)std::min<long long>(maxlev, (long long)INT32_MAX);
+    P.src = src;
+    P.nnz = g->nnz;
+    P.push_v = push_v;
+    P.sd = seldev;
+    P.sched = w.sched;
+    P.sched_len = 1;
+    if (!device_decides) {
+      std::vector<int> sv;
+      if (mode == BFS_SCHEDULE) {
+        sv.assign(opt->schedule_host, opt->schedule_host + std::min(opt->schedule_len, LOGCAP));
+      } else {
+        sv.push_back(mode);
+      }
+      P.sched_len = (int)sv.size();
+      BFS_HIP(hipMemcpyAsync(w.sched, sv.data(), sv.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    BFS_HIP(hipMemsetAsync(w.bar, 0, sizeof(GridBar), s));
+    hipError_t le = launch_persistent(P, s);
+    if (le != hipSuccess) {
+      (void)hipGetLastError();  // fall back to the launch-ahead loop below
+      persistent = false;
+    }
+  }
+  if (!persistent) {
+    BFS_HIP(launch_reset(a, src, w.ring, s));
+    BFS_HIP(launch_finish_f0(w, s));
+    if (device_decides) BFS_HIP(launch_select(seldev, w.ring, 0, g->n, g->nnz, w.gsum, s, true, learned, w.log));
+  }
+
+  int syncs = 0;
+  int k = 0;
+  std::vector<int> host_variant;  // variants the host chose (fixed / schedule modes)
+  std::vector<float> level_ms;
+  if (!device_loop) {
+    BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[0].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+    BFS_HIP(hipStreamSynchronize(s));
+    ++syncs;
+    long long cnt = hc.pinned[0].count;
+    long long eF = (long long)hc.pinned[0].edges;
+    int dec = hc.pinned[0].decision;
+    for (;;) {
+      int v = device_decides ? dec : fixed_variant(k);
+      if (v < 0 || v >= BFS_NUM_VARIANTS || (is_pull(v) && !have_csc)) v = push_v;
+      host_variant.push_back(v);
+      a = level_args(g, w, levels, parents, k, DEFAULT_HUB);
+      a.gate = -1;
+      if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
+      BFS_HIP(launch_step(v, a, (int)cnt, eF, s));
+      if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));
+      BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, s));
+      if (device_decides)
+        BFS_HIP(launch_select(seldev, w.ring, k + 1, g->n, g->nnz, w.gsum, s, false, learned, w.log));
+      BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[(k + 1) % RING].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+      BFS_HIP(hipStreamSynchronize(s));
+      ++syncs;
+      if (timing) {
+        float ms = 0.f;
+        BFS_HIP(hipEventElapsedTime(&ms, hc.ev[2], hc.ev[3]));
+        level_ms.push_back(ms);
+      }
+      const LevelCtr c = hc.pinned[0];
+      if (c.count == 0) break;
+      cnt = c.count;
+      eF = (long long)c.edges;
+      dec = c.decision;
+      ++k;
+      if (k >= maxlev) {
+        set_error("level loop reached max_levels = %lld", maxlev);
+        return BFS_ELEVELCAP;
+      }
+    }
+  } else if (!persistent) {
+    // Enqueue BATCH levels ahead; every step kernel checks the device-side
+    // decision (gate) and the frontier size, so levels past the end are
+    // no-ops.  The host reads the loop control once per batch.
+    constexpr int BATCH = 16;
+    hipEvent_t *evs = hc.lev_ev;
+    bool done = false;
+    while (!done) {
+      const int k0 = k;
+      for (int i = 0; i < BATCH; ++i, ++k) {
+        a = level_args(g, w, levels, parents, k, DEFAULT_HUB);
+        if (timing) BFS_HIP(hipEventRecord(evs[2 * i], s));
+        if (device_decides) {
+          for (int v : cands) {
+            a.gate = v;
+            BFS_HIP(launch_step(v, a, -1, -1, s));
+          }
+        } else {
+          a.gate = -2;
+          int v = fixed_variant(k);
+          host_variant.push_back(v);
+          BFS_HIP(launch_step(v, a, -1, -1, s));
+        }
+        if (timing) BFS_HIP(hipEventRecord(evs[2 * i + 1], s));
+        BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, s));
+        if (device_decides)
+          BFS_HIP(launch_select(seldev, w.ring, k + 1, g->n, g->nnz, w.gsum, s, false, learned, w.log));
+      }
+      BFS_HIP(hipMemcpyAsync(hc.pinned_u64, w.ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
+      BFS_HIP(hipStreamSynchronize(s));
+      ++syncs;
+      const LoopCtl *c = reinterpret_cast<const LoopCtl *>(hc.pinned_u64);
+      done = c->done != 0;
+      if (timing) {
+        const int last = done ? std::min((int)c->levels, k) : k;
+        for (int i = 0; i < BATCH && k0 + i < last; ++i) {
+          float ms = 0.f;
+          BFS_HIP(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
+          level_ms.push_back(ms);
+        }
+      }
+      if (!done && k >= maxlev) {
+        set_error("level loop reached max_levels = %lld", maxlev);
+        return BFS_ELEVELCAP;
+      }
     }
   }
   BFS_HIP(hipEventRecord(hc.ev[1], s));
+  BFS_HIP(hipMemcpyAsync(hc.pinned_u64, w.ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
   BFS_HIP(hipEventSynchronize(hc.ev[1]));
-  if (st) {
-    float ms = 0.f;
-    BFS_HIP(hipEventElapsedTime(&ms, hc.ev[0], hc.ev[1]));
-    st->num_levels = k + 1;
-    st->reached = reached;
-    st->component_edges = comp_edges;
-    st->elapsed_ms = ms;
-    st->host_syncs = syncs;
-    st->fell_back = st->fell_back | fell_back_any;
-    if (learned) {
-      BFS_HIP(hipMemcpy(hc.pinned_u64, w.gsum, 16, hipMemcpyDeviceToHost));
-      st->graph_ld = (int64_t)hc.pinned_u64[0];
-      st->graph_ld2 = (int64_t)hc.pinned_u64[1];
+  BFS_HIP(hipStreamSynchronize(s));
+  LoopCtl ctl;
+  memcpy(&ctl, hc.pinned_u64, sizeof(ctl));
+  if (persistent) {
+    BFS_HIP(hipMemcpy(hc.pinned_u64 + 16, &reinterpret_cast<GridBar *>(w.bar)->err.v, 4, hipMemcpyDeviceToHost));
+    if (reinterpret_cast<u32 *>(hc.pinned_u64 + 16)[0] != 0u) {
+      set_error("persistent search: a grid barrier timed out");
+      return BFS_EHIP;
     }
+    if (ctl.pad[0] == 2) {
+      set_error("level loop reached max_levels = %lld", maxlev);
+      return BFS_ELEVELCAP;
+    }
+    syncs = 1;
+    if (mode >= 0 && mode < BFS_NUM_VARIANTS) host_variant.assign((size_t)ctl.levels + 1, mode);
+    if (mode == BFS_SCHEDULE)
+      for (int i = 0; i <= (int)ctl.levels; ++i)
+        host_variant.push_back(opt->schedule_host[std::min(i, opt->schedule_len - 1)]);
+  }
+  const int nlev = (int)ctl.levels;
+  if (nlev > maxlev) {
+    set_error("level loop reached max_levels = %lld", maxlev);
+    return BFS_ELEVELCAP;
+  }
+  if (!st) return BFS_OK;
+  float ms = 0.f;
+  BFS_HIP(hipEventElapsedTime(&ms, hc.ev[0], hc.ev[1]));
+  st->num_levels = nlev;
+  st->reached = (int64_t)ctl.reached;
+  st->component_edges = (int64_t)ctl.comp_edges;
+  st->elapsed_ms = ms;
+  st->host_syncs = syncs;
+  st->fell_back = fell_back_all;
+  if (learned) {
+    BFS_HIP(hipMemcpy(hc.pinned_u64, w.gsum, 16, hipMemcpyDeviceToHost));
+    st->graph_ld = (int64_t)hc.pinned_u64[0];
+    st->graph_ld2 = (int64_t)hc.pinned_u64[1];
+  }
+  // per-level statistics from the device log (entry k+1 also carries the
+  // scan length of the step that expanded F_k)
+  const int L = std::min(nlev + 1, LOGCAP);
+  std::vector<LevelLog> lg(L);
+  BFS_HIP(hipMemcpy(lg.data(), w.log, L * sizeof(LevelLog), hipMemcpyDeviceToHost));
+  int any_fb = 0;
+  for (int k2 = 0; k2 < std::min(nlev, L); ++k2) any_fb |= lg[k2].fallback;
+  st->fell_back |= any_fb;
+  if (!want_levels) return BFS_OK;
+  long long nU = g->n, eU = g->nnz;
+  const int cap = std::min(st->level_capacity, L - 1 >= 0 ? L - 1 : 0);
+  for (int k2 = 0; k2 < std::min(nlev, cap); ++k2) {
+    const LevelLog &e = lg[k2];
+    nU -= e.count;
+    eU -= (long long)e.in_edges;
+    const int v = device_decides ? e.variant : host_variant[k2];
+    if (st->level_variant) st->level_variant[k2] = v;
+    if (st->level_frontier) st->level_frontier[k2] = e.count;
+    if (st->level_frontier_edges) st->level_frontier_edges[k2] = (int64_t)e.edges;
+    if (st->level_unvisited) st->level_unvisited[k2] = nU;
+    if (st->level_unvisited_edges) st->level_unvisited_edges[k2] = eU;
+    if (st->level_fallback) st->level_fallback[k2] = e.fallback;
+    if (st->level_frontier_ld) st->level_frontier_ld[k2] = (int64_t)e.ld;
+    if (st->level_frontier_ld2) st->level_frontier_ld2[k2] = (int64_t)e.ld2;
+    if (st->level_scanned) st->level_scanned[k2] = (int64_t)lg[k2 + 1].scanned;
+    if (st->level_next) st->level_next[k2] = lg[k2 + 1].count;
+    float lms = (timing && k2 < (int)level_ms.size()) ? level_ms[k2] : 0.f;
+    if (timing && persistent && k2 + 1 < L) lms = (float)((double)(lg[k2 + 1].t - lg[k2].t) / wall_khz());
+    if (st->level_ms) st->level_ms[k2] = lms;
   }
   return BFS_OK;
 }

@@ -50,11 +50,14 @@ struct SelDevice {
   int cls[NC];
   u64 *state;            // nU, eU, dir, prev_nf (per workspace)
   int push_v, pull_v;
+  bool use_net;          // weights present
 };
 
 bool selector_loaded();
 SelDevice selector_device(const Workspace &w, int push_v, int pull_v);
+// Decides the variant for level k (after F_k's counters are final): the
+// network when use_net and weights are loaded, else the direction rule.
 hipError_t launch_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, const u64 *gsum,
-                         hipStream_t s, bool init);
+                         hipStream_t s, bool init, bool use_net, LevelLog *log);
 
 }  // namespace bfs

@@ -220,3 +220,52 @@ def test_push_scanned_equals_frontier_edges():
         np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
         np.testing.assert_array_equal(st["next"][:-1], st["frontier"][1:])
         assert st["next"][-1] == 0
+
+
+@pytest.mark.parametrize("variant", VARIANTS + [B.AUTO_HEURISTIC])
+def test_device_loop_every_variant(variant):
+    """Levels enqueued ahead with device-side gating give the same depths,
+    statistics and (heuristic) decisions as the host-driven loop."""
+    for g in (gg.workload("rmat14"), gg.lattice(200, seed=6), gg.directed_random(2000, 9000, seed=2)):
+        g.with_csc()
+        dg = B.DeviceGraph.from_graph(g)
+        for s in gg.pick_sources(g, 2, 4):
+            lv, par, st = _run(dg, g, s, variant, flags=B.F_DEVICE_LOOP, level_stats=True)
+            nl = _check(g, s, lv, par, f"device loop {g.name} v={variant}")
+            _, _, st_h = _run(dg, g, s, variant, level_stats=True)
+            assert st["num_levels"] == nl == st_h["num_levels"]
+            for key in ("variant", "frontier", "frontier_edges", "unvisited", "unvisited_edges", "next"):
+                np.testing.assert_array_equal(st[key], st_h[key], err_msg=key)
+            if variant == B.PULL_B:
+                np.testing.assert_array_equal(st["scanned"], st_h["scanned"])
+            assert st["host_syncs"] <= 1 + nl // 16 + 1
+
+
+def test_device_loop_schedule_and_cap():
+    g = gg.workload("rmat14")
+    dg = B.DeviceGraph.from_graph(g)
+    (s,) = gg.pick_sources(g, 1, 1402)
+    ref, _, nl = oracle.bfs(g.row_ptr, g.col_idx, int(s))
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        sched = rng.integers(0, B.NUM_VARIANTS, size=nl + 3)
+        lv, par, st = _run(dg, g, s, B.SCHEDULE, schedule=sched, flags=B.F_DEVICE_LOOP, level_stats=True)
+        np.testing.assert_array_equal(lv, ref)
+        np.testing.assert_array_equal(st["variant"], sched[:nl])
+    path = gg.from_edge_list(50, [(i, i + 1) for i in range(49)], True)
+    dp = B.DeviceGraph.from_graph(path)
+    with pytest.raises(B.BfsError) as e:
+        B.bfs_levels(dp, 0, variant=B.PUSH_Q_BLOCK, max_levels=10, flags=B.F_DEVICE_LOOP)
+    assert e.value.code == -6
+    lv, st = B.bfs_levels(dp, 0, variant=B.AUTO_HEURISTIC, flags=B.F_DEVICE_LOOP)
+    np.testing.assert_array_equal(lv.cpu().numpy(), np.arange(50))
+    assert st["num_levels"] == 50
+
+
+def test_device_loop_timing_fills_level_ms():
+    g = gg.workload("rmat14")
+    dg = B.DeviceGraph.from_graph(g)
+    (s,) = gg.pick_sources(g, 1, 1402)
+    for fl in (0, B.F_DEVICE_LOOP):
+        _, st = B.bfs_levels(dg, int(s), variant=B.AUTO_HEURISTIC, flags=B.F_LEVEL_TIMING | fl)
+        assert (st["ms"] > 0).all() and len(st["ms"]) == st["num_levels"]
