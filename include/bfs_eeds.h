@@ -142,7 +142,7 @@ typedef struct bfs_stats {
   int32_t *level_fallback;   /* learned mode: 1 where the heuristic decided */
   int64_t *level_frontier_ld;  /* sum over F_k of floor(log2(1 + outdeg)) */
   int64_t *level_frontier_ld2; /* sum over F_k of floor(log2(1 + outdeg))^2 */
-  int64_t graph_ld, graph_ld2; /* the same two sums over all of V (learned mode) */
+  int64_t graph_ld, graph_ld2; /* the same two sums over all of V (learned mode or level stats) */
   int64_t *level_scanned;      /* edges examined by the step that expanded F_k */
   int64_t *level_next;         /* |F_{k+1}| found by that step */
   float *level_ms;             /* BFS_F_LEVEL_TIMING: device time of that step */

@@ -307,7 +307,8 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
 
   BFS_HIP(hipEventRecord(hc.ev[0], s));
   BFS_HIP(hipMemsetAsync(w.ctl, 0, sizeof(LoopCtl), s));
-  if (learned) BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
+  const bool graph_sums = learned || want_levels;
+  if (graph_sums) BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
   StepArgs a = level_args(g, w, levels, parents, 0, DEFAULT_HUB);
   SelDevice seldev = selector_device(w, push_v, pull_v);
   bool persistent = device_loop;
@@ -478,7 +479,7 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   st->elapsed_ms = ms;
   st->host_syncs = syncs;
   st->fell_back = fell_back_all;
-  if (learned) {
+  if (graph_sums) {
     BFS_HIP(hipMemcpy(hc.pinned_u64, w.gsum, 16, hipMemcpyDeviceToHost));
     st->graph_ld = (int64_t)hc.pinned_u64[0];
     st->graph_ld2 = (int64_t)hc.pinned_u64[1];

@@ -1,0 +1,71 @@
+"""The trained selector (paper_2607_17106_amd/selector_weights.npz): levels
+stay exact under its choices, its device-side choices equal the reference's,
+and on freshly measured per-level step times of a held-out R-MAT graph it
+costs no more than the direction heuristic (the gain it was trained for)."""
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from oracle import features, heuristic, mlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2607_17106_amd as B  # noqa: E402
+from paper_2607_17106_amd import selector  # noqa: E402
+
+W = selector.DEFAULT_PATH
+
+
+@pytest.fixture(scope="module")
+def weights():
+    if not os.path.exists(W):
+        pytest.skip("no trained selector weights committed")
+    z = np.load(W, allow_pickle=False)
+    assert selector.load(W)
+    yield z
+    B.selector_clear()
+
+
+def test_trained_selector_exact_and_matches_reference(weights):
+    g = gg.rmat(18, seed=4918).with_csc()  # held out (training used 4016..4022 and lattices)
+    dg = B.DeviceGraph.from_graph(g)
+    classes = weights["classes"]
+    for s in gg.pick_sources(g, 6, 4919):
+        ref, _, nl = oracle.bfs(g.row_ptr, g.col_idx, int(s))
+        lv, par, st = B.bfs_parents(dg, int(s), variant=B.AUTO_LEARNED, level_stats=True)
+        np.testing.assert_array_equal(lv.cpu().numpy(), ref)
+        feats = features.level_features(g.row_ptr, g.csc_ptr, ref)
+        xn = ((feats - weights["mean"]) / weights["std"]).astype(np.float32)
+        cls, conf = mlp.predict(weights["params"], xn, acc="fp32")
+        prof = oracle.level_profile(g.row_ptr, g.csc_ptr, g.csc_idx, ref)
+        dirs = heuristic.replay(g.n, prof["nF"], prof["eF"], prof["eU"])
+        oor = ((feats < weights["fmin"]) | (feats > weights["fmax"])).any(axis=1)
+        fb = oor | ~(conf.astype(np.float32) >= weights["min_conf"])
+        exp = np.where(fb, np.where(np.array(dirs) == 1, B.PULL_B, B.PUSH_Q_BLOCK), classes[cls])
+        np.testing.assert_array_equal(st["variant"], exp)
+
+
+def test_trained_selector_gain_over_heuristic(weights):
+    """Per-level step times measured now, from the exact state of every level
+    of 8 searches on a held-out scale-20 R-MAT: the schedule the trained
+    selector picks must cost no more than the direction heuristic's (with 10%
+    slack for timing noise); the measured gain is printed."""
+    g = gg.rmat(20, seed=4920).with_csc()
+    dg = B.DeviceGraph.from_graph(g)
+    classes = [int(c) for c in weights["classes"]]
+    depths = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    cost = {"learned": 0.0, "heuristic": 0.0, "best": 0.0}
+    for s in gg.pick_sources(g, 8, 4921):
+        _, st_l = B.bfs_levels(dg, int(s), variant=B.AUTO_LEARNED, level_stats=True, levels=depths)
+        _, st_h = B.bfs_levels(dg, int(s), variant=B.AUTO_HEURISTIC, level_stats=True)
+        for k in range(st_l["num_levels"]):
+            t = {v: B.step_time(dg, depths, k, v, reps=3) for v in set(classes) | {B.PUSH_Q_BLOCK, B.PULL_B}}
+            cost["learned"] += t[int(st_l["variant"][k])]
+            cost["heuristic"] += t[int(st_h["variant"][k])]
+            cost["best"] += min(t[v] for v in classes)
+    print("summed step ms:", cost)
+    assert cost["learned"] <= 1.10 * cost["heuristic"]
