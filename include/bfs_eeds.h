@@ -180,7 +180,10 @@ int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_
  * Many independent graphs stored back to back (a disjoint union).  Instance b
  * owns global vertices [v_off[b], v_off[b+1]); row_ptr has total_n+1 GLOBAL
  * entry offsets; col_idx holds LOCAL vertex ids of the same instance.  All
- * instances are searched in one persistent launch. */
+ * instances are searched in one persistent launch: each workgroup takes the
+ * next instance (largest first) from a queue and runs that whole search
+ * itself, choosing top-down or bottom-up per level by the direction rule, so
+ * no instance needs synchronisation across workgroups. */
 typedef struct bfs_graph_batch {
   int32_t num;               /* instances, > 0 */
   int32_t total_n;
@@ -189,14 +192,17 @@ typedef struct bfs_graph_batch {
   const int64_t *e_off_host; /* host [num+1] */
   const int32_t *row_ptr;    /* device [total_n+1] */
   const int32_t *col_idx;    /* device [total_nnz] */
+  int32_t symmetric;         /* 1: every instance is symmetric, so bottom-up steps may
+                                use the CSR as in-edges; 0: top-down steps only */
 } bfs_graph_batch;
 
 typedef struct bfs_batch_config {
-  int32_t block_threads;     /* 256, 512 or 1024 */
-  int32_t small_vertices;    /* instances with n <= this run inside one workgroup with
-                                LDS bitmaps; others are cut into vertex chunks */
-  int32_t chunk_vertices;    /* vertex-chunk size of a large-instance task */
-  int32_t blocks_per_cu;     /* resident workgroups per compute unit (1..8) */
+  int32_t block_threads;     /* 256, 512 or 1024 threads per workgroup */
+  int32_t small_vertices;    /* instances with n <= this keep their visited and frontier
+                                bitmaps in LDS; larger ones in private scratch memory */
+  int32_t chunk_vertices;    /* frontier vertices flattened per workgroup pass
+                                (a multiple of block_threads, <= 4 * block_threads) */
+  int32_t blocks_per_cu;     /* resident workgroups per compute unit (1..4) */
 } bfs_batch_config;
 
 /* levels: device [total_n] int32, per instance in local depth terms.

@@ -75,7 +75,7 @@ class BfsStats(ctypes.Structure):
 class BfsGraphBatch(ctypes.Structure):
     _fields_ = [("num", c_int32), ("total_n", c_int32), ("total_nnz", c_int32),
                 ("v_off_host", POINTER(c_int64)), ("e_off_host", POINTER(c_int64)),
-                ("row_ptr", c_void_p), ("col_idx", c_void_p)]
+                ("row_ptr", c_void_p), ("col_idx", c_void_p), ("symmetric", c_int32)]
 
 
 class BfsBatchConfig(ctypes.Structure):

@@ -196,9 +196,9 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
 
 @dataclass
 class BatchConfig:
-    block_threads: int = 256
+    block_threads: int = 512
     small_vertices: int = 65536
-    chunk_vertices: int = 4096
+    chunk_vertices: int = 512
     blocks_per_cu: int = 2
 
     def c(self):
@@ -222,8 +222,10 @@ class DeviceBatch:
         self.col_idx = _dev_i32(b.col_idx, device)
         self.sources = np.ascontiguousarray(b.sources, dtype=np.int32)
         P64 = ctypes.POINTER(ctypes.c_int64)
+        self.symmetric = all(g.symmetric for g in b.graphs)
         self._c = L.BfsGraphBatch(self.num, self.total_n, self.total_nnz, self.v_off.ctypes.data_as(P64),
-                                  self.e_off.ctypes.data_as(P64), self.row_ptr.data_ptr(), self.col_idx.data_ptr())
+                                  self.e_off.ctypes.data_as(P64), self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                                  1 if self.symmetric else 0)
 
     @property
     def c(self):
