@@ -2,19 +2,23 @@
 """BFS throughput on one MI355X: GTEPS and HBM-roofline fraction.
 
 Workload: R-MAT scale 22 (4,194,304 vertices, edge factor 16, a,b,c,d =
-.57,.19,.19,.05, symmetrised, self-loops and duplicates removed), 64 seeded
-sources from the largest component.  One step = one BFS from each of the 64
-sources with the per-level variant choice (learned selector when trained
-weights are present, else the direction heuristic); depths only.  Inputs are
-resident in HBM before the timed region.
+.57,.19,.19,.05, seeded relabel, symmetrised, self-loops and duplicate edges
+removed; 128,307,516 CSR entries) and 64 seeded sources from its largest
+component.  One step = the depths from all 64 sources, computed by the
+64-lane bit-packed multi-source search (bfs_multi) -- the batched form of this
+job.  Inputs are resident in HBM before the timed region.  The same JSON line
+also reports, on the same graph and sources, the single-source forms (learned
+per-level selector, direction heuristic, every fixed variant) and the
+512-instance batched launch against instance-by-instance runs.
 
-  python bench.py [--steps K] [--warmup W] [--mode learned|heuristic|<variant>]
+  python bench.py [--steps K] [--warmup W] [--no-sweep] [--no-batch]
 
-Prints ONE JSON line.  GTEPS counts undirected edges of the traversed
-component: (sum of out-degrees of reached vertices) / 2, summed over sources.
-The roofline block prices the dominant step kernel with the algorithmic byte
-model of paper_2607_17106_amd.bytemodel, timed with HIP events on the stream
-the library launches on, inside the timed region.
+GTEPS counts undirected edges of the traversed component: (sum of
+out-degrees of reached vertices) / 2, summed over sources.  The roofline
+block prices the dominant kernel (the step type with the most time in the
+timed region) with the algorithmic byte model of
+paper_2607_17106_amd.bytemodel; its time comes from HIP events the library
+records on the stream it launches on, inside the timed region.
 """
 from __future__ import annotations
 
@@ -48,7 +52,7 @@ def cpu_model() -> str:
 
 def cpu_baseline(g, sources, seconds: float):
     """The oracle (plain FIFO-queue BFS in C, one thread) on a bounded sample
-    of the same sources: runs whole BFSs until `seconds` have elapsed."""
+    of the same sources: whole searches until `seconds` of BFS time."""
     import oracle  # the CPU oracle is used here only, as the reported baseline
     edges = 0
     dt = 0.0
@@ -62,30 +66,37 @@ def cpu_baseline(g, sources, seconds: float):
         if dt >= seconds:
             break
     return {"value": round(edges / dt / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of {len(sources)} sources, whole BFSs, {dt:.1f} s, {cpu_model()}"}
+            "sample": f"{done} of {len(sources)} single-source searches on the same graph, "
+                      f"{dt:.1f} s of BFS time, {cpu_model()}"}
+
+
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--sources", type=int, default=64)
-    ap.add_argument("--mode", default="auto")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true", help="skip the fixed-variant comparison")
+    ap.add_argument("--no-sweep", action="store_true", help="skip single-source modes and fixed variants")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch")
     ap.add_argument("--sweep-sources", type=int, default=16)
-    ap.add_argument("--device-loop", action="store_true",
-                    help="persistent whole-search kernel instead of the host-driven level loop")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU; runs on more than one GPU are not part of this build "
-              "(see DESIGN.md, 'Sharding')", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md, 'Sharding' describes "
+              "how the search would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import graphgen as gg
     import paper_2607_17106_amd as B
@@ -95,141 +106,135 @@ def main():
     t0 = time.time()
     g = gg.workload(args.workload)
     nsrc, sseed = gg.WORKLOAD_SOURCES.get(args.workload, (args.sources, 1))
-    sources = gg.pick_sources(g, min(args.sources, nsrc) if args.sources else nsrc, sseed)
+    sources = gg.pick_sources(g, min(args.sources, nsrc), sseed)
     log(f"[bench] graph {g.name}: n={g.n} nnz={g.nnz} sources={len(sources)} ({time.time() - t0:.1f} s)")
     dg = B.DeviceGraph.from_graph(g)
-    ws = torch.empty(B.workspace_size(g.n), dtype=torch.uint8, device="cuda")
-    levels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    lv_multi = torch.empty((len(sources), g.n), dtype=torch.int32, device="cuda")
+    ws_multi = torch.empty(B.workspace_size(g.n, 64), dtype=torch.uint8, device="cuda")
 
-    mode = args.mode
-    if mode == "auto":
-        mode = "learned" if selector.load_default() else "heuristic"
-    elif mode == "learned":
-        if not selector.load_default():
-            log("[bench] no trained selector weights found; learned mode falls back to the heuristic")
-    variant = {"learned": B.AUTO_LEARNED, "heuristic": B.AUTO_HEURISTIC}.get(mode)
-    if variant is None:
-        inv = {v: k for k, v in B.VARIANT_NAMES.items()}
-        variant = inv[mode]
-
-    loop_flag = B.F_DEVICE_LOOP if args.device_loop else 0
-
-    def one_pass(var, srcs, timing=True, events=None):
-        flags = (B.F_LEVEL_TIMING if timing else 0) | loop_flag
-        sts = []
-        stream = torch.cuda.current_stream()
-        for s in srcs:
-            if events is not None:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-            _, st = B.bfs_levels(dg, int(s), variant=var, flags=flags, workspace=ws, levels=levels)
-            if events is not None:
-                e1.record(stream)
-                events.append((e0, e1))
-            sts.append(st)
-        return sts
+    # ---------------------------------------------------------- timed step
+    def step(timing):
+        return B.bfs_multi(dg, sources, flags=B.F_LEVEL_TIMING if timing else 0, workspace=ws_multi,
+                           levels=lv_multi)[1]
 
     for _ in range(args.warmup):
-        one_pass(variant, sources, timing=False)
+        step(False)
     torch.cuda.synchronize()
-    all_stats = []
-    call_events = []
+    stats = []
     t_start = time.perf_counter()
-    for step in range(args.steps):
-        all_stats.extend(one_pass(variant, sources, events=call_events))
-        log(f"[bench] step {step + 1}/{args.steps} done")
+    for i in range(args.steps):
+        stats.append(step(True))
+        log(f"[bench] step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    teps_edges = sum(st["component_edges"] for st in all_stats) / 2
-    gteps = teps_edges / elapsed / 1e9
-    ms_per_step = elapsed * 1e3 / args.steps
+    gteps = sum(st["component_edges"] for st in stats) / 2 / elapsed / 1e9
 
-    # roofline of the dominant kernel over the timed region
-    per_var_t, per_var_b, per_var_n = {}, {}, {}
-    for st in all_stats:
-        bts = bytemodel.level_bytes(st, g.n)
+    # roofline of the dominant level kernel (bottom-up or top-down step)
+    per_t, per_b, per_n = {}, {}, {}
+    for st in stats:
+        bts = bytemodel.ms_level_bytes(st, g.n)
         for k in range(st["num_levels"]):
-            v = int(st["variant"][k])
-            per_var_t[v] = per_var_t.get(v, 0.0) + float(st["ms"][k])
-            per_var_b[v] = per_var_b.get(v, 0.0) + bts[k]
-            per_var_n[v] = per_var_n.get(v, 0) + 1
-    st0 = all_stats[0]
+            v = "ms_pull" if int(st["variant"][k]) == B.PULL_B else "ms_push"
+            per_t[v] = per_t.get(v, 0.0) + float(st["ms"][k])
+            per_b[v] = per_b.get(v, 0.0) + bts[k]
+            per_n[v] = per_n.get(v, 0) + 1
+    dom = max(per_t, key=per_t.get)
+    achieved = per_b[dom] / (per_t[dom] * 1e-3) / 1e9
+    kernel_name = {"ms_pull": "k_ms_pull", "ms_push": "k_ms_push + k_ms_push_update"}[dom]
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel_name,
+            "launches": per_n[dom], "avg_launch_us": round(per_t[dom] * 1e3 / per_n[dom], 2),
+            "bytes_per_launch": round(per_b[dom] / per_n[dom]),
+            "time_share_of_level_kernels": round(per_t[dom] / sum(per_t.values()), 3),
+            "per_kernel_gbs": {k: round(per_b[k] / (per_t[k] * 1e-3) / 1e9, 1) for k in per_t}}
+    st0 = stats[0]
     for k in range(st0["num_levels"]):
-        log(f"[bench] level {k}: {B.VARIANT_NAMES[int(st0['variant'][k])]:>16} nF={st0['frontier'][k]} "
-            f"eF={st0['frontier_edges'][k]} nU={st0['unvisited'][k]} scan={st0['scanned'][k]} "
-            f"next={st0['next'][k]} ms={st0['ms'][k]:.4f}")
-    dev_ms = sum(st["elapsed_ms"] for st in all_stats) / len(all_stats)
-    per_variant_gbs = {B.VARIANT_NAMES[v]: round(per_var_b[v] / (per_var_t[v] * 1e-3) / 1e9, 1)
-                       for v in per_var_t if per_var_t[v] > 0}
-    if args.device_loop:
-        # one persistent kernel per search: price the whole search per launch
-        call_ms = [e0.elapsed_time(e1) for e0, e1 in call_events]
-        bytes_per = [sum(bytemodel.level_bytes(st, g.n)) + bytemodel.reset_bytes(g.n) for st in all_stats]
-        avg_ms = sum(call_ms) / len(call_ms)
-        avg_b = sum(bytes_per) / len(bytes_per)
-        achieved = avg_b / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_bfs_persistent (whole search)", "launches": len(call_ms),
-                "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": round(avg_b),
-                "per_level_variant_gbs": per_variant_gbs}
-    else:
-        dom = max(per_var_t, key=per_var_t.get)
-        achieved = per_var_b[dom] / (per_var_t[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": B.VARIANT_NAMES[dom], "launches": per_var_n[dom],
-                "avg_launch_us": round(per_var_t[dom] * 1e3 / per_var_n[dom], 2),
-                "bytes_per_launch": round(per_var_b[dom] / per_var_n[dom]),
-                "time_share": round(per_var_t[dom] / sum(per_var_t.values()), 3),
-                "per_variant_gbs": per_variant_gbs}
-
-    extra = {"bfs_device_ms_mean": round(dev_ms, 4),
-             "levels_mean": round(float(np.mean([st["num_levels"] for st in all_stats])), 2)}
-    if not args.no_sweep:
-        sweep = {}
-        sub = sources[: args.sweep_sources]
-        for v in range(B.NUM_VARIANTS):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            sts = one_pass(v, sub, timing=False)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t1
-            sweep[B.VARIANT_NAMES[v]] = round(sum(s["component_edges"] for s in sts) / 2 / dt / 1e9, 3)
-        for m, var in (("heuristic", B.AUTO_HEURISTIC),):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            sts = one_pass(var, sub, timing=False)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t1
-            sweep[m] = round(sum(s["component_edges"] for s in sts) / 2 / dt / 1e9, 3)
-        extra["fixed_and_heuristic_gteps"] = sweep
-        extra["sweep_sources"] = len(sub)
-        log(f"[bench] sweep {sweep}")
-    try:
-        t1 = time.perf_counter()
-        lvm, stm = B.bfs_multi(dg, sources)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        lvm, stm = B.bfs_multi(dg, sources)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        extra["msbfs_64lane_gteps"] = round(stm["component_edges"] / 2 / dt / 1e9, 3)
-        del lvm
-    except B.BfsError as e:
-        extra["msbfs_64lane_gteps"] = None
-        log(f"[bench] bfs_multi unavailable: {e}")
-
-    out = {"metric": METRIC, "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        log(f"[bench] ms level {k}: {'pull' if int(st0['variant'][k]) == B.PULL_B else 'push'} "
+            f"active={st0['frontier'][k]} ef={st0['frontier_edges'][k]} eu={st0['unvisited_edges'][k]} "
+            f"unvis={st0['unvisited'][k]} scan={st0['scanned'][k]} "
+            f"new={st0['next'][k]} ms={st0['ms'][k]:.4f}")
+    out = {"metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-           "config": {"workload": f"{args.workload}-{len(sources)}src", "graph": g.name, "n": g.n, "nnz": g.nnz,
-                      "sources": len(sources), "mode": mode, "output": "depths",
-                      "level_loop": "device" if args.device_loop else "host"},
+           "config": {"workload": f"{args.workload}-{len(sources)}src", "graph": "R-MAT scale 22, edge factor 16, "
+                      "a,b,c,d=.57,.19,.19,.05, symmetrised", "n": g.n, "nnz": g.nnz, "sources": len(sources),
+                      "method": "64-lane bit-packed multi-source BFS (bfs_multi)", "output": "depths [64][n]"},
            "roofline": roof}
+
+    # ------------------------------------------- single-source comparisons
+    if not args.no_sweep:
+        ws = torch.empty(B.workspace_size(g.n), dtype=torch.uint8, device="cuda")
+        lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+        def run_single(var, srcs, flags=0):
+            edges = 0
+            for s in srcs:
+                _, st = B.bfs_levels(dg, int(s), variant=var, flags=flags, workspace=ws, levels=lv)
+                edges += st["component_edges"] // 2
+            return edges
+
+        single = {}
+        have_learned = selector.load_default()
+        modes = [("heuristic", B.AUTO_HEURISTIC, sources)]
+        if have_learned:
+            modes.insert(0, ("learned", B.AUTO_LEARNED, sources))
+        modes += [(B.VARIANT_NAMES[v], v, sources[: args.sweep_sources]) for v in range(B.NUM_VARIANTS)]
+        for name, var, srcs in modes:
+            run_single(var, srcs[:2])  # warm-up
+            edges, dt = timed(lambda: run_single(var, srcs))
+            single[name] = round(edges / dt / 1e9, 3)
+            log(f"[bench] single-source {name}: {single[name]} GTEPS")
+        fixed = {k: v for k, v in single.items() if k not in ("learned", "heuristic")}
+        best_fixed = max(fixed, key=fixed.get)
+        out["single_source_gteps"] = single
+        out["best_fixed_variant"] = {"name": best_fixed, "gteps": fixed[best_fixed]}
+        out["multi_vs_best_fixed"] = round(gteps / fixed[best_fixed], 2)
+        if have_learned:
+            out["learned_vs_best_fixed"] = round(single["learned"] / fixed[best_fixed], 2)
+            out["learned_vs_heuristic"] = round(single["learned"] / single["heuristic"], 2)
+        B.selector_clear()
+
+    # ------------------------------------------------ 512-instance batch
+    if not args.no_batch:
+        t1 = time.time()
+        bb = gg.mixed_batch(512, seed=5501)
+        log(f"[bench] batch of {bb.num}: n={bb.total_n} nnz={bb.total_nnz} ({time.time() - t1:.0f} s)")
+        db = B.DeviceBatch(bb)
+        lvb = torch.empty(bb.total_n, dtype=torch.int32, device="cuda")
+        cfg, tune_ms = B.bfs_batch_autotune(db, levels=lvb)
+        B.bfs_batch(db, levels=lvb)
+        (lvb, stb), dtb = timed(lambda: B.bfs_batch(db, levels=lvb))
+        batch_gteps = stb["component_edges"] / 2 / dtb / 1e9
+        # instance by instance with a fixed variant and with the heuristic, on every 8th instance
+        sub = list(range(0, bb.num, 8))
+        sub_batch = gg.concat([bb.graphs[i] for i in sub], [int(bb.sources[i]) for i in sub])
+        dsub = B.DeviceBatch(sub_batch)
+        lvs = torch.empty(sub_batch.total_n, dtype=torch.int32, device="cuda")
+        B.bfs_batch(dsub, levels=lvs)
+        (_, sts), dts = timed(lambda: B.bfs_batch(dsub, levels=lvs))
+        dgs = [B.DeviceGraph.from_graph(bb.graphs[i]) for i in sub]
+        one = {}
+        for name, var in (("heuristic", B.AUTO_HEURISTIC), ("push_b_noatomic", B.PUSH_B_NOATOMIC)):
+            def one_by_one():
+                e = 0
+                for d, i in zip(dgs, sub):
+                    _, st = B.bfs_levels(d, int(bb.sources[i]), variant=var)
+                    e += st["component_edges"] // 2
+                return e
+            one_by_one()
+            e, dt = timed(one_by_one)
+            one[name] = round(e / dt / 1e9, 3)
+        out["batch512"] = {"gteps": round(batch_gteps, 3), "ms": round(dtb * 1e3, 2),
+                           "config": {"block_threads": cfg.block_threads, "blocks_per_cu": cfg.blocks_per_cu,
+                                      "small_vertices": cfg.small_vertices, "chunk_vertices": cfg.chunk_vertices},
+                           "autotune_best_ms": round(tune_ms, 2),
+                           "sample_64_instances": {"batched_gteps": round(sts["component_edges"] / 2 / dts / 1e9, 3),
+                                                   "one_by_one_gteps": one}}
+        log(f"[bench] batch512 {out['batch512']}")
+        del db, dsub, dgs
+
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, list(sources), args.cpu_seconds)
-    out.update(extra)
     print(json.dumps(out), flush=True)
 
 

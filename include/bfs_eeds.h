@@ -172,7 +172,19 @@ int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *pa
  * on whole words.  sources_host: host [k]; levels: device [k][n] int32
  * (row i = depths from sources_host[i]).  st->component_edges sums over rows.
  * opt->variant: BFS_V_PUSH_Q_THREAD/BLOCK/MERGE select top-down, BFS_V_PULL_B
- * bottom-up, anything else the per-level heuristic. */
+ * bottom-up, anything else the per-level heuristic.
+ * With BFS_F_LEVEL_STATS (or BFS_F_LEVEL_TIMING) one per-level entry is
+ * written per level of each 64-lane group, in order, and st->num_levels is
+ * the number of entries: level_variant = BFS_V_PULL_B (bottom-up) or
+ * BFS_V_PUSH_Q_THREAD (top-down); level_frontier / level_frontier_edges =
+ * vertices in some lane's frontier and their out-edges; level_unvisited =
+ * vertices missing some lane when the step started (bottom-up steps only,
+ * else 0); level_unvisited_edges = in-edges of vertices missing some lane;
+ * level_scanned = edges examined; level_next = (lane, vertex) pairs found;
+ * level_frontier_ld = vertices with a lane found; level_frontier_ld2 = examined
+ * edges whose source vertex is in the frontier (frontier words gathered);
+ * level_ms = step time.  Depths are written to `levels` once, by an output
+ * pass after each group's last level (and by a flush pass every 255 levels). */
 int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_t *levels,
               const bfs_options *opt, bfs_stats *st, void *stream);
 

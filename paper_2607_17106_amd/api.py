@@ -179,19 +179,23 @@ def bfs_parents(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, fl
 
 
 def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: int = 0, workspace=None,
-              levels=None, stream=None):
+              levels=None, stream=None, level_stats: bool = False, stats_capacity: int = 1 << 14):
     """Depths [k][n] from k sources in 64-lane bit-packed groups."""
     lib = L.load()
     src = np.ascontiguousarray(sources, dtype=np.int32)
     k = int(src.size)
     if levels is None:
         levels = torch.empty((max(k, 1), g.n), dtype=torch.int32, device=g.row_ptr.device)
-    sb = _StatsBuf(0)
+    if flags & L.F_LEVEL_TIMING:
+        level_stats = True
+    if level_stats:
+        flags |= L.F_LEVEL_STATS
+    sb = _StatsBuf(stats_capacity if level_stats else 0)
     opt, keep = _options(variant, flags, None, workspace, 0, None)
     rc = lib.bfs_multi(g.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k, _ptr(levels),
                        ctypes.byref(opt), ctypes.byref(sb.s), _stream(stream))
     L.check(rc, "bfs_multi")
-    return levels[:k], sb.as_dict(False)
+    return levels[:k], sb.as_dict(level_stats)
 
 
 @dataclass

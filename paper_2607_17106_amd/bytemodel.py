@@ -56,3 +56,55 @@ def level_bytes(stats: dict, n: int, parents: bool = False):
                               int(stats["frontier_edges"][i]), nU_before, int(stats["next"][i]),
                               int(stats["scanned"][i]), parents))
     return out
+
+
+MS_PLANES = 8  # depth bit planes per window of the multi-source search
+
+
+def ms_rel(k: int) -> int:
+    """Relative depth stored by level k's discoveries (windows of 255 levels)."""
+    return k % ((1 << MS_PLANES) - 1) + 1
+
+
+def ms_step_bytes(pull: bool, n: int, k: int, nf: int, unvis: int, scan: int, hits: int, found: int) -> float:
+    """One level k of the 64-lane multi-source search (u64 words per vertex).
+
+    Both directions clear the dead frontier buffer (8n) and record each found
+    vertex as a visited-word write plus a read-modify-write of the depth
+    planes the relative depth sets (16 bytes per set bit).
+      bottom-up: 8n visited + 8n next words + n/8 next bitmap + 8 per unvis
+                 (csc_ptr pair) + 4 per scanned in-edge + 1/8 per probe of the
+                 frontier bitmap + 8 per gathered frontier word (hits)
+      top-down : n/8 frontier bitmap + 16 per frontier vertex (word, row_ptr
+                 pair) + 12 per scanned edge (target id, its visited word)
+                 + 8 per found vertex (its next word) + update pass: 8n next
+                 words + n/8 next bitmap + 8 per found (visited read)
+    nf = frontier vertices, unvis = vertices missing some lane (bottom-up),
+    hits = in-edges whose source is in the frontier, found = vertices with a
+    new lane."""
+    disc = found * (8.0 + 16.0 * bin(ms_rel(k)).count("1"))
+    if pull:
+        return 8.0 * n + 8.0 * n + 8.0 * n + n / 8.0 + 8.0 * unvis + 4.125 * scan + 8.0 * hits + disc
+    return 8.0 * n + n / 8.0 + 16.0 * nf + 12.0 * scan + 8.0 * found + 8.0 * n + n / 8.0 + 8.0 * found + disc
+
+
+def ms_level_bytes(stats: dict, n: int):
+    """Per-level bytes of a bfs_multi run with level stats (one group of up to
+    64 lanes: the level index restarts at 0 for each group)."""
+    out = []
+    k = 0
+    for i in range(int(stats["num_levels"])):
+        pull = int(stats["variant"][i]) == L.PULL_B
+        out.append(ms_step_bytes(pull, n, k, int(stats["frontier"][i]), int(stats["unvisited"][i]),
+                                 int(stats["scanned"][i]), int(stats["frontier_ld2"][i]),
+                                 int(stats["frontier_ld"][i])))
+        k = 0 if int(stats["next"][i]) == 0 else k + 1
+    return out
+
+
+def ms_fixed_bytes(n: int, lanes: int, planes: int) -> float:
+    """Per group outside the levels: zeroing visited, two frontier buffers and
+    the frontier bitmap (24n + n/8), zeroing the planes in use (8n each), and
+    the output pass (8n visited + 8n per plane read, 4 bytes per (lane,
+    vertex) written, each row once)."""
+    return 24.0 * n + n / 8.0 + 8.0 * n * planes + 8.0 * n + 8.0 * n * planes + 4.0 * lanes * n

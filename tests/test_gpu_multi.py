@@ -14,17 +14,37 @@ import paper_2607_17106_amd as B  # noqa: E402
 MODES = [B.AUTO_HEURISTIC, B.PUSH_Q_BLOCK, B.PULL_B]
 
 
-def _check(g, srcs, variant):
+def _check(g, srcs, variant, level_stats=False):
     dg = B.DeviceGraph.from_graph(g)
-    lv, st = B.bfs_multi(dg, srcs, variant=variant)
+    lv, st = B.bfs_multi(dg, srcs, variant=variant, level_stats=level_stats)
     lv = lv.cpu().numpy()
     ref = oracle.multi(g.row_ptr, g.col_idx, srcs)
     for i in range(len(srcs)):
         np.testing.assert_array_equal(lv[i], ref[i], err_msg=f"lane {i} source {srcs[i]} mode {variant}")
     assert st["component_edges"] == sum(oracle.edges_in_component(g.row_ptr, ref[i]) for i in range(len(srcs)))
     assert st["reached"] == int((ref >= 0).sum())
-    assert st["num_levels"] == int(ref.max()) + 1
+    if level_stats:
+        _check_level_stats(g, np.asarray(srcs), ref, st)
+    else:
+        assert st["num_levels"] == int(ref.max()) + 1
     return st
+
+
+def _check_level_stats(g, srcs, ref, st):
+    """Per-level entries, group by group, against counts from the oracle's
+    depths: lane pairs and vertices found at each level, frontier sizes."""
+    i = 0
+    for g0 in range(0, len(srcs), 64):
+        r = ref[g0:g0 + 64]
+        depth_max = int(r.max())
+        for k in range(depth_max + 1):
+            found = r == k + 1
+            assert int(st["next"][i]) == int(found.sum()), (g0, k)
+            assert int(st["frontier_ld"][i]) == int(found.any(axis=0).sum()), (g0, k)
+            assert int(st["frontier"][i]) == int((r == k).any(axis=0).sum()), (g0, k)
+            assert 0 <= int(st["frontier_ld2"][i]) <= int(st["scanned"][i])
+            i += 1
+    assert st["num_levels"] == i
 
 
 @pytest.mark.parametrize("variant", MODES)
@@ -51,6 +71,24 @@ def test_directed_and_lattice(variant):
     _check(g, gg.pick_sources(g, 33, 8), variant)
     g = gg.from_edge_list(5, [(1, 2)], True)  # isolated sources
     _check(g, np.array([0, 1, 4]), variant)
+
+
+@pytest.mark.parametrize("variant", MODES)
+def test_long_paths_cross_depth_windows(variant):
+    """Depths above 255 take more than one window of depth planes (flush
+    passes between windows)."""
+    n = 700
+    g = gg.from_edge_list(n, [(i, i + 1) for i in range(n - 1)], True)
+    _check(g, np.array([0, 699, 350, 100, 0, 3]), variant, level_stats=True)
+    g = gg.lattice(200, p_delete=0.0, shortcut_frac=0.0, seed=1)
+    _check(g, np.array([0, 199, 200 * 200 - 1, 20100]), variant)
+
+
+@pytest.mark.parametrize("variant", MODES)
+def test_level_stats(variant):
+    g = gg.rmat(12, seed=77)
+    srcs = gg.pick_sources(g, 50, 6)
+    _check(g, np.concatenate([srcs, srcs[:20]]), variant, level_stats=True)
 
 
 def test_multi_errors():
