@@ -140,7 +140,7 @@ def main():
             per_n[v] = per_n.get(v, 0) + 1
     dom = max(per_t, key=per_t.get)
     achieved = per_b[dom] / (per_t[dom] * 1e-3) / 1e9
-    kernel_name = {"ms_pull": "k_ms_pull", "ms_push": "k_ms_push + k_ms_push_update"}[dom]
+    kernel_name = {"ms_pull": "k_ms_pull_heavy + k_ms_pull_tile", "ms_push": "k_ms_push + k_ms_push_update"}[dom]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel_name,
             "launches": per_n[dom], "avg_launch_us": round(per_t[dom] * 1e3 / per_n[dom], 2),

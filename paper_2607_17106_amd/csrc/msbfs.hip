@@ -33,9 +33,19 @@
 
 namespace bfs {
 
-constexpr int MS_T = 4;
-constexpr long long MS_ALPHA = 4;  // bottom-up when frontier out-edges exceed 1/4 of eu
+constexpr int MS_T = 4;   // in-edges per lane before the wave-cooperative scan (push)
+constexpr int MS_HEAD = 8; // in-edges a light vertex's own thread reads before the merged walk (pull)
+constexpr long long MS_ALPHA = 7;  // bottom-up when frontier out-edges exceed 1/7 of eu (and n/8)
 constexpr int MS_PLANES = 8;       // relative depths 0..255 per window
+constexpr int MS_HEAVY = 1024;     // in-degree above which a vertex's in-edges are split over waves
+constexpr int MS_HCHUNK = 1024;    // in-edges per wave in the heavy pass (<= MS_HEAVY)
+constexpr int MS_EPT = 8;          // in-edges per thread per tile iteration
+constexpr int MS_VPT_SPARSE = 4;   // vertices per thread in the bottom-up tile when few in-edges remain
+constexpr int MS_CAP0 = 32;        // in-edges per pending vertex in the first merged round (dense frontiers)
+constexpr int MS_HB = 1024;        // vertices per workgroup in the heavy-list build
+constexpr int MS_SUM_WORDS = 8192; // frontier summary: 2^18 bits = 32 KB of LDS
+constexpr int MS_SUM_GRID = 1024;  // persistent workgroups of the summary-filtered bottom-up kernels
+static_assert(MS_HCHUNK <= MS_HEAVY, "a heavy list is longer than one chunk");
 
 struct MsCtr {  // one 64-byte line per shard
   u64 newbits;     // (lane, vertex) pairs discovered
@@ -63,15 +73,28 @@ struct MsArgs {
   u64 *vis;
   u64 *planes;          // plane b at planes + b * n
   u64 *flushed;         // lanes whose depths a flush pass has written
+  u64 *accb;            // heavy vertices: lanes found by the heavy pass this level (else 0)
+  const int *hv;        // heavy vertices in increasing order
+  const int *hpre;      // hpre[i]: first chunk of hv[i]; hpre[hcount] = hchunks
+  int hcount, hchunks;
+  const int *ov;        // the same for out-degree (CSR): heavy sources of the top-down step
+  const int *opre;
+  int ocount, ochunks;
   int *levels;          // row l at levels + l * n
   int base, np, nflush; // output passes: window base, planes in use, flushes so far
+  int cap0;             // bottom-up: in-edges per pending vertex in the first merged round
+  const u32 *fsum;      // summary of fbits: bit i set if any vertex in [i << sshift, (i+1) << sshift) is
+  int sshift;           // in the frontier; MS_SUM_WORDS words, staged in LDS by bottom-up kernels
+                        // when the frontier is sparse
   MsCtr *sh;            // NSH shards of this level's counters
 };
 
 struct MsCarve {
-  u64 *fr[3], *vis, *flushed, *planes, *fb[2];
+  u64 *fr[3], *vis, *flushed, *accb, *planes, *fb[2];
+  u32 *fsum;
+  int *hv, *hpre, *ov, *opre, *bcnt, *bchk;
   MsCtr *sh, *tot;
-  int *src;             // [64] sources of the group, [64] their degrees
+  int *src;             // [64] sources of the group, [64] their degrees, [2] heavy totals
   size_t bytes;
 };
 
@@ -85,14 +108,31 @@ static MsCarve ms_carve(uintptr_t p, int n) {
   off += vb;
   c.flushed = reinterpret_cast<u64 *>(p + off);
   off += vb;
+  c.accb = reinterpret_cast<u64 *>(p + off);
+  off += vb;
+  const size_t ib = al(((size_t)n + 1) * 4), nb = al(((size_t)n / MS_HB + 2) * 4);
+  c.hv = reinterpret_cast<int *>(p + off);
+  off += ib;
+  c.hpre = reinterpret_cast<int *>(p + off);
+  off += ib;
+  c.ov = reinterpret_cast<int *>(p + off);
+  off += ib;
+  c.opre = reinterpret_cast<int *>(p + off);
+  off += ib;
+  c.bcnt = reinterpret_cast<int *>(p + off);
+  off += nb;
+  c.bchk = reinterpret_cast<int *>(p + off);
+  off += nb;
   c.planes = reinterpret_cast<u64 *>(p + off);
   off += al((size_t)MS_PLANES * n * 8);
   for (int i = 0; i < 2; ++i, off += bb) c.fb[i] = reinterpret_cast<u64 *>(p + off);
+  c.fsum = reinterpret_cast<u32 *>(p + off);
+  off += al((size_t)MS_SUM_WORDS * 4);
   c.sh = reinterpret_cast<MsCtr *>(p + off);
   c.tot = c.sh + NSH;
   off += (size_t)(NSH + 1) * sizeof(MsCtr);
   c.src = reinterpret_cast<int *>(p + off);
-  off += 512;
+  off += 1024;
   c.bytes = off;
   return c;
 }
@@ -100,6 +140,47 @@ static MsCarve ms_carve(uintptr_t p, int n) {
 size_t workspace_bytes_multi(int n) { return ms_carve(0, n).bytes; }
 
 __device__ __forceinline__ bool in_front(const u64 *fb, int u) { return (fb[u >> 6] >> (u & 63)) & 1ull; }
+
+// Frontier test with the LDS summary first (SUM) or the bitmap alone.
+template <bool SUM>
+__device__ __forceinline__ bool in_front_s(const MsArgs &a, const u32 *s_sum, int u) {
+  if (SUM && !((s_sum[u >> (a.sshift + 5)] >> ((u >> a.sshift) & 31)) & 1u)) return false;
+  return in_front(a.fbits, u);
+}
+
+template <bool SUM>
+__device__ __forceinline__ void ms_stage_summary(const MsArgs &a, u32 *s_sum) {
+  if (SUM) {
+    for (int i = threadIdx.x; i < MS_SUM_WORDS; i += BLOCK) s_sum[i] = a.fsum[i];
+    __syncthreads();
+  }
+}
+
+// Summary of the frontier bitmap (one thread per summary word): bit i of the
+// summary is the OR of bitmap bits [i << sshift, (i+1) << sshift), sshift >= 4.
+__global__ __launch_bounds__(BLOCK) void k_ms_summary(const u64 *fb, int nwords, u32 *sum, int sshift) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= MS_SUM_WORDS) return;
+  u32 out = 0;
+  if (sshift < 6) {  // 64 >> sshift groups per bitmap word
+    const int gpw = 64 >> sshift, wpw = 32 / gpw;  // groups per word, bitmap words per summary word
+    for (int k = 0; k < wpw; ++k) {
+      const long long w = (long long)i * wpw + k;
+      const u64 x = w < nwords ? fb[w] : 0ull;
+      for (int gi = 0; gi < gpw; ++gi)
+        if ((x >> (gi << sshift)) & ((1ull << (1 << sshift)) - 1ull)) out |= 1u << (k * gpw + gi);
+    }
+  } else {  // each group spans 1 << (sshift - 6) bitmap words
+    const int wpg = 1 << (sshift - 6);
+    for (int gi = 0; gi < 32; ++gi) {
+      const long long w0 = ((long long)i * 32 + gi) * wpg;
+      u64 x = 0ull;
+      for (int k = 0; k < wpg && w0 + k < nwords; ++k) x |= fb[w0 + k];
+      if (x) out |= 1u << gi;
+    }
+  }
+  sum[i] = out;
+}
 
 struct MsStats {
   u64 c[MS_NCTR] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -113,6 +194,24 @@ struct MsStats {
   }
 };
 enum { C_NEW, C_COMP, C_ACTIVE, C_ACTOUT, C_DONEIN, C_SCAN, C_UNVIS, C_HITS };
+
+// Workgroup-level flush: one atomic per counter and workgroup.  Every thread
+// of the workgroup must call it.
+__device__ __forceinline__ void ms_flush_block(MsStats &st, MsCtr *sh) {
+  __shared__ u64 s_red[BLOCK / WAVE][MS_NCTR];
+#pragma unroll
+  for (int j = 0; j < MS_NCTR; ++j) {
+    const u64 r = wave_sum_u64(st.c[j]);
+    if (lane() == 0) s_red[threadIdx.x / WAVE][j] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < MS_NCTR) {
+    u64 r = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / WAVE; ++w) r += s_red[w][threadIdx.x];
+    if (r) atomicAdd(reinterpret_cast<u64 *>(sh + (blockIdx.x % NSH)) + threadIdx.x, r);
+  }
+}
 
 __device__ __forceinline__ void ms_clear_dead(const MsArgs &a) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,77 +308,358 @@ __global__ __launch_bounds__(BLOCK) void k_ms_fill(u64 *p, int n) {
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) p[i] = 0ull;
 }
 
+// ------------------------------------------------------------ heavy list
+// Vertices with in-degree (CSC) or out-degree (CSR) > MS_HEAVY, in increasing
+// order, and the prefix of their chunk counts: a count pass per MS_HB vertices, a one-workgroup scan of
+// the per-workgroup totals, and a write pass.  Built once per call.
+__device__ __forceinline__ int ms_heavy_chunks(const int *cp, int v) {
+  const int d = cp[v + 1] - cp[v];
+  return d > MS_HEAVY ? (d + MS_HCHUNK - 1) / MS_HCHUNK : 0;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, int *bcnt, int *bchk) {
+  __shared__ int s_w[BLOCK / WAVE];
+  const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
+  int c = 0, k = 0;
+  for (int v = v0 + threadIdx.x; v < v1; v += BLOCK) {
+    const int h = ms_heavy_chunks(cp, v);
+    c += h ? 1 : 0;
+    k += h;
+  }
+  int tc, tk;
+  block_excl_scan(c, &tc, s_w);
+  block_excl_scan(k, &tk, s_w);
+  if (threadIdx.x == 0) {
+    bcnt[blockIdx.x] = tc;
+    bchk[blockIdx.x] = tk;
+  }
+}
+
+// In place: bcnt/bchk become exclusive offsets; tot = {heavy vertices, chunks}.
+__global__ __launch_bounds__(BLOCK) void k_ms_heavy_scan(int nb, int *bcnt, int *bchk, int *tot) {
+  __shared__ int s_w[BLOCK / WAVE];
+  int rc = 0, rk = 0;
+  for (int base = 0; base < nb; base += BLOCK) {
+    const int i = base + threadIdx.x;
+    const int c = i < nb ? bcnt[i] : 0, k = i < nb ? bchk[i] : 0;
+    int tc, tk;
+    const int oc = block_excl_scan(c, &tc, s_w);
+    const int ok = block_excl_scan(k, &tk, s_w);
+    if (i < nb) {
+      bcnt[i] = rc + oc;
+      bchk[i] = rk + ok;
+    }
+    rc += tc;
+    rk += tk;
+  }
+  if (threadIdx.x == 0) {
+    tot[0] = rc;
+    tot[1] = rk;
+  }
+}
+
+// Also clears accb of every heavy vertex (the only entries the pull uses)
+// when accb is given.
+__global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, const int *bcnt, const int *bchk,
+                                                          int *hv, int *hpre, u64 *accb, const int *tot) {
+  __shared__ int s_w[BLOCK / WAVE];
+  const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
+  int rc = bcnt[blockIdx.x], rk = bchk[blockIdx.x];
+  for (int vb = v0; vb < v1; vb += BLOCK) {  // uniform per workgroup
+    const int v = vb + threadIdx.x;
+    const int h = v < v1 ? ms_heavy_chunks(cp, v) : 0;
+    int tc, tk;
+    const int oc = block_excl_scan(h ? 1 : 0, &tc, s_w);
+    const int ok = block_excl_scan(h, &tk, s_w);
+    if (h) {
+      hv[rc + oc] = v;
+      hpre[rc + oc] = rk + ok;
+      if (accb) accb[v] = 0ull;
+    }
+    rc += tc;
+    rk += tk;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) hpre[tot[0]] = tot[1];
+}
+
 // ------------------------------------------------------------------ pull
-__global__ __launch_bounds__(BLOCK) void k_ms_pull(MsArgs a) {
-  ms_clear_dead(a);
+// Index i of the heavy vertex owning chunk q: the last i with hpre[i] <= q
+// (hpre[hcount] = hchunks > q).  Wave-uniform 64-ary search: each round the
+// 64 lanes test 64 evenly spaced entries of the current interval and a ballot
+// narrows it 64-fold, so 12K heavy vertices take 3 rounds of one load each.
+__device__ __forceinline__ int ms_heavy_of_chunk(const int *hpre, int hcount, int q) {
+  int lo = 0, hi = hcount;  // hpre[lo] <= q < hpre[hi]
+  while (hi - lo > 1) {
+    const int step = (hi - lo + WAVE - 1) / WAVE;
+    const int idx = lo + lane() * step;
+    const bool le = idx < hi && hpre[idx] <= q;
+    const u64 m = __ballot(le);  // lanes 0..k are set (hpre is non-decreasing); lane 0 always
+    const int k = 63 - __clzll((long long)m);
+    lo = lo + k * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
+// Bottom-up, heavy part: one wave per chunk of MS_HCHUNK in-edges of a heavy
+// vertex that still misses lanes.  The wave ORs the frontier words of 64
+// in-edges at a time, MS_HU rounds per iteration with their loads in flight
+// together (bitmap probe first).  Every MS_POST iterations it posts its
+// lanes to accb[v] with a returning atomic OR, which also tells it what the
+// other chunks of v have found; it stops once v's missing lanes are covered.
+constexpr int MS_HU = 4;    // 64-edge rounds per heavy-pass iteration
+constexpr int MS_POST = 1;  // iterations between posts
+
+template <bool SUM>
+__global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
+  extern __shared__ u32 s_sum[];
+  ms_stage_summary<SUM>(a, s_sum);
   MsStats st;
   const int wv = threadIdx.x / WAVE;
-  const int nwords = (a.n + WAVE - 1) / WAVE;
-  for (int w = blockIdx.x * (BLOCK / WAVE) + wv; w < nwords; w += gridDim.x * (BLOCK / WAVE)) {
-    const int v = w * WAVE + lane();
-    u64 vw = 0, need = 0, acc = 0;
-    int b = 0, e = 0;
-    bool pending = false;
-    if (v < a.n) {
-      vw = a.vis[v];
-      need = a.full & ~vw;
-      if (need) {
-        st.c[C_UNVIS] += 1;
-        b = a.cp[v];
-        e = a.cp[v + 1];
-        const int d = e - b;
-        int u[MS_T];
+  for (int q = blockIdx.x * (BLOCK / WAVE) + wv; q < a.hchunks; q += gridDim.x * (BLOCK / WAVE)) {
+    const int i = ms_heavy_of_chunk(a.hpre, a.hcount, q);
+    const int v = a.hv[i];
+    const u64 need = a.full & ~a.vis[v];
+    if (!need) continue;
+    u64 known = a.accb[v];  // other chunks' results so far (possibly stale: only less early exit)
+    if ((known & need) == need) continue;
+    const int sb = a.cp[v] + (q - a.hpre[i]) * MS_HCHUNK, se = min(a.cp[v + 1], sb + MS_HCHUNK);
+    u64 mine = 0ull, posted = 0ull;
+    int round = 0;
+    for (int base = sb; base < se; base += MS_HU * WAVE) {  // MS_HU rounds of 64 in-edges, loads in flight together
+      int u[MS_HU];
 #pragma unroll
-        for (int t = 0; t < MS_T; ++t) u[t] = (t < d) ? a.cx[b + t] : -1;
-        bool hit[MS_T];
-#pragma unroll
-        for (int t = 0; t < MS_T; ++t) hit[t] = u[t] >= 0 && in_front(a.fbits, u[t]);
-#pragma unroll
-        for (int t = 0; t < MS_T; ++t)
-          if (hit[t]) {
-            acc |= a.front[u[t]];
-            st.c[C_HITS] += 1;
-          }
-        st.c[C_SCAN] += (u64)min(d, MS_T);
-        pending = d > MS_T && (acc & need) != need;
-        b += MS_T;
+      for (int r = 0; r < MS_HU; ++r) {
+        const int j = base + r * WAVE + lane();
+        u[r] = j < se ? a.cx[j] : -1;
       }
-    }
-    u64 pm = __ballot(pending);
-    while (pm) {
-      const int l = __ffsll((long long)pm) - 1;
-      pm &= pm - 1;
-      const int vb = __shfl(b, l), ve = __shfl(e, l);
-      const u64 ln = __shfl(need, l);
-      u64 wacc = __shfl(acc, l);
-      for (int base = vb; base < ve; base += WAVE) {
-        const int j = base + lane();
-        u64 f = 0ull;
-        if (j < ve) {
-          const int u = a.cx[j];
-          if (in_front(a.fbits, u)) {
-            f = a.front[u];
-            st.c[C_HITS] += 1;
-          }
+      bool hit[MS_HU];
+#pragma unroll
+      for (int r = 0; r < MS_HU; ++r) hit[r] = u[r] >= 0 && in_front_s<SUM>(a, s_sum, u[r]);
+      u64 f = 0ull;
+#pragma unroll
+      for (int r = 0; r < MS_HU; ++r)
+        if (hit[r]) {
+          f |= a.front[u[r]];
+          st.c[C_HITS] += 1;
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
-        wacc |= f;
-        if (lane() == l) st.c[C_SCAN] += (u64)min(WAVE, ve - base);
-        if ((wacc & ln) == ln) break;
+      for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
+      mine |= f & need;
+      if (lane() == 0) st.c[C_SCAN] += (u64)min(MS_HU * WAVE, se - base);
+      if (((known | mine) & need) == need) break;
+      if (++round % MS_POST == 0 && (mine & ~posted)) {
+        u64 old = 0ull;
+        if (lane() == 0) old = atomicOr(a.accb + v, mine);
+        known |= __shfl(old, 0);
+        posted = mine;
+        if (((known | mine) & need) == need) break;
       }
-      if (lane() == l) acc = wacc;
     }
-    u64 nw = 0ull;
-    if (v < a.n) {
-      nw = acc & need;
-      a.next[v] = nw;
-      if (nw) ms_discover(a, v, vw, nw, st);
-    }
-    const u64 nb = __ballot(nw != 0ull);
-    if (lane() == 0) a.nbits[w] = nb;
+    if (lane() == 0 && (mine & ~posted & ~known)) atomicOr(a.accb + v, mine);
   }
-  st.flush(a.sh);
+  ms_flush_block(st, a.sh);
+}
+
+// Exclusive scans of VPT values per thread at once, in the order
+// (slot j, thread t): slot j of thread t gets the sum of every slot j' < j of
+// all threads plus slot j of threads < t.  *total gets the sum of all.  Two
+// barriers.
+template <int VPT>
+__device__ __forceinline__ void ms_multi_scan(const int (&x)[VPT], int (&off)[VPT], int *total,
+                                              int (*s_w)[BLOCK / WAVE]) {
+  const int w = threadIdx.x / WAVE;
+  int incl[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    incl[j] = wave_incl_scan(x[j]);
+    if (lane() == WAVE - 1) s_w[j][w] = incl[j];
+  }
+  __syncthreads();
+  int run = 0;
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    int before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / WAVE; ++i) {
+      const int tw = s_w[j][i];
+      before += i < w ? tw : 0;
+      all += tw;
+    }
+    off[j] = run + before + incl[j] - x[j];
+    run += all;
+  }
+  *total = run;
+  __syncthreads();
+}
+
+// Bottom-up, tile part: one workgroup per tile of VPT * BLOCK consecutive
+// vertices (slot j of thread t holds vertex tile_base + j * BLOCK + t, so
+// every load and store of a slot is coalesced and a wave's slot is one word of
+// the bitmaps).  A light vertex's own thread first ORs the frontier words of
+// its first MS_HEAD in-edges (bitmap probe first).  The remaining in-edge
+// lists of the vertices that still miss lanes are laid end to end (one scan
+// over all slots) and walked MS_EPT * BLOCK edges per iteration: an edge finds
+// its vertex by binary search over the scanned offsets in LDS and is skipped
+// once that vertex has all its missing lanes; the gathered words are
+// OR-reduced per vertex inside the wave (a segmented scan: a wave's edges
+// belong to non-decreasing vertices) and posted with one LDS atomic per vertex
+// and wave.  Heavy vertices take the heavy pass's result from accb.  Also
+// writes next, the next bitmap and the discoveries, and clears the dead
+// frontier buffer.
+template <int VPT, bool SUM>
+__global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
+  constexpr int TV = VPT * BLOCK;
+  extern __shared__ u32 s_sum[];
+  __shared__ int s_off[TV + 1];
+  __shared__ int s_beg[TV];
+  __shared__ u64 s_need[TV];
+  __shared__ u64 s_acc[TV];
+  __shared__ int s_w[VPT][BLOCK / WAVE];
+  ms_clear_dead(a);
+  ms_stage_summary<SUM>(a, s_sum);
+  MsStats st;
+  const int t = threadIdx.x;
+  const int ntiles = (a.n + TV - 1) / TV;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // uniform per workgroup
+    u64 vw[VPT], need[VPT], acc[VPT];
+    int len[VPT], b[VPT], d[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = tile * TV + j * BLOCK + t;
+      vw[j] = v < a.n ? a.vis[v] : ~0ull;
+      need[j] = a.full & ~vw[j];
+      acc[j] = 0ull;
+      len[j] = 0;
+      b[j] = 0;
+      d[j] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      if (need[j]) {
+        const int v = tile * TV + j * BLOCK + t;
+        st.c[C_UNVIS] += 1;
+        b[j] = a.cp[v];
+        d[j] = a.cp[v + 1] - b[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      if (!need[j]) continue;
+      const int v = tile * TV + j * BLOCK + t;
+      if (d[j] > MS_HEAVY) {
+        acc[j] = a.accb[v];
+        if (acc[j]) a.accb[v] = 0ull;  // ready for the next bottom-up level
+        continue;
+      }
+      int u[MS_HEAD];
+#pragma unroll
+      for (int i = 0; i < MS_HEAD; ++i) u[i] = i < d[j] ? a.cx[b[j] + i] : -1;
+      bool hit[MS_HEAD];
+#pragma unroll
+      for (int i = 0; i < MS_HEAD; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
+#pragma unroll
+      for (int i = 0; i < MS_HEAD; ++i)
+        if (hit[i]) {
+          acc[j] |= a.front[u[i]];
+          st.c[C_HITS] += 1;
+        }
+      st.c[C_SCAN] += (u64)min(d[j], MS_HEAD);
+      if (d[j] > MS_HEAD && (acc[j] & need[j]) != need[j]) {
+        len[j] = d[j] - MS_HEAD;
+        b[j] += MS_HEAD;
+      }
+    }
+    bool pend = false;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) pend |= len[j] > 0;
+    // Rounds: each pending vertex walks at most `cap` more in-edges per round
+    // (cap grows 4x per round), and vertices whose missing lanes are covered
+    // drop out between rounds.  With a sparse frontier few vertices finish
+    // early, and the host passes a cap that takes every list in one round.
+    for (int cap = a.cap0; __syncthreads_or(pend); cap = cap > (1 << 28) ? cap : cap * 4) {  // uniform
+      int take[VPT], off[VPT], total;
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) take[j] = min(len[j], cap);
+      ms_multi_scan(take, off, &total, s_w);
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const int l = j * BLOCK + t;
+        s_off[l] = off[j];
+        s_beg[l] = b[j];
+        s_need[l] = need[j];
+        s_acc[l] = acc[j];
+      }
+      if (t == 0) s_off[TV] = total;
+      __syncthreads();
+      for (int c0 = 0; c0 < total; c0 += MS_EPT * BLOCK) {  // uniform per workgroup
+        int o[MS_EPT], u[MS_EPT];
+#pragma unroll
+        for (int i = 0; i < MS_EPT; ++i) {
+          const int e = c0 + i * BLOCK + t;
+          o[i] = -1;
+          u[i] = -1;
+          if (e < total) {
+            int lo = 0, hi = TV;  // s_off[lo] <= e < s_off[hi]
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if (s_off[mid] <= e) lo = mid; else hi = mid;
+            }
+            o[i] = lo;
+            const u64 nd = s_need[lo];
+            if ((s_acc[lo] & nd) != nd) {
+              u[i] = a.cx[s_beg[lo] + (e - s_off[lo])];
+              st.c[C_SCAN] += 1;
+            }
+          }
+        }
+        bool hit[MS_EPT];
+#pragma unroll
+        for (int i = 0; i < MS_EPT; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
+#pragma unroll
+        for (int i = 0; i < MS_EPT; ++i) {
+          u64 f = hit[i] ? a.front[u[i]] : 0ull;
+          st.c[C_HITS] += hit[i] ? 1 : 0;
+          if (__ballot(f != 0ull)) {
+            const int oi = o[i];
+#pragma unroll
+            for (int dd = 1; dd < WAVE; dd <<= 1) {
+              const u64 y = __shfl_up(f, (unsigned)dd);
+              const int oy = __shfl_up(oi, (unsigned)dd);
+              if (lane() >= dd && oy == oi) f |= y;
+            }
+            const int on = __shfl_down(oi, 1u);
+            const bool tail = lane() == WAVE - 1 || on != oi;
+            if (tail && f) atomicOr(&s_acc[oi], f);
+          }
+        }
+      }
+      __syncthreads();
+      pend = false;
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        acc[j] = s_acc[j * BLOCK + t];
+        b[j] += take[j];
+        len[j] -= take[j];
+        if ((acc[j] & need[j]) == need[j]) len[j] = 0;
+        pend |= len[j] > 0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = tile * TV + j * BLOCK + t;
+      u64 nw = 0ull;
+      if (v < a.n) {
+        nw = acc[j] & need[j];
+        a.next[v] = nw;
+        if (nw) ms_discover(a, v, vw[j], nw, st);
+      }
+      const u64 nb = __ballot(nw != 0ull);
+      const int w0 = tile * TV + j * BLOCK + (t & ~(WAVE - 1));
+      if (lane() == 0 && w0 < a.n) a.nbits[w0 / WAVE] = nb;
+    }
+  }
+  ms_flush_block(st, a.sh);
 }
 
 // ------------------------------------------------------------------ push
@@ -298,6 +678,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
     if (fu) {
       b = a.rp[u];
       e = a.rp[u + 1];
+      if (e - b > MS_HEAVY) e = b;  // heavy source: its chunks go to k_ms_push_heavy
       const int d = e - b;
 #pragma unroll
       for (int t = 0; t < MS_T; ++t)
@@ -324,7 +705,38 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
       if (lane() == l) st.c[C_SCAN] += (u64)(ve - vb);
     }
   }
-  st.flush(a.sh);
+  ms_flush_block(st, a.sh);
+}
+
+// Top-down, heavy part: one wave per chunk of MS_HCHUNK out-edges of a
+// heavy source (out-degree > MS_HEAVY) that is in the frontier, so a hub's
+// list is spread over many waves.
+__global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
+  MsStats st;
+  const int wv = threadIdx.x / WAVE;
+  for (int q = blockIdx.x * (BLOCK / WAVE) + wv; q < a.ochunks; q += gridDim.x * (BLOCK / WAVE)) {
+    const int i = ms_heavy_of_chunk(a.opre, a.ocount, q);
+    const int u = a.ov[i];
+    if (!in_front(a.fbits, u)) continue;
+    const u64 fu = a.front[u];
+    const int sb = a.rp[u] + (q - a.opre[i]) * MS_HCHUNK, se = min(a.rp[u + 1], sb + MS_HCHUNK);
+    for (int base = sb; base < se; base += MS_HU * WAVE) {
+      int v[MS_HU];
+#pragma unroll
+      for (int r = 0; r < MS_HU; ++r) {
+        const int j = base + r * WAVE + lane();
+        v[r] = j < se ? a.ci[j] : -1;
+      }
+      u64 m[MS_HU];
+#pragma unroll
+      for (int r = 0; r < MS_HU; ++r) m[r] = v[r] >= 0 ? fu & ~a.vis[v[r]] : 0ull;
+#pragma unroll
+      for (int r = 0; r < MS_HU; ++r)
+        if (m[r]) atomicOr(a.next + v[r], m[r]);
+    }
+    if (lane() == 0) st.c[C_SCAN] += (u64)(se - sb);
+  }
+  ms_flush_block(st, a.sh);
 }
 
 // Owner-computes update after a push: F_{k+1}[v] = next[v] (already masked).
@@ -338,7 +750,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_update(MsArgs a) {
     const int w = (base + (int)(threadIdx.x & ~(WAVE - 1))) / WAVE;
     if (lane() == 0 && w * WAVE < a.n) a.nbits[w] = nb;
   }
-  st.flush(a.sh);
+  ms_flush_block(st, a.sh);
 }
 
 // Output pass.  flush = 0: the final pass, every lane not yet written (depth
@@ -427,6 +839,25 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   HostCtx &hc = host_ctx();
   const int grid_v = std::min(4096, (n + BLOCK - 1) / BLOCK);
   const int grid_w = std::min(4096, ((n + WAVE - 1) / WAVE + 3) / 4);
+  const int grid_t1 = std::min(65536, (n + BLOCK - 1) / BLOCK);
+  const int grid_t4 = std::min(65536, (n + MS_VPT_SPARSE * BLOCK - 1) / (MS_VPT_SPARSE * BLOCK));
+  // heavy in-degree vertices and their chunk prefix (read back with the first group's sync)
+  const int nbh = (n + MS_HB - 1) / MS_HB;
+  int *htot_dev = src_dev + 192;
+  int *htot_host = reinterpret_cast<int *>(hc.pinned_u64 + 64);
+  hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk);
+  hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev);
+  hipLaunchKernelGGL(k_ms_heavy_write, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.hv, W.hpre,
+                     W.accb, htot_dev);
+  // the same over out-degrees for the top-down step (a symmetric graph passes one array twice)
+  if (g->row_ptr != g->csc_ptr) {
+    hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk);
+    hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev + 2);
+    hipLaunchKernelGGL(k_ms_heavy_write, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk, W.ov, W.opre,
+                       (u64 *)nullptr, htot_dev + 2);
+  }
+  BFS_HIP(hipGetLastError());
+  BFS_HIP(hipMemcpyAsync(htot_host, htot_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
   long long reached = 0, comp = 0;
   int max_levels = 0, syncs = 0;
   const int flags = opt ? opt->flags : 0;
@@ -448,6 +879,12 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.vis = W.vis;
     a.planes = W.planes;
     a.flushed = W.flushed;
+    a.accb = W.accb;
+    a.hv = W.hv;
+    a.hpre = W.hpre;
+    a.fsum = W.fsum;
+    a.sshift = 4;
+    while (((long long)n >> a.sshift) > (long long)MS_SUM_WORDS * 32) ++a.sshift;
     a.levels = levels + (size_t)g0 * n;
     a.sh = sh;
     a.base = 0;
@@ -462,6 +899,19 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     int *deg_host = reinterpret_cast<int *>(hc.pinned_u64);
     BFS_HIP(hipMemcpyAsync(deg_host, src_dev + 64, L * sizeof(int), hipMemcpyDeviceToHost, s));
     BFS_HIP(hipStreamSynchronize(s));
+    a.hcount = htot_host[0];
+    a.hchunks = htot_host[1];
+    if (g->row_ptr != g->csc_ptr) {
+      a.ov = W.ov;
+      a.opre = W.opre;
+      a.ocount = htot_host[2];
+      a.ochunks = htot_host[3];
+    } else {
+      a.ov = W.hv;
+      a.opre = W.hpre;
+      a.ocount = a.hcount;
+      a.ochunks = a.hchunks;
+    }
     long long nf = 0, ef = 0, src_comp = 0;
     {
       std::vector<std::pair<int, int>> sd;
@@ -490,11 +940,12 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       else {
         // Direction rule for bit-packed lanes: a bottom-up step exits early
         // only once every lane a vertex misses is found, so it costs close to
-        // all in-edges of the vertices still missing a lane (eu); top-down
-        // costs the frontier's out-edges (ef).  Bottom-up when
-        // ef > eu / MS_ALPHA; back to top-down under Beamer's beta test.
+        // all in-edges of the vertices still missing a lane (eu) plus a pass
+        // over all n vertices; top-down costs the frontier's out-edges (ef),
+        // one atomic each.  Bottom-up when ef > eu / MS_ALPHA and ef > n / 8;
+        // back to top-down under Beamer's beta test.
         if (msdir == 0) {
-          if (ef * MS_ALPHA > eu) msdir = 1;
+          if (ef * MS_ALPHA > eu && ef * 8 > (long long)n) msdir = 1;
         } else if (nf * HeuristicState::kBeta < (long long)n && prev_nf >= 0 && nf < prev_nf) {
           msdir = 0;
         }
@@ -522,9 +973,41 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(BLOCK), 0, s, sh);
       if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
       if (dir == 1) {
-        hipLaunchKernelGGL(k_ms_pull, dim3(grid_w), dim3(BLOCK), 0, s, a);
+        // early exits pay for extra rounds only when the frontier carries a
+        // large share of the remaining in-edges
+        a.cap0 = ef * 4 > eu ? MS_CAP0 : (1 << 30);
+        // a sparse frontier is tested against its LDS summary first: most
+        // in-neighbours are rejected without touching the bitmap
+        const bool sum = (nf << a.sshift) * 64 < (long long)n;
+        if (sum)
+          hipLaunchKernelGGL(k_ms_summary, dim3(MS_SUM_WORDS / BLOCK), dim3(BLOCK), 0, s, (const u64 *)a.fbits,
+                             (n + 63) / 64, W.fsum, a.sshift);
+        const size_t lds = sum ? MS_SUM_WORDS * sizeof(u32) : 0;
+        if (a.hchunks > 0) {
+          const int gh = std::min(sum ? MS_SUM_GRID : 4096, (a.hchunks + 3) / 4);
+          if (sum)
+            hipLaunchKernelGGL(k_ms_pull_heavy<true>, dim3(gh), dim3(BLOCK), lds, s, a);
+          else
+            hipLaunchKernelGGL(k_ms_pull_heavy<false>, dim3(gh), dim3(BLOCK), 0, s, a);
+        }
+        // one vertex per thread while many in-edges remain to be scanned (more
+        // workgroups in flight); four when few do (fixed costs amortised)
+        if (eu > 2 * (long long)n) {
+          if (sum)
+            hipLaunchKernelGGL((k_ms_pull_tile<1, true>), dim3(std::min(grid_t1, MS_SUM_GRID)), dim3(BLOCK), lds, s, a);
+          else
+            hipLaunchKernelGGL((k_ms_pull_tile<1, false>), dim3(grid_t1), dim3(BLOCK), 0, s, a);
+        } else {
+          if (sum)
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, true>), dim3(std::min(grid_t4, MS_SUM_GRID)), dim3(BLOCK),
+                               lds, s, a);
+          else
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false>), dim3(grid_t4), dim3(BLOCK), 0, s, a);
+        }
       } else {
         hipLaunchKernelGGL(k_ms_push, dim3(grid_w), dim3(BLOCK), 0, s, a);
+        if (a.ochunks > 0)
+          hipLaunchKernelGGL(k_ms_push_heavy, dim3(std::min(4096, (a.ochunks + 3) / 4)), dim3(BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
       }
       if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));

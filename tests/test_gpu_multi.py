@@ -85,10 +85,40 @@ def test_long_paths_cross_depth_windows(variant):
 
 
 @pytest.mark.parametrize("variant", MODES)
+def test_directed_hubs(variant):
+    """Directed graph whose heavy in-degree and heavy out-degree vertices
+    differ (separate chunk lists for the two directions)."""
+    rng = np.random.default_rng(11)
+    n = 9000
+    e = [rng.integers(0, n, 30000), rng.integers(0, n, 30000)]
+    src = np.concatenate([e[0], np.full(3000, 7), rng.integers(0, n, 2600)])
+    dst = np.concatenate([e[1], rng.integers(0, n, 3000), np.full(2600, 4242)])
+    g = gg.from_edge_list(n, np.stack([src, dst], 1), False)
+    deg_out = np.diff(g.row_ptr)
+    deg_in = np.diff(g.csc_ptr)
+    assert deg_out[7] > 1024 and deg_in[4242] > 1024 and deg_in[7] < 1024 and deg_out[4242] < 1024
+    _check(g, np.array([7, 4242, 1, 2, 3, 100, 7]), variant, level_stats=True)
+
+
+@pytest.mark.parametrize("variant", MODES)
 def test_level_stats(variant):
     g = gg.rmat(12, seed=77)
     srcs = gg.pick_sources(g, 50, 6)
     _check(g, np.concatenate([srcs, srcs[:20]]), variant, level_stats=True)
+
+
+@pytest.mark.parametrize("variant", [B.AUTO_HEURISTIC, B.PULL_B])
+def test_large_sparse_graph(variant):
+    """n above 2^23: the frontier summary groups span more than one bitmap
+    word; most vertices isolated (depth -1 in every row)."""
+    rng = np.random.default_rng(12)
+    n = 9_000_000
+    a = rng.integers(0, 2_000_000, 400_000)
+    b = rng.integers(0, 2_000_000, 400_000)
+    c = rng.integers(0, n, 100_000)
+    d = rng.integers(0, n, 100_000)
+    g = gg.from_edge_list(n, np.stack([np.concatenate([a, c]), np.concatenate([b, d])], 1), True)
+    _check(g, gg.pick_sources(g, 8, 13), variant, level_stats=True)
 
 
 def test_multi_errors():
