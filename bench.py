@@ -33,6 +33,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of k_ms_pull_tile on this workload: two rocprofv3 --pmc runs of
+# `bench.py --steps 3 --warmup 1 --no-sweep --no-batch --no-cpu` (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch averaged over the kernel's 16 dispatches),
+# each scaled by what the same counter reads for a plain copy of 1 GiB
+# (`bench.py --copy-calibration 1073741824`: FETCH_SIZE 524300 KiB -> x2.0,
+# WRITE_SIZE 1048576 KiB -> x1.0).  Reported only while the kernel sources
+# hash to the values the counters were taken with.
+TILE_TRAFFIC = {
+    "sources_sha256": {
+        "paper_2607_17106_amd/csrc/msbfs.hip": "858be9f83a2357ab573fa9fe58f8dc9fa74d2b6673d096bf7842c406115b2a92",
+        "paper_2607_17106_amd/csrc/common.hpp": "f8b19fcbc9a66cd71f0b882946620fd743f1827bfb536f5541b271e84c6d2f24",
+    },
+    "fetch_kib": 679795.7, "write_kib": 121160.4, "fetch_scale": 2.0, "write_scale": 1.0,
+}
+
+
+def tile_traffic_bytes():
+    """Measured HBM bytes per k_ms_pull_tile launch, or None once the kernel
+    sources differ from those the counters were taken with."""
+    import hashlib
+    for rel, h in TILE_TRAFFIC["sources_sha256"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != h:
+                return None
+    t = TILE_TRAFFIC
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 METRIC = "GTEPS and HBM-roofline fraction at 1 GPU: fixed variant vs learned/batched"
 
 
@@ -91,6 +118,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip single-source modes and fixed variants")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch")
     ap.add_argument("--sweep-sources", type=int, default=16)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (3 times): the reference "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md, 'Sharding' describes "
@@ -98,6 +128,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}))
+        return
     import graphgen as gg
     import paper_2607_17106_amd as B
     from paper_2607_17106_amd import bytemodel, selector
@@ -129,24 +167,35 @@ def main():
     elapsed = time.perf_counter() - t_start
     gteps = sum(st["component_edges"] for st in stats) / 2 / elapsed / 1e9
 
-    # roofline of the dominant level kernel (bottom-up or top-down step)
-    per_t, per_b, per_n = {}, {}, {}
+    # roofline of the dominant kernel: the bottom-up tile kernel (k_ms_pull_tile),
+    # timed alone by the library's HIP events on its stream, priced by its own
+    # algorithmic bytes (bytemodel.ms_tile_bytes)
+    t_tile = b_tile = 0.0
+    n_tile = 0
+    per_t, per_b = {}, {}
     for st in stats:
-        bts = bytemodel.ms_level_bytes(st, g.n)
+        tb = bytemodel.ms_tile_level_bytes(st, g.n)
+        lb = bytemodel.ms_level_bytes(st, g.n)
         for k in range(st["num_levels"]):
-            v = "ms_pull" if int(st["variant"][k]) == B.PULL_B else "ms_push"
+            v = "bottom_up_step" if int(st["variant"][k]) == B.PULL_B else "top_down_step"
             per_t[v] = per_t.get(v, 0.0) + float(st["ms"][k])
-            per_b[v] = per_b.get(v, 0.0) + bts[k]
-            per_n[v] = per_n.get(v, 0) + 1
-    dom = max(per_t, key=per_t.get)
-    achieved = per_b[dom] / (per_t[dom] * 1e-3) / 1e9
-    kernel_name = {"ms_pull": "k_ms_pull_heavy + k_ms_pull_tile", "ms_push": "k_ms_push + k_ms_push_update"}[dom]
+            per_b[v] = per_b.get(v, 0.0) + lb[k]
+            if tb[k] is not None:
+                t_tile += float(st["ms_main"][k])
+                b_tile += tb[k]
+                n_tile += 1
+    achieved = b_tile / (t_tile * 1e-3) / 1e9
+    step_level_ms = sum(per_t.values()) / len(stats)
+    traffic = tile_traffic_bytes() if args.workload == "rmat22" and len(sources) == 64 else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel_name,
-            "launches": per_n[dom], "avg_launch_us": round(per_t[dom] * 1e3 / per_n[dom], 2),
-            "bytes_per_launch": round(per_b[dom] / per_n[dom]),
-            "time_share_of_level_kernels": round(per_t[dom] / sum(per_t.values()), 3),
-            "per_kernel_gbs": {k: round(per_b[k] / (per_t[k] * 1e-3) / 1e9, 1) for k in per_t}}
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic) if traffic is not None else None, "kernel": "k_ms_pull_tile",
+            "launches": n_tile, "avg_launch_us": round(t_tile * 1e3 / max(n_tile, 1), 2),
+            "bytes_per_launch": round(b_tile / max(n_tile, 1)),
+            "time_share_of_level_steps": round(t_tile / len(stats) / step_level_ms, 3),
+            "level_steps_gbs": {k: round(per_b[k] / (per_t[k] * 1e-3) / 1e9, 1) for k in per_t}}
+    if traffic is not None:
+        roof["traffic_over_algorithmic"] = round(traffic / (b_tile / max(n_tile, 1)), 2)
     st0 = stats[0]
     for k in range(st0["num_levels"]):
         log(f"[bench] ms level {k}: {'pull' if int(st0['variant'][k]) == B.PULL_B else 'push'} "

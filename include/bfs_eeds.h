@@ -146,6 +146,11 @@ typedef struct bfs_stats {
   int64_t *level_scanned;      /* edges examined by the step that expanded F_k */
   int64_t *level_next;         /* |F_{k+1}| found by that step */
   float *level_ms;             /* BFS_F_LEVEL_TIMING: device time of that step */
+  /* bfs_multi only (untouched by the single-source calls): */
+  float *level_ms_main;        /* BFS_F_LEVEL_TIMING: device time of the step's main kernel
+                                  (bottom-up: the tile kernel; top-down: the light-source kernel) */
+  int64_t *level_scanned_aux;  /* edges examined by the step's heavy-vertex kernel (part of level_scanned) */
+  int64_t *level_hits_aux;     /* frontier words that kernel gathered (part of level_frontier_ld2) */
 } bfs_stats;
 
 /* Workspace bytes for a graph of n vertices.  lanes = 1 for bfs_levels /

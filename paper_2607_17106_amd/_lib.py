@@ -69,7 +69,8 @@ class BfsStats(ctypes.Structure):
                 ("level_fallback", POINTER(c_int32)), ("level_frontier_ld", POINTER(c_int64)),
                 ("level_frontier_ld2", POINTER(c_int64)), ("graph_ld", c_int64), ("graph_ld2", c_int64),
                 ("level_scanned", POINTER(c_int64)), ("level_next", POINTER(c_int64)),
-                ("level_ms", POINTER(c_float))]
+                ("level_ms", POINTER(c_float)), ("level_ms_main", POINTER(c_float)),
+                ("level_scanned_aux", POINTER(c_int64)), ("level_hits_aux", POINTER(c_int64))]
 
 
 class BfsGraphBatch(ctypes.Structure):

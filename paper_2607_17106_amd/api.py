@@ -85,6 +85,9 @@ class _StatsBuf:
         self.scanned = np.zeros(cap, np.int64)
         self.nxt = np.zeros(cap, np.int64)
         self.ms = np.zeros(cap, np.float32)
+        self.ms_main = np.zeros(cap, np.float32)
+        self.scan_aux = np.zeros(cap, np.int64)
+        self.hits_aux = np.zeros(cap, np.int64)
         P32, P64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
         self.s = L.BfsStats()
         self.s.level_capacity = cap
@@ -99,6 +102,9 @@ class _StatsBuf:
         self.s.level_scanned = self.scanned.ctypes.data_as(P64)
         self.s.level_next = self.nxt.ctypes.data_as(P64)
         self.s.level_ms = self.ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self.s.level_ms_main = self.ms_main.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self.s.level_scanned_aux = self.scan_aux.ctypes.data_as(P64)
+        self.s.level_hits_aux = self.hits_aux.ctypes.data_as(P64)
 
     def as_dict(self, per_level: bool):
         s = self.s
@@ -111,7 +117,9 @@ class _StatsBuf:
                      frontier_edges=self.frontier_edges[:k].copy(), unvisited=self.unvisited[:k].copy(),
                      unvisited_edges=self.unvisited_edges[:k].copy(), fallback=self.fallback[:k].copy(),
                      frontier_ld=self.fld[:k].copy(), frontier_ld2=self.fld2[:k].copy(),
-                     scanned=self.scanned[:k].copy(), next=self.nxt[:k].copy(), ms=self.ms[:k].copy())
+                     scanned=self.scanned[:k].copy(), next=self.nxt[:k].copy(), ms=self.ms[:k].copy(),
+                     ms_main=self.ms_main[:k].copy(), scanned_aux=self.scan_aux[:k].copy(),
+                     hits_aux=self.hits_aux[:k].copy())
         return d
 
 

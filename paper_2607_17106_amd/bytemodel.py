@@ -88,6 +88,35 @@ def ms_step_bytes(pull: bool, n: int, k: int, nf: int, unvis: int, scan: int, hi
     return 8.0 * n + n / 8.0 + 16.0 * nf + 12.0 * scan + 8.0 * found + 8.0 * n + n / 8.0 + 8.0 * found + disc
 
 
+def ms_tile_bytes(n: int, k: int, unvis: int, scan_light: int, hits_light: int, found: int) -> float:
+    """The bottom-up tile kernel alone: the dense per-vertex part (8n visited
+    read, 8n next written, 8n dead buffer cleared, n/8 next bitmap, 8 per
+    unvis for the csc_ptr pair), the light vertices' in-edges (4 per column id
+    + 1/8 per bitmap probe), their gathered frontier words (8 each) and the
+    discoveries (visited write + plane updates).  The heavy kernel's edges and
+    gathers are excluded (scan_light = scanned - scanned_aux, hits_light =
+    hits - hits_aux)."""
+    disc = found * (8.0 + 16.0 * bin(ms_rel(k)).count("1"))
+    return 24.0 * n + n / 8.0 + 8.0 * unvis + 4.125 * scan_light + 8.0 * hits_light + disc
+
+
+def ms_tile_level_bytes(stats: dict, n: int):
+    """ms_tile_bytes for every bottom-up level of a bfs_multi run (None for
+    top-down levels)."""
+    out = []
+    k = 0
+    for i in range(int(stats["num_levels"])):
+        if int(stats["variant"][i]) == L.PULL_B:
+            out.append(ms_tile_bytes(n, k, int(stats["unvisited"][i]),
+                                     int(stats["scanned"][i]) - int(stats["scanned_aux"][i]),
+                                     int(stats["frontier_ld2"][i]) - int(stats["hits_aux"][i]),
+                                     int(stats["frontier_ld"][i])))
+        else:
+            out.append(None)
+        k = 0 if int(stats["next"][i]) == 0 else k + 1
+    return out
+
+
 def ms_level_bytes(stats: dict, n: int):
     """Per-level bytes of a bfs_multi run with level stats (one group of up to
     64 lanes: the level index restarts at 0 for each group)."""

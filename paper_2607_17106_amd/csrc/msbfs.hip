@@ -47,7 +47,7 @@ constexpr int MS_SUM_WORDS = 8192; // frontier summary: 2^18 bits = 32 KB of LDS
 constexpr int MS_SUM_GRID = 1024;  // persistent workgroups of the summary-filtered bottom-up kernels
 static_assert(MS_HCHUNK <= MS_HEAVY, "a heavy list is longer than one chunk");
 
-struct MsCtr {  // one 64-byte line per shard
+struct MsCtr {  // two 64-byte lines per shard
   u64 newbits;     // (lane, vertex) pairs discovered
   u64 comp_edges;  // sum over discoveries of outdeg(v) (per lane)
   u64 active;      // vertices with at least one new lane (next frontier size)
@@ -56,9 +56,12 @@ struct MsCtr {  // one 64-byte line per shard
   u64 scanned;     // edges examined
   u64 unvis;       // vertices still missing some lane when the step started
   u64 hits;        // examined edges whose source is in the frontier (words gathered)
+  u64 hscanned;    // the part of `scanned` examined by the heavy-vertex kernel
+  u64 hhits;       // the part of `hits` gathered by it
+  u64 pad[6];
 };
-static_assert(sizeof(MsCtr) == 64, "MsCtr is one line");
-constexpr int MS_NCTR = 8;
+static_assert(sizeof(MsCtr) == 128, "MsCtr is two lines");
+constexpr int MS_NCTR = 16;
 
 struct MsArgs {
   int n, k, L;          // vertices, level, lanes in this group
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_summary(const u64 *fb, int nwords,
 }
 
 struct MsStats {
-  u64 c[MS_NCTR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  u64 c[MS_NCTR] = {};
   __device__ __forceinline__ void flush(MsCtr *sh) {
     u64 *f = reinterpret_cast<u64 *>(sh + (blockIdx.x % NSH));
 #pragma unroll
@@ -193,7 +196,7 @@ struct MsStats {
     }
   }
 };
-enum { C_NEW, C_COMP, C_ACTIVE, C_ACTOUT, C_DONEIN, C_SCAN, C_UNVIS, C_HITS };
+enum { C_NEW, C_COMP, C_ACTIVE, C_ACTOUT, C_DONEIN, C_SCAN, C_UNVIS, C_HITS, C_HSCAN, C_HHITS };
 
 // Workgroup-level flush: one atomic per counter and workgroup.  Every thread
 // of the workgroup must call it.
@@ -442,11 +445,15 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
         if (hit[r]) {
           f |= a.front[u[r]];
           st.c[C_HITS] += 1;
+          st.c[C_HHITS] += 1;
         }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
       mine |= f & need;
-      if (lane() == 0) st.c[C_SCAN] += (u64)min(MS_HU * WAVE, se - base);
+      if (lane() == 0) {
+        st.c[C_SCAN] += (u64)min(MS_HU * WAVE, se - base);
+        st.c[C_HSCAN] += (u64)min(MS_HU * WAVE, se - base);
+      }
       if (((known | mine) & need) == need) break;
       if (++round % MS_POST == 0 && (mine & ~posted)) {
         u64 old = 0ull;
@@ -734,7 +741,10 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
       for (int r = 0; r < MS_HU; ++r)
         if (m[r]) atomicOr(a.next + v[r], m[r]);
     }
-    if (lane() == 0) st.c[C_SCAN] += (u64)(se - sb);
+    if (lane() == 0) {
+      st.c[C_SCAN] += (u64)(se - sb);
+      st.c[C_HSCAN] += (u64)(se - sb);
+    }
   }
   ms_flush_block(st, a.sh);
 }
@@ -992,6 +1002,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         }
         // one vertex per thread while many in-edges remain to be scanned (more
         // workgroups in flight); four when few do (fixed costs amortised)
+        if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[0], s));
         if (eu > 2 * (long long)n) {
           if (sum)
             hipLaunchKernelGGL((k_ms_pull_tile<1, true>), dim3(std::min(grid_t1, MS_SUM_GRID)), dim3(BLOCK), lds, s, a);
@@ -1004,8 +1015,11 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           else
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false>), dim3(grid_t4), dim3(BLOCK), 0, s, a);
         }
+        if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[1], s));
       } else {
+        if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[0], s));
         hipLaunchKernelGGL(k_ms_push, dim3(grid_w), dim3(BLOCK), 0, s, a);
+        if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[1], s));
         if (a.ochunks > 0)
           hipLaunchKernelGGL(k_ms_push_heavy, dim3(std::min(4096, (a.ochunks + 3) / 4)), dim3(BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
@@ -1030,6 +1044,13 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         if (st->level_next) st->level_next[r] = (long long)c.newbits;
         if (st->level_frontier_ld) st->level_frontier_ld[r] = (long long)c.active;
         if (st->level_frontier_ld2) st->level_frontier_ld2[r] = (long long)c.hits;
+        if (st->level_scanned_aux) st->level_scanned_aux[r] = (long long)c.hscanned;
+        if (st->level_hits_aux) st->level_hits_aux[r] = (long long)c.hhits;
+        if (st->level_ms_main) {
+          float ms = 0.f;
+          if (timing) BFS_HIP(hipEventElapsedTime(&ms, hc.lev_ev[0], hc.lev_ev[1]));
+          st->level_ms_main[r] = ms;
+        }
         if (st->level_ms) {
           float ms = 0.f;
           if (timing) BFS_HIP(hipEventElapsedTime(&ms, hc.ev[2], hc.ev[3]));

@@ -43,6 +43,8 @@ def _check_level_stats(g, srcs, ref, st):
             assert int(st["frontier_ld"][i]) == int(found.any(axis=0).sum()), (g0, k)
             assert int(st["frontier"][i]) == int((r == k).any(axis=0).sum()), (g0, k)
             assert 0 <= int(st["frontier_ld2"][i]) <= int(st["scanned"][i])
+            assert 0 <= int(st["scanned_aux"][i]) <= int(st["scanned"][i])
+            assert 0 <= int(st["hits_aux"][i]) <= min(int(st["frontier_ld2"][i]), int(st["scanned_aux"][i]))
             i += 1
     assert st["num_levels"] == i
 
