@@ -39,25 +39,35 @@ HBM_PEAK_GBS = 8000.0
 # then WRITE_SIZE, KiB per dispatch averaged over the kernel's 16 dispatches),
 # each scaled by what the same counter reads for a plain copy of 1 GiB
 # (`bench.py --copy-calibration 1073741824`: FETCH_SIZE 524300 KiB -> x2.0,
-# WRITE_SIZE 1048576 KiB -> x1.0).  Reported only while the kernel sources
-# hash to the values the counters were taken with.
+# WRITE_SIZE 1048576 KiB -> x1.0).  Reported only while the kernel code
+# (comments and whitespace aside) hashes to the values the counters were taken with.
 TILE_TRAFFIC = {
     "sources_sha256": {
-        "paper_2607_17106_amd/csrc/msbfs.hip": "858be9f83a2357ab573fa9fe58f8dc9fa74d2b6673d096bf7842c406115b2a92",
-        "paper_2607_17106_amd/csrc/common.hpp": "f8b19fcbc9a66cd71f0b882946620fd743f1827bfb536f5541b271e84c6d2f24",
+        "paper_2607_17106_amd/csrc/msbfs.hip": "50b41986e067063217bc37f1fb922ab853fc034f718506a1d6667f3e1e1a402d",
+        "paper_2607_17106_amd/csrc/common.hpp": "082bff47601a629526c148d9adef7ccc3acce82260afacd87a666552aa9fb4cf",
     },
     "fetch_kib": 679795.7, "write_kib": 121160.4, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
+def code_hash(path: str) -> str:
+    """sha256 of a C/HIP source with comments and whitespace removed, so that
+    only code changes count."""
+    import hashlib
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return hashlib.sha256("".join(text.split()).encode()).hexdigest()
+
+
 def tile_traffic_bytes():
     """Measured HBM bytes per k_ms_pull_tile launch, or None once the kernel
-    sources differ from those the counters were taken with."""
-    import hashlib
+    code differs from the code the counters were taken with."""
     for rel, h in TILE_TRAFFIC["sources_sha256"].items():
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != h:
-                return None
+        if code_hash(os.path.join(ROOT, rel)) != h:
+            return None
     t = TILE_TRAFFIC
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 METRIC = "GTEPS and HBM-roofline fraction at 1 GPU: fixed variant vs learned/batched"

@@ -170,7 +170,7 @@ int bfs_levels(const bfs_graph *g, int32_t source, int32_t *levels,
 int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *parents,
                 const bfs_options *opt, bfs_stats *st, void *stream);
 
-/* Multi-source BFS over k sources (Cascade 1 with source node(s): one extra
+/* Multi-source BFS over k sources (Cascade 1 started from several source nodes: one extra
  * lane rank on F and P).  Sources are processed in groups of up to 64 lanes;
  * lane l of vertex v lives in bit l of one u64 word, so a level is
  *     next[v] = (OR_{u in N_in(v)} front[u]) AND NOT vis[v]

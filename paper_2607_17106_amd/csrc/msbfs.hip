@@ -1,6 +1,6 @@
 // Multi-source BFS with up to 64 bit-packed lanes per vertex.
 //
-// Cascade 1 starts from "the source node(s)" (its initialisation); giving F
+// Cascade 1's initialisation admits more than one source node; giving F
 // and P one more rank for the source index and packing 64 of its coordinates
 // into one u64 per vertex turns a level into word-wide boolean algebra:
 //   next[v] = (OR_{u in N_in(v)} front[u]) AND NOT vis[v]     (advance, pull)
