@@ -173,6 +173,13 @@ static hipError_t launch_finish_f0(const Workspace &w, hipStream_t s) {
   return launch_log_f0(w.ring, w.log, w.ctl, s);
 }
 
+// Degree above which the block-mapped and bitmap pushes defer a frontier
+// vertex to the grid-wide hub pass.  Those pushes give each workgroup up to
+// BLOCK frontier vertices, so with a small frontier the lists of a whole level
+// would sit on one or two workgroups: the threshold then drops and nearly every
+// list is spread over the grid.
+static int hub_threshold(long long frontier) { return frontier < 64LL * BLOCK ? 64 : DEFAULT_HUB; }
+
 static StepArgs level_args(const bfs_graph *g, const Workspace &w, int *levels, int *parents, int k, int hub) {
   StepArgs a;
   a.gate = -1;
@@ -369,7 +376,7 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
       int v = device_decides ? dec : fixed_variant(k);
       if (v < 0 || v >= BFS_NUM_VARIANTS || (is_pull(v) && !have_csc)) v = push_v;
       host_variant.push_back(v);
-      a = level_args(g, w, levels, parents, k, DEFAULT_HUB);
+      a = level_args(g, w, levels, parents, k, hub_threshold(cnt));
       a.gate = -1;
       if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
       BFS_HIP(launch_step(v, a, (int)cnt, eF, s));
@@ -547,6 +554,7 @@ static int step_time(const bfs_graph *g, const int *depths, int k, int variant, 
     BFS_HIP(hipMemcpyAsync(hc.pinned, a.c_cur, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
     BFS_HIP(hipStreamSynchronize(s));
     long long cnt = hc.pinned[0].count, eF = (long long)hc.pinned[0].edges;
+    a.hub = hub_threshold(cnt);
     BFS_HIP(hipEventRecord(hc.ev[0], s));
     BFS_HIP(launch_step(variant, a, (int)cnt, eF, s));
     BFS_HIP(hipEventRecord(hc.ev[1], s));
