@@ -85,6 +85,7 @@ struct MsArgs {
   int ocount, ochunks;
   int *levels;          // row l at levels + l * n
   int base, np, nflush; // output passes: window base, planes in use, flushes so far
+  bool vec4;            // output rows are 16-byte aligned at multiples of 4 vertices
   int cap0;             // bottom-up: in-edges per pending vertex in the first merged round
   const u32 *fsum;      // summary of fbits: bit i set if any vertex in [i << sshift, (i+1) << sshift) is
   int sshift;           // in the frontier; MS_SUM_WORDS words, staged in LDS by bottom-up kernels
@@ -238,48 +239,74 @@ __device__ __forceinline__ void ms_discover(const MsArgs &a, int v, u64 vis_old,
   if ((vnew & a.full) == a.full) st.c[C_DONEIN] += (u64)(a.cp[v + 1] - a.cp[v]);
 }
 
-// Writes the depth of every lane of v not in `skip`: a.base + r for visited
-// lanes (r read from the NP planes in use), -1 for the others.  Called by
-// whole waves holding 64 consecutive vertices, so each of the L row stores
-// covers 64 consecutive ints; lanes with valid = false store nothing.  The
-// planes are split into 32-bit halves so one bit-field extract per plane
-// gives a lane's bit.
+// Output pass body: each thread owns 4 consecutive vertices v0..v0+3 and, for
+// every lane row, writes their 4 depths (a.base + r for visited lanes, r read
+// from the NP planes in use; -1 for the others) as one 16-byte store when all
+// four are due and the row is 16-byte aligned (a.vec4), else one by one.  A
+// wave thus writes 1 KB of consecutive ints per row instruction.  Lanes in
+// `skip` are not written.  The planes are split into 32-bit halves so one
+// bit-field extract per plane gives a lane's bit.
 template <int NP>
-__device__ __forceinline__ void ms_store_depths(const MsArgs &a, int v, bool valid, u64 vw, u64 skip) {
-  uint32_t pl[2][NP];
+__device__ __forceinline__ void ms_store_depths4(const MsArgs &a, int v0, const u64 (&vw)[4], const u64 (&skip)[4]) {
+  uint32_t pl[4][2][NP];
+  u64 store[4];
 #pragma unroll
-  for (int b = 0; b < NP; ++b) {
-    const u64 w = valid ? a.planes[(size_t)b * a.n + v] : 0ull;
-    pl[0][b] = (uint32_t)w;
-    pl[1][b] = (uint32_t)(w >> 32);
+  for (int j = 0; j < 4; ++j) {
+    const bool valid = v0 + j < a.n;
+    store[j] = valid ? ~skip[j] : 0ull;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const u64 w = valid ? a.planes[(size_t)b * a.n + v0 + j] : 0ull;
+      pl[j][0][b] = (uint32_t)w;
+      pl[j][1][b] = (uint32_t)(w >> 32);
+    }
   }
-  const u64 store = valid ? ~skip : 0ull;
-  int *out = a.levels + v;
+  int *out = a.levels + v0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const uint32_t vis_h = (uint32_t)(vw >> (32 * h)), st_h = (uint32_t)(store >> (32 * h));
     const int lend = min(a.L - 32 * h, 32);
     for (int l = 0; l < lend; ++l, out += a.n) {
-      int r = 0;
+      int val[4];
+      bool st4 = a.vec4;
+      bool stj[4];
 #pragma unroll
-      for (int b = 0; b < NP; ++b) r |= (int)((pl[h][b] >> l) & 1u) << b;
-      if ((st_h >> l) & 1u) *out = ((vis_h >> l) & 1u) ? a.base + r : -1;
+      for (int j = 0; j < 4; ++j) {
+        int r = 0;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) r |= (int)((pl[j][h][b] >> l) & 1u) << b;
+        val[j] = ((uint32_t)(vw[j] >> (32 * h)) >> l) & 1u ? a.base + r : -1;
+        stj[j] = ((uint32_t)(store[j] >> (32 * h)) >> l) & 1u;
+        st4 = st4 && stj[j];
+      }
+      if (st4) {
+        *reinterpret_cast<int4 *>(out) = make_int4(val[0], val[1], val[2], val[3]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (stj[j]) out[j] = val[j];
+      }
     }
   }
 }
 
 template <int NP>
 __device__ __forceinline__ void ms_out_body(const MsArgs &a, int flush) {
-  for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {  // uniform per wave
-    const int v = base + threadIdx.x;
-    const bool valid = v < a.n;
-    const u64 vw = valid ? a.vis[v] & a.full : 0ull;
-    const u64 fl = (valid && a.nflush) ? a.flushed[v] : 0ull;
+  for (int base = blockIdx.x * 4 * BLOCK; base < a.n; base += gridDim.x * 4 * BLOCK) {  // uniform per wave
+    const int v0 = base + 4 * threadIdx.x;
+    u64 vw[4], skip[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int v = v0 + j;
+      const bool valid = v < a.n;
+      vw[j] = valid ? a.vis[v] & a.full : 0ull;
+      const u64 fl = (valid && a.nflush) ? a.flushed[v] : 0ull;
+      skip[j] = flush ? ~(vw[j] & ~fl) : fl;
+    }
+    ms_store_depths4<NP>(a, v0, vw, skip);
     if (flush) {
-      ms_store_depths<NP>(a, v, valid, vw, ~(vw & ~fl));
-      if (valid) a.flushed[v] = vw;
-    } else {
-      ms_store_depths<NP>(a, v, valid, vw, fl);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (v0 + j < a.n) a.flushed[v0 + j] = vw[j];
     }
   }
 }
@@ -506,12 +533,12 @@ __device__ __forceinline__ void ms_multi_scan(const int (&x)[VPT], int (&off)[VP
 // the bitmaps).  A light vertex's own thread first ORs the frontier words of
 // its first MS_HEAD in-edges (bitmap probe first).  The remaining in-edge
 // lists of the vertices that still miss lanes are laid end to end (one scan
-// over all slots) and walked MS_EPT * BLOCK edges per iteration: an edge finds
-// its vertex by binary search over the scanned offsets in LDS and is skipped
-// once that vertex has all its missing lanes; the gathered words are
-// OR-reduced per vertex inside the wave (a segmented scan: a wave's edges
-// belong to non-decreasing vertices) and posted with one LDS atomic per vertex
-// and wave.  Heavy vertices take the heavy pass's result from accb.  Also
+// over all slots) and walked MS_EPT * BLOCK edges per iteration, MS_EPT
+// consecutive ones per thread: the thread finds the vertex of its first edge
+// by binary search over the scanned offsets in LDS and advances linearly, skips
+// the gathers of a vertex that already has all its missing lanes, ORs the
+// gathered words per vertex, and posts them with LDS atomics (the last vertex
+// of each thread through one segmented scan over the wave).  Heavy vertices take the heavy pass's result from accb.  Also
 // writes next, the next bitmap and the discoveries, and clears the dead
 // frontier buffer.
 template <int VPT, bool SUM>
@@ -600,22 +627,40 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       if (t == 0) s_off[TV] = total;
       __syncthreads();
       for (int c0 = 0; c0 < total; c0 += MS_EPT * BLOCK) {  // uniform per workgroup
-        int o[MS_EPT], u[MS_EPT];
+        // thread t takes MS_EPT consecutive positions of the laid-out lists:
+        // one binary search for the first owner, then a linear advance
+        const int e0 = c0 + t * MS_EPT;
+        int o = -1, next_off = 0, base_j = 0;
+        bool skip = true;
+        if (e0 < total) {
+          int lo = 0, hi = TV;  // s_off[lo] <= e0 < s_off[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid] <= e0) lo = mid; else hi = mid;
+          }
+          o = lo;
+          next_off = s_off[o + 1];
+          base_j = s_beg[o] - s_off[o];
+          const u64 nd = s_need[o];
+          skip = (s_acc[o] & nd) == nd;  // lanes already complete: no more gathers for o
+        }
+        int own[MS_EPT], u[MS_EPT];
 #pragma unroll
         for (int i = 0; i < MS_EPT; ++i) {
-          const int e = c0 + i * BLOCK + t;
-          o[i] = -1;
+          const int e = e0 + i;
+          own[i] = -1;
           u[i] = -1;
-          if (e < total) {
-            int lo = 0, hi = TV;  // s_off[lo] <= e < s_off[hi]
-            while (hi - lo > 1) {
-              const int mid = (lo + hi) >> 1;
-              if (s_off[mid] <= e) lo = mid; else hi = mid;
+          if (o >= 0 && e < total) {
+            while (e >= next_off) {  // next owner with edges left (s_off[TV] = total > e)
+              ++o;
+              next_off = s_off[o + 1];
+              base_j = s_beg[o] - s_off[o];
+              const u64 nd = s_need[o];
+              skip = (s_acc[o] & nd) == nd;
             }
-            o[i] = lo;
-            const u64 nd = s_need[lo];
-            if ((s_acc[lo] & nd) != nd) {
-              u[i] = a.cx[s_beg[lo] + (e - s_off[lo])];
+            own[i] = o;
+            if (!skip) {
+              u[i] = a.cx[base_j + e];
               st.c[C_SCAN] += 1;
             }
           }
@@ -623,22 +668,32 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
         bool hit[MS_EPT];
 #pragma unroll
         for (int i = 0; i < MS_EPT; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
+        // OR per owner inside the thread; a segment that ends inside the thread
+        // is posted directly, the thread's last segment goes through one
+        // segmented scan over the wave (equal owners in neighbouring lanes merge)
+        u64 run = 0ull;
+        int ro = own[0];
 #pragma unroll
         for (int i = 0; i < MS_EPT; ++i) {
-          u64 f = hit[i] ? a.front[u[i]] : 0ull;
+          const u64 f = hit[i] ? a.front[u[i]] : 0ull;
           st.c[C_HITS] += hit[i] ? 1 : 0;
-          if (__ballot(f != 0ull)) {
-            const int oi = o[i];
-#pragma unroll
-            for (int dd = 1; dd < WAVE; dd <<= 1) {
-              const u64 y = __shfl_up(f, (unsigned)dd);
-              const int oy = __shfl_up(oi, (unsigned)dd);
-              if (lane() >= dd && oy == oi) f |= y;
-            }
-            const int on = __shfl_down(oi, 1u);
-            const bool tail = lane() == WAVE - 1 || on != oi;
-            if (tail && f) atomicOr(&s_acc[oi], f);
+          if (own[i] != ro) {
+            if (run) atomicOr(&s_acc[ro], run);
+            run = 0ull;
+            ro = own[i];
           }
+          run |= f;
+        }
+        if (__ballot(run != 0ull)) {
+#pragma unroll
+          for (int dd = 1; dd < WAVE; dd <<= 1) {
+            const u64 y = __shfl_up(run, (unsigned)dd);
+            const int oy = __shfl_up(ro, (unsigned)dd);
+            if (lane() >= dd && oy == ro) run |= y;
+          }
+          const int on = __shfl_down(ro, 1u);
+          const bool tail = lane() == WAVE - 1 || on != ro;
+          if (tail && run) atomicOr(&s_acc[ro], run);
         }
       }
       __syncthreads();
@@ -848,6 +903,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   int *src_dev = W.src;
   HostCtx &hc = host_ctx();
   const int grid_v = std::min(4096, (n + BLOCK - 1) / BLOCK);
+  const int grid_o = std::min(4096, (n + 4 * BLOCK - 1) / (4 * BLOCK));
   const int grid_w = std::min(4096, ((n + WAVE - 1) / WAVE + 3) / 4);
   const int grid_t1 = std::min(65536, (n + BLOCK - 1) / BLOCK);
   const int grid_t4 = std::min(65536, (n + MS_VPT_SPARSE * BLOCK - 1) / (MS_VPT_SPARSE * BLOCK));
@@ -900,6 +956,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.base = 0;
     a.np = 0;
     a.nflush = 0;
+    a.vec4 = n % 4 == 0 && reinterpret_cast<uintptr_t>(a.levels) % 16 == 0;
     hipLaunchKernelGGL(k_ms_init, dim3(grid_v), dim3(BLOCK), 0, s, a, fr[0], fr[1], W.fb[0]);
     BFS_HIP(hipMemcpyAsync(src_dev, sources + g0, L * sizeof(int), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, s, a, (const int *)src_dev, fr[0], W.fb[0]);
@@ -964,7 +1021,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       }
       // relative depth of this step's discoveries; a full window is written out first
       if (lev + 1 - a.base >= (1 << MS_PLANES)) {
-        hipLaunchKernelGGL(k_ms_out, dim3(grid_v), dim3(BLOCK), 0, s, a, 1);
+        hipLaunchKernelGGL(k_ms_out, dim3(grid_o), dim3(BLOCK), 0, s, a, 1);
         ++a.nflush;
         a.base = lev;
         a.np = 0;
@@ -1070,7 +1127,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       }
     }
     comp += src_comp;  // each lane's source belongs to its component
-    hipLaunchKernelGGL(k_ms_out, dim3(grid_v), dim3(BLOCK), 0, s, a, 0);
+    hipLaunchKernelGGL(k_ms_out, dim3(grid_o), dim3(BLOCK), 0, s, a, 0);
     BFS_HIP(hipGetLastError());
     max_levels = std::max(max_levels, lev);
   }
