@@ -199,7 +199,8 @@ int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_
  * entry offsets; col_idx holds LOCAL vertex ids of the same instance.  All
  * instances are searched in one persistent launch: each workgroup takes the
  * next instance (largest first) from a queue and runs that whole search
- * itself, choosing top-down or bottom-up per level by the direction rule, so
+ * itself, choosing bottom-up for a level when the in-edges it expects to read
+ * (min(e_U, n_U (e_U + e_F) / e_F)) are fewer than the frontier's out-edges, so
  * no instance needs synchronisation across workgroups. */
 typedef struct bfs_graph_batch {
   int32_t num;               /* instances, > 0 */

@@ -9,8 +9,9 @@
 // workgroup-scope atomics that resolve in that L2 (or in LDS), and no wait on
 // another workgroup ever happens, so the launch always drains.
 //
-// Per level the workgroup applies the direction rule (Beamer et al.,
-// alpha 14, beta 24) to its own counts:
+// Per level the workgroup picks a direction from its own counts, comparing
+// the in-edges a bottom-up step is expected to read with the frontier's
+// out-edges (see the rule in k_batch):
 //   top-down: the frontier queue is cut into chunks; each chunk's edges are
 //     flattened with a workgroup scan and split evenly over the lanes
 //     (Table 3, variant 1 at workgroup scale); a lane claims an unvisited
@@ -139,19 +140,20 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs A) {
     __syncthreads();
     long long nF = s_qn, eF = (long long)s_efn;
     long long eU = (long long)(rp[n] - rp[0]) - eF;
+    long long nU = n - 1;
     long long comp = eF;
     int dir = 0;
-    long long prev_nf = -1;
     int k = 0;
     for (;; ++k) {
       if (A.symmetric) {
-        if (dir == 0) {
-          if (eF * 14 > eU) dir = 1;
-        } else if (nF * 24 < n && prev_nf >= 0 && nF < prev_nf) {
-          dir = 0;
-        }
+        // One workgroup pays for every in-edge a bottom-up step reads.  An
+        // unvisited vertex reads about (e_U + e_F) / e_F in-edges before it
+        // meets a frontier member (in-edges drawn at random), and at most its
+        // degree, so the step reads about min(e_U, n_U (e_U + e_F) / e_F);
+        // the top-down step reads e_F.
+        const long long scan = eF > 0 ? min(eU, nU * ((eU + eF) / eF + 1)) : eU;
+        dir = scan < eF ? 1 : 0;
       }
-      prev_nf = nF;
       __syncthreads();
       if (threadIdx.x == 0) {
         s_qn = 0;
@@ -261,6 +263,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs A) {
       nF = s_qn;
       eF = (long long)s_efn;
       eU -= eF;  // symmetric instances: in-edges = out-edges of the new vertices
+      nU -= nF;
       comp += eF;
       int *tq = qc;
       qc = qn;

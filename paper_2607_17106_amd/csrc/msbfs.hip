@@ -85,7 +85,6 @@ struct MsArgs {
   int ocount, ochunks;
   int *levels;          // row l at levels + l * n
   int base, np, nflush; // output passes: window base, planes in use, flushes so far
-  bool vec4;            // output rows are 16-byte aligned at multiples of 4 vertices
   int cap0;             // bottom-up: in-edges per pending vertex in the first merged round
   const u32 *fsum;      // summary of fbits: bit i set if any vertex in [i << sshift, (i+1) << sshift) is
   int sshift;           // in the frontier; MS_SUM_WORDS words, staged in LDS by bottom-up kernels
@@ -239,74 +238,48 @@ __device__ __forceinline__ void ms_discover(const MsArgs &a, int v, u64 vis_old,
   if ((vnew & a.full) == a.full) st.c[C_DONEIN] += (u64)(a.cp[v + 1] - a.cp[v]);
 }
 
-// Output pass body: each thread owns 4 consecutive vertices v0..v0+3 and, for
-// every lane row, writes their 4 depths (a.base + r for visited lanes, r read
-// from the NP planes in use; -1 for the others) as one 16-byte store when all
-// four are due and the row is 16-byte aligned (a.vec4), else one by one.  A
-// wave thus writes 1 KB of consecutive ints per row instruction.  Lanes in
-// `skip` are not written.  The planes are split into 32-bit halves so one
-// bit-field extract per plane gives a lane's bit.
+// Writes the depth of every lane of v not in `skip`: a.base + r for visited
+// lanes (r read from the NP planes in use), -1 for the others.  Called by
+// whole waves holding 64 consecutive vertices, so each of the L row stores
+// covers 64 consecutive ints; lanes with valid = false store nothing.  The
+// planes are split into 32-bit halves so one bit-field extract per plane
+// gives a lane's bit.
 template <int NP>
-__device__ __forceinline__ void ms_store_depths4(const MsArgs &a, int v0, const u64 (&vw)[4], const u64 (&skip)[4]) {
-  uint32_t pl[4][2][NP];
-  u64 store[4];
+__device__ __forceinline__ void ms_store_depths(const MsArgs &a, int v, bool valid, u64 vw, u64 skip) {
+  uint32_t pl[2][NP];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const bool valid = v0 + j < a.n;
-    store[j] = valid ? ~skip[j] : 0ull;
-#pragma unroll
-    for (int b = 0; b < NP; ++b) {
-      const u64 w = valid ? a.planes[(size_t)b * a.n + v0 + j] : 0ull;
-      pl[j][0][b] = (uint32_t)w;
-      pl[j][1][b] = (uint32_t)(w >> 32);
-    }
+  for (int b = 0; b < NP; ++b) {
+    const u64 w = valid ? a.planes[(size_t)b * a.n + v] : 0ull;
+    pl[0][b] = (uint32_t)w;
+    pl[1][b] = (uint32_t)(w >> 32);
   }
-  int *out = a.levels + v0;
+  const u64 store = valid ? ~skip : 0ull;
+  int *out = a.levels + v;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
+    const uint32_t vis_h = (uint32_t)(vw >> (32 * h)), st_h = (uint32_t)(store >> (32 * h));
     const int lend = min(a.L - 32 * h, 32);
     for (int l = 0; l < lend; ++l, out += a.n) {
-      int val[4];
-      bool st4 = a.vec4;
-      bool stj[4];
+      int r = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int r = 0;
-#pragma unroll
-        for (int b = 0; b < NP; ++b) r |= (int)((pl[j][h][b] >> l) & 1u) << b;
-        val[j] = ((uint32_t)(vw[j] >> (32 * h)) >> l) & 1u ? a.base + r : -1;
-        stj[j] = ((uint32_t)(store[j] >> (32 * h)) >> l) & 1u;
-        st4 = st4 && stj[j];
-      }
-      if (st4) {
-        *reinterpret_cast<int4 *>(out) = make_int4(val[0], val[1], val[2], val[3]);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (stj[j]) out[j] = val[j];
-      }
+      for (int b = 0; b < NP; ++b) r |= (int)((pl[h][b] >> l) & 1u) << b;
+      if ((st_h >> l) & 1u) *out = ((vis_h >> l) & 1u) ? a.base + r : -1;
     }
   }
 }
 
 template <int NP>
 __device__ __forceinline__ void ms_out_body(const MsArgs &a, int flush) {
-  for (int base = blockIdx.x * 4 * BLOCK; base < a.n; base += gridDim.x * 4 * BLOCK) {  // uniform per wave
-    const int v0 = base + 4 * threadIdx.x;
-    u64 vw[4], skip[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int v = v0 + j;
-      const bool valid = v < a.n;
-      vw[j] = valid ? a.vis[v] & a.full : 0ull;
-      const u64 fl = (valid && a.nflush) ? a.flushed[v] : 0ull;
-      skip[j] = flush ? ~(vw[j] & ~fl) : fl;
-    }
-    ms_store_depths4<NP>(a, v0, vw, skip);
+  for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {  // uniform per wave
+    const int v = base + threadIdx.x;
+    const bool valid = v < a.n;
+    const u64 vw = valid ? a.vis[v] & a.full : 0ull;
+    const u64 fl = (valid && a.nflush) ? a.flushed[v] : 0ull;
     if (flush) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (v0 + j < a.n) a.flushed[v0 + j] = vw[j];
+      ms_store_depths<NP>(a, v, valid, vw, ~(vw & ~fl));
+      if (valid) a.flushed[v] = vw;
+    } else {
+      ms_store_depths<NP>(a, v, valid, vw, fl);
     }
   }
 }
@@ -835,14 +808,18 @@ __global__ __launch_bounds__(BLOCK) void k_ms_out(MsArgs a, int flush) {
   }
 }
 
+// Reduces the NSH counter shards of a level into *tot (pinned host memory,
+// read by the host after the stream sync) and clears each shard after reading
+// it, ready for the next level.
 __global__ __launch_bounds__(NSH) void k_ms_finish(MsCtr *sh, MsCtr *tot) {
   __shared__ u64 s_red[MS_NCTR][NSH / WAVE];
   const int t = threadIdx.x;
-  const u64 *f = reinterpret_cast<const u64 *>(sh + t);
+  u64 *f = reinterpret_cast<u64 *>(sh + t);
   for (int j = 0; j < MS_NCTR; ++j) {
     u64 r = wave_sum_u64(f[j]);
     if (lane() == 0) s_red[j][t / WAVE] = r;
   }
+  for (int j = 0; j < MS_NCTR; ++j) f[j] = 0ull;
   __syncthreads();
   if (t < MS_NCTR) {
     u64 r = 0;
@@ -899,11 +876,10 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   }
   const MsCarve W = ms_carve(reinterpret_cast<uintptr_t>(wsp), n);
   u64 *const *fr = W.fr;
-  MsCtr *sh = W.sh, *tot = W.tot;
+  MsCtr *sh = W.sh;
   int *src_dev = W.src;
   HostCtx &hc = host_ctx();
   const int grid_v = std::min(4096, (n + BLOCK - 1) / BLOCK);
-  const int grid_o = std::min(4096, (n + 4 * BLOCK - 1) / (4 * BLOCK));
   const int grid_w = std::min(4096, ((n + WAVE - 1) / WAVE + 3) / 4);
   const int grid_t1 = std::min(65536, (n + BLOCK - 1) / BLOCK);
   const int grid_t4 = std::min(65536, (n + MS_VPT_SPARSE * BLOCK - 1) / (MS_VPT_SPARSE * BLOCK));
@@ -956,8 +932,8 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.base = 0;
     a.np = 0;
     a.nflush = 0;
-    a.vec4 = n % 4 == 0 && reinterpret_cast<uintptr_t>(a.levels) % 16 == 0;
     hipLaunchKernelGGL(k_ms_init, dim3(grid_v), dim3(BLOCK), 0, s, a, fr[0], fr[1], W.fb[0]);
+    hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(BLOCK), 0, s, sh);  // k_ms_finish keeps them clear afterwards
     BFS_HIP(hipMemcpyAsync(src_dev, sources + g0, L * sizeof(int), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, s, a, (const int *)src_dev, fr[0], W.fb[0]);
     // counts of F_0 for the direction rule: distinct source vertices and their degrees
@@ -1021,7 +997,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       }
       // relative depth of this step's discoveries; a full window is written out first
       if (lev + 1 - a.base >= (1 << MS_PLANES)) {
-        hipLaunchKernelGGL(k_ms_out, dim3(grid_o), dim3(BLOCK), 0, s, a, 1);
+        hipLaunchKernelGGL(k_ms_out, dim3(grid_v), dim3(BLOCK), 0, s, a, 1);
         ++a.nflush;
         a.base = lev;
         a.np = 0;
@@ -1037,7 +1013,6 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       a.dead = fr[(lev + 2) % 3];
       a.fbits = W.fb[lev & 1];
       a.nbits = W.fb[(lev + 1) & 1];
-      hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(BLOCK), 0, s, sh);
       if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
       if (dir == 1) {
         // early exits pay for extra rounds only when the frontier carries a
@@ -1082,9 +1057,8 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
       }
       if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));
-      hipLaunchKernelGGL(k_ms_finish, dim3(1), dim3(NSH), 0, s, sh, tot);
+      hipLaunchKernelGGL(k_ms_finish, dim3(1), dim3(NSH), 0, s, sh, reinterpret_cast<MsCtr *>(hc.pinned));
       BFS_HIP(hipGetLastError());
-      BFS_HIP(hipMemcpyAsync(hc.pinned, tot, sizeof(MsCtr), hipMemcpyDeviceToHost, s));
       BFS_HIP(hipStreamSynchronize(s));
       ++syncs;
       MsCtr c;
@@ -1127,7 +1101,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       }
     }
     comp += src_comp;  // each lane's source belongs to its component
-    hipLaunchKernelGGL(k_ms_out, dim3(grid_o), dim3(BLOCK), 0, s, a, 0);
+    hipLaunchKernelGGL(k_ms_out, dim3(grid_v), dim3(BLOCK), 0, s, a, 0);
     BFS_HIP(hipGetLastError());
     max_levels = std::max(max_levels, lev);
   }
