@@ -97,6 +97,9 @@ int bfs_version(void);
                                     size back only every few levels (fewer host syncs) */
 #define BFS_F_LEVEL_TIMING 16    /* time each level's step with HIP events on the stream
                                     (fills level_ms; implies BFS_F_LEVEL_STATS) */
+#define BFS_F_GRAPH_SUMS 32      /* options.graph_ld / graph_ld2 hold the graph-wide
+                                    feature sums (from bfs_graph_sums): the call uses
+                                    them instead of recomputing them over all vertices */
 
 /* ----------------------------------------------------------------- types */
 typedef struct bfs_graph {
@@ -120,6 +123,7 @@ typedef struct bfs_options {
   int32_t heuristic_pull;        /* pull variant used by the heuristic (-1 => default) */
   void *workspace;               /* device scratch, or NULL for a library-cached buffer */
   size_t workspace_bytes;
+  int64_t graph_ld, graph_ld2;   /* with BFS_F_GRAPH_SUMS: the values bfs_graph_sums returned */
 } bfs_options;
 
 typedef struct bfs_stats {
@@ -152,6 +156,12 @@ typedef struct bfs_stats {
   int64_t *level_scanned_aux;  /* edges examined by the step's heavy-vertex kernel (part of level_scanned) */
   int64_t *level_hits_aux;     /* frontier words that kernel gathered (part of level_frontier_ld2) */
 } bfs_stats;
+
+/* Graph-wide sums over all vertices of floor(log2(1 + outdeg)) and of its
+ * square: the two graph features of the learned per-level selector.  A caller
+ * that searches one graph many times computes them once and passes them with
+ * BFS_F_GRAPH_SUMS.  ld, ld2: host outputs.  Synchronises the stream. */
+int bfs_graph_sums(const bfs_graph *g, int64_t *ld, int64_t *ld2, void *stream);
 
 /* Workspace bytes for a graph of n vertices.  lanes = 1 for bfs_levels /
  * bfs_parents, 2..64 for bfs_multi (bit-packed lanes, u64 words per vertex). */

@@ -64,6 +64,16 @@ class DeviceGraph:
     def c(self):
         return ctypes.byref(self._c)
 
+    def graph_sums(self, stream=None):
+        """The selector's graph-wide feature sums (bfs_graph_sums), computed on
+        first use and kept with the graph."""
+        if getattr(self, "_gsums", None) is None:
+            ld, ld2 = ctypes.c_int64(0), ctypes.c_int64(0)
+            L.check(L.load().bfs_graph_sums(self.c, ctypes.byref(ld), ctypes.byref(ld2), _stream(stream)),
+                    "bfs_graph_sums")
+            self._gsums = (int(ld.value), int(ld2.value))
+        return self._gsums
+
 
 def workspace_size(n: int, lanes: int = 1) -> int:
     b = ctypes.c_size_t(0)
@@ -156,6 +166,9 @@ def _run_single(fn_name, g: DeviceGraph, source, want_parents, variant, flags, s
         flags |= L.F_LEVEL_STATS
     sb = _StatsBuf(stats_capacity if level_stats else 0)
     opt, keep = _options(variant, flags, schedule, workspace, max_levels, heuristic_push)
+    if variant == L.AUTO_LEARNED or level_stats:
+        opt.graph_ld, opt.graph_ld2 = g.graph_sums(stream)
+        opt.flags |= L.F_GRAPH_SUMS
     if want_parents:
         rc = lib.bfs_parents(g.c, int(source), _ptr(levels), _ptr(parents), ctypes.byref(opt),
                              ctypes.byref(sb.s), _stream(stream))

@@ -17,13 +17,39 @@
 #include "common.hpp"
 #include "selector.hpp"
 #include "selector_dev.hpp"
+#include "step_bodies.hpp"
 
 namespace bfs {
 
-__global__ __launch_bounds__(64) void k_select(SelDevice sd, RingSlot *ring, int k, int n, int nnz,
-                                               const u64 *gsum, int init, int use_net, LevelLog *log) {
+__global__ __launch_bounds__(64) void k_select(SelDevice sd, RingSlot *ring, int k, int n, int nnz, int init,
+                                               int use_net, LevelLog *log) {
   __shared__ __align__(16) char smem[SM_SELECT];
-  body_select(sd, ring, k, n, nnz, gsum, init, use_net, log, smem);
+  __shared__ int4 s_wt[SEL_W16];
+  body_select(sd, ring, k, n, nnz, init, use_net, log, smem, s_wt);
+}
+
+// The per-level counter reduction (body_finish) followed, in the same
+// workgroup, by the choice for the next level: one launch per level instead
+// of two.
+// of two.  With `host` (pinned host memory) the level's totals, decision
+// included, are also written there for the host loop to read after its sync.
+__global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl,
+                                                       SelDevice sd, RingSlot *ring, int n, int nnz, int use_net,
+                                                       LevelCtr *host) {
+  __shared__ __align__(16) char smem[SM_FINISH + SM_SELECT];
+  __shared__ int4 s_wt[SEL_W16];
+  body_finish(slot, qcap, k, log, ctl, smem);
+  __syncthreads();
+  __threadfence_block();
+  if (threadIdx.x < WAVE) body_select(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH, s_wt);
+  if (threadIdx.x == 0 && host) *host = slot->tot;  // lane 0 wrote the decision above
+}
+
+hipError_t launch_finish_select(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl, const SelDevice &sd,
+                                RingSlot *ring, int n, int nnz, bool use_net, LevelCtr *host, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_select, dim3(1), dim3(NSH), 0, s, slot, qcap, k, log, ctl, sd, ring, n, nnz,
+                     (use_net && sd.use_net) ? 1 : 0, host);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------ selector set
@@ -62,12 +88,13 @@ SelDevice selector_device(const Workspace &w, int push_v, int pull_v) {
   d.state = w.gsum + 2;
   d.push_v = push_v;
   d.pull_v = pull_v;
+  d.gld = d.gld2 = 0;
   return d;
 }
 
-hipError_t launch_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, const u64 *gsum,
-                         hipStream_t s, bool init, bool use_net, LevelLog *log) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, sd, ring, k, n, nnz, gsum, init ? 1 : 0,
+hipError_t launch_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, hipStream_t s, bool init,
+                         bool use_net, LevelLog *log) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, sd, ring, k, n, nnz, init ? 1 : 0,
                      (use_net && sd.use_net) ? 1 : 0, log);
   return hipGetLastError();
 }

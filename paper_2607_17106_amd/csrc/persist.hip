@@ -109,7 +109,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs P) {
     __syncthreads();
     __threadfence();
     if (P.decide && threadIdx.x < WAVE)
-      body_select(P.sd, P.ring, 0, a.n, P.nnz, P.gsum, 1, P.use_net, P.log, smem);
+      body_select(P.sd, P.ring, 0, a.n, P.nnz, 1, P.use_net, P.log, smem);
   }
   if (!grid_sync(P.bar, epoch)) return;
   for (int k = 0;; ++k) {
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs P) {
         __syncthreads();
         __threadfence();
         if (threadIdx.x < WAVE)
-          body_select(P.sd, P.ring, k + 1, a.n, P.nnz, P.gsum, 0, P.use_net, P.log, smem + SM_FINISH);
+          body_select(P.sd, P.ring, k + 1, a.n, P.nnz, 0, P.use_net, P.log, smem + SM_FINISH);
       }
     }
     if (!grid_sync(P.bar, epoch)) break;

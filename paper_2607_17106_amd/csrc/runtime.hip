@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -173,6 +174,18 @@ static hipError_t launch_finish_f0(const Workspace &w, hipStream_t s) {
   return launch_log_f0(w.ring, w.log, w.ctl, s);
 }
 
+// Graph-wide sums of floor(log2(1 + outdeg)) and of its square (selector
+// features): computed over all vertices and read back (one stream sync).
+static int graph_ld_sums(const bfs_graph *g, const Workspace &w, hipStream_t s, u64 *ld, u64 *ld2) {
+  HostCtx &hc = host_ctx();
+  BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
+  BFS_HIP(hipMemcpyAsync(hc.pinned_u64, w.gsum, 16, hipMemcpyDeviceToHost, s));
+  BFS_HIP(hipStreamSynchronize(s));
+  *ld = hc.pinned_u64[0];
+  *ld2 = hc.pinned_u64[1];
+  return BFS_OK;
+}
+
 // Degree above which the block-mapped and bitmap pushes defer a frontier
 // vertex to the grid-wide hub pass.  Those pushes give each workgroup up to
 // BLOCK frontier vertices, so with a small frontier the lists of a whole level
@@ -315,9 +328,20 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   BFS_HIP(hipEventRecord(hc.ev[0], s));
   BFS_HIP(hipMemsetAsync(w.ctl, 0, sizeof(LoopCtl), s));
   const bool graph_sums = learned || want_levels;
-  if (graph_sums) BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
+  u64 gld = 0, gld2 = 0;
+  if (graph_sums) {
+    if (opt->flags & BFS_F_GRAPH_SUMS) {
+      gld = (u64)opt->graph_ld;
+      gld2 = (u64)opt->graph_ld2;
+    } else {
+      rc = graph_ld_sums(g, w, s, &gld, &gld2);
+      if (rc) return rc;
+    }
+  }
   StepArgs a = level_args(g, w, levels, parents, 0, DEFAULT_HUB);
   SelDevice seldev = selector_device(w, push_v, pull_v);
+  seldev.gld = gld;
+  seldev.gld2 = gld2;
   bool persistent = device_loop;
   if (persistent) {
     PersistArgs P;
@@ -358,7 +382,7 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   if (!persistent) {
     BFS_HIP(launch_reset(a, src, w.ring, s));
     BFS_HIP(launch_finish_f0(w, s));
-    if (device_decides) BFS_HIP(launch_select(seldev, w.ring, 0, g->n, g->nnz, w.gsum, s, true, learned, w.log));
+    if (device_decides) BFS_HIP(launch_select(seldev, w.ring, 0, g->n, g->nnz, s, true, learned, w.log));
   }
 
   int syncs = 0;
@@ -381,10 +405,13 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
       if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
       BFS_HIP(launch_step(v, a, (int)cnt, eF, s));
       if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));
-      BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, s));
-      if (device_decides)
-        BFS_HIP(launch_select(seldev, w.ring, k + 1, g->n, g->nnz, w.gsum, s, false, learned, w.log));
-      BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[(k + 1) % RING].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+      if (device_decides) {
+        BFS_HIP(launch_finish_select(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, seldev, w.ring, g->n,
+                                     g->nnz, learned, hc.pinned, s));
+      } else {
+        BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, s));
+        BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[(k + 1) % RING].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+      }
       BFS_HIP(hipStreamSynchronize(s));
       ++syncs;
       if (timing) {
@@ -427,9 +454,11 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
           BFS_HIP(launch_step(v, a, -1, -1, s));
         }
         if (timing) BFS_HIP(hipEventRecord(evs[2 * i + 1], s));
-        BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, s));
         if (device_decides)
-          BFS_HIP(launch_select(seldev, w.ring, k + 1, g->n, g->nnz, w.gsum, s, false, learned, w.log));
+          BFS_HIP(launch_finish_select(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, seldev, w.ring, g->n,
+                                       g->nnz, learned, nullptr, s));
+        else
+          BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, s));
       }
       BFS_HIP(hipMemcpyAsync(hc.pinned_u64, w.ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
       BFS_HIP(hipStreamSynchronize(s));
@@ -487,9 +516,8 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   st->host_syncs = syncs;
   st->fell_back = fell_back_all;
   if (graph_sums) {
-    BFS_HIP(hipMemcpy(hc.pinned_u64, w.gsum, 16, hipMemcpyDeviceToHost));
-    st->graph_ld = (int64_t)hc.pinned_u64[0];
-    st->graph_ld2 = (int64_t)hc.pinned_u64[1];
+    st->graph_ld = (int64_t)gld;
+    st->graph_ld2 = (int64_t)gld2;
   }
   // per-level statistics from the device log (entry k+1 also carries the
   // scan length of the step that expanded F_k)
@@ -618,6 +646,30 @@ int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *pa
     return BFS_EINVAL;
   }
   return run_single(g, source, levels, parents, opt, st, (hipStream_t)stream);
+}
+
+int bfs_graph_sums(const bfs_graph *g, int64_t *ld, int64_t *ld2, void *stream) {
+  if (!g || g->n <= 0 || !g->row_ptr || !ld || !ld2) {
+    set_error("bfs_graph_sums: invalid argument");
+    return BFS_EINVAL;
+  }
+  static std::mutex mu;
+  static u64 *buf[64] = {nullptr};
+  int dev = 0;
+  BFS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) dev = 0;
+  Workspace w{};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!buf[dev]) BFS_HIP(hipMalloc((void **)&buf[dev], GSUM_WORDS * 8));
+    w.gsum = buf[dev];
+  }
+  u64 a = 0, b = 0;
+  const int rc = graph_ld_sums(g, w, (hipStream_t)stream, &a, &b);
+  if (rc) return rc;
+  *ld = (int64_t)a;
+  *ld2 = (int64_t)b;
+  return BFS_OK;
 }
 
 int bfs_step_time(const bfs_graph *g, const int32_t *depths, int32_t k, int32_t variant, int32_t reps,

@@ -51,13 +51,17 @@ struct SelDevice {
   u64 *state;            // nU, eU, dir, prev_nf (per workspace)
   int push_v, pull_v;
   bool use_net;          // weights present
+  u64 gld, gld2;         // graph-wide sums of floor(log2(1 + outdeg)) and its square
 };
 
 bool selector_loaded();
 SelDevice selector_device(const Workspace &w, int push_v, int pull_v);
 // Decides the variant for level k (after F_k's counters are final): the
 // network when use_net and weights are loaded, else the direction rule.
-hipError_t launch_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, const u64 *gsum,
-                         hipStream_t s, bool init, bool use_net, LevelLog *log);
+hipError_t launch_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, hipStream_t s, bool init,
+                         bool use_net, LevelLog *log);
+// Level-k counter reduction and the choice for level k in one launch.
+hipError_t launch_finish_select(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl, const SelDevice &sd,
+                                RingSlot *ring, int n, int nnz, bool use_net, LevelCtr *host, hipStream_t s);
 
 }  // namespace bfs

@@ -91,8 +91,12 @@ __device__ inline void argmax_conf(float logit, int *cls, float *conf) {
 // totals, advances the direction rule, evaluates the network on F_k's
 // features and stores the choice in ring[k % RING].decision.
 // Run by one whole wave.  smem: SM_SELECT bytes.
-__device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz,
-                                            const u64 *gsum, int init, int use_net, LevelLog *log, char *smem) {
+// bf16 weights staged in LDS before the forward pass (16-byte copies, all in
+// flight at once), instead of one dependent 2-byte global load per product.
+constexpr int SEL_W16 = (NPARAM * 2 + 15) / 16;  // 16-byte units; the source buffer extends past them
+
+__device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, int init,
+                                            int use_net, LevelLog *log, char *smem, int4 *s_wt = nullptr) {
   float *s_x = reinterpret_cast<float *>(smem), *h0 = s_x + NF, *h1 = h0 + NH, *h2 = h1 + NH;
   int &s_hv = *reinterpret_cast<int *>(h2 + NH);
   LevelCtr *c = &ring[k % RING].tot;
@@ -121,7 +125,7 @@ __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring,
     s_hv = dir ? sd.pull_v : sd.push_v;
     float f[NF];
     level_features((double)n, (double)nnz, (double)k, (double)nF, (double)c->edges, (double)st[0], (double)st[1],
-                   (double)c->ld, (double)c->ld2, (double)gsum[0], (double)gsum[1], f);
+                   (double)c->ld, (double)c->ld2, (double)sd.gld, (double)sd.gld2, f);
     for (int i = 0; i < NF; ++i) s_x[i] = f[i];
   }
   __builtin_amdgcn_wave_barrier();
@@ -148,8 +152,15 @@ __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring,
   __builtin_amdgcn_wave_barrier();
   if (lane() < NF) s_x[lane()] = xn;
   __builtin_amdgcn_wave_barrier();
+  const u16 *w = sd.w;
+  if (s_wt) {
+    const int4 *src = reinterpret_cast<const int4 *>(sd.w);
+    for (int i = lane(); i < SEL_W16; i += WAVE) s_wt[i] = src[i];
+    __builtin_amdgcn_wave_barrier();
+    w = reinterpret_cast<const u16 *>(s_wt);
+  }
   float z1, z2;
-  float logit = forward_row(WBf16{sd.w}, sd.p, s_x, h0, h1, h2, z1, z2);
+  float logit = forward_row(WBf16{w}, sd.p, s_x, h0, h1, h2, z1, z2);
   int cls;
   float conf;
   argmax_conf(logit, &cls, &conf);

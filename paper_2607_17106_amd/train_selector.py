@@ -139,6 +139,7 @@ def main():
     ap.add_argument("--min-conf", type=float, default=0.4)
     ap.add_argument("--quick", action="store_true", help="small graphs only (smoke run)")
     args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
     torch.cuda.set_device(0)
     graphs = TRAIN_GRAPHS if not args.quick else [("rmat", 14, 4014), ("lattice", 256, 4100)]
     Xs, Ts, Hs, metas = [], [], [], []

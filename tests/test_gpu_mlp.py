@@ -153,3 +153,37 @@ def test_level_features_match_reference():
             f = B.level_features(st, g.n, g.nnz)
             ref = features.level_features(g.row_ptr, g.csc_ptr, lv.cpu().numpy())
             np.testing.assert_array_equal(f, ref)
+
+
+def test_graph_sums_and_given_sums_path():
+    """bfs_graph_sums equals the sums written out from the degrees, and a
+    learned search fed those sums (BFS_F_GRAPH_SUMS, what the binding does)
+    chooses exactly as one that computes them itself (raw C call without the
+    flag)."""
+    import ctypes
+    from paper_2607_17106_amd import _lib as L, api
+    g = gg.rmat(15, seed=4015).with_csc()
+    dg = B.DeviceGraph.from_graph(g)
+    ld = np.floor(np.log2(1 + np.diff(g.row_ptr).astype(np.float64))).astype(np.int64)
+    assert dg.graph_sums() == (int(ld.sum()), int((ld * ld).sum()))
+    rng = np.random.default_rng(16)
+    params = mlp.init_params(21)
+    params[mlp.OFF_B3:] = rng.normal(0, 1, 4)
+    wide_min, wide_max = np.full(12, -1e30, np.float32), np.full(12, 1e30, np.float32)
+    classes = [B.PUSH_Q_BLOCK, B.PUSH_Q_MERGE, B.PUSH_B_NOATOMIC, B.PULL_B]
+    try:
+        B.selector_set(params, np.zeros(12, np.float32), np.ones(12, np.float32), wide_min, wide_max, 0.0, classes)
+        for s in gg.pick_sources(g, 3, 17):
+            lv1, st1 = B.bfs_levels(dg, int(s), variant=B.AUTO_LEARNED, level_stats=True)
+            opt, _ = api._options(B.AUTO_LEARNED, L.F_LEVEL_STATS, None, None, 0, None)
+            sb = api._StatsBuf(4096)
+            lv2 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            L.check(L.load().bfs_levels(dg.c, int(s), api._ptr(lv2), ctypes.byref(opt), ctypes.byref(sb.s),
+                                        api._stream(None)), "bfs_levels")
+            st2 = sb.as_dict(True)
+            assert not (opt.flags & L.F_GRAPH_SUMS)
+            np.testing.assert_array_equal(st1["variant"], st2["variant"])
+            np.testing.assert_array_equal(lv1.cpu().numpy(), lv2.cpu().numpy())
+            assert (st1["graph_ld"], st1["graph_ld2"]) == (st2["graph_ld"], st2["graph_ld2"]) == dg.graph_sums()
+    finally:
+        B.selector_clear()
