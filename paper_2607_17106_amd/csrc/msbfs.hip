@@ -58,7 +58,8 @@ struct MsCtr {  // two 64-byte lines per shard
   u64 hits;        // examined edges whose source is in the frontier (words gathered)
   u64 hscanned;    // the part of `scanned` examined by the heavy-vertex kernel
   u64 hhits;       // the part of `hits` gathered by it
-  u64 pad[6];
+  u64 hpend;       // bottom-up: heavy vertices still missing some lane after the step
+  u64 pad[5];
 };
 static_assert(sizeof(MsCtr) == 128, "MsCtr is two lines");
 constexpr int MS_NCTR = 16;
@@ -196,7 +197,7 @@ struct MsStats {
     }
   }
 };
-enum { C_NEW, C_COMP, C_ACTIVE, C_ACTOUT, C_DONEIN, C_SCAN, C_UNVIS, C_HITS, C_HSCAN, C_HHITS };
+enum { C_NEW, C_COMP, C_ACTIVE, C_ACTOUT, C_DONEIN, C_SCAN, C_UNVIS, C_HITS, C_HSCAN, C_HHITS, C_HPEND };
 
 // Workgroup-level flush: one atomic per counter and workgroup.  Every thread
 // of the workgroup must call it.
@@ -263,7 +264,7 @@ __device__ __forceinline__ void ms_store_depths(const MsArgs &a, int v, bool val
       int r = 0;
 #pragma unroll
       for (int b = 0; b < NP; ++b) r |= (int)((pl[h][b] >> l) & 1u) << b;
-      if ((st_h >> l) & 1u) *out = ((vis_h >> l) & 1u) ? a.base + r : -1;
+      if ((st_h >> l) & 1u) __builtin_nontemporal_store(((vis_h >> l) & 1u) ? a.base + r : -1, out);
     }
   }
 }
@@ -506,15 +507,18 @@ __device__ __forceinline__ void ms_multi_scan(const int (&x)[VPT], int (&off)[VP
 // the bitmaps).  A light vertex's own thread first ORs the frontier words of
 // its first MS_HEAD in-edges (bitmap probe first).  The remaining in-edge
 // lists of the vertices that still miss lanes are laid end to end (one scan
-// over all slots) and walked MS_EPT * BLOCK edges per iteration, MS_EPT
-// consecutive ones per thread: the thread finds the vertex of its first edge
-// by binary search over the scanned offsets in LDS and advances linearly, skips
-// the gathers of a vertex that already has all its missing lanes, ORs the
-// gathered words per vertex, and posts them with LDS atomics (the last vertex
-// of each thread through one segmented scan over the wave).  Heavy vertices take the heavy pass's result from accb.  Also
+// over all slots) and walked MS_EPT * BLOCK edges per iteration.  CONSEC
+// (sparse frontiers, one round): MS_EPT consecutive edges per thread; the
+// thread finds the vertex of its first edge by binary search over the scanned
+// offsets in LDS and advances linearly, skips the gathers of a vertex that
+// already has all its missing lanes, ORs the gathered words per vertex, and
+// posts them with LDS atomics (the last vertex of each thread through one
+// segmented scan over the wave).  Otherwise (dense frontiers, capped rounds):
+// edge i * BLOCK + t per position, each with its own owner search and
+// done-check, one segmented scan per position.  Heavy vertices take the heavy pass's result from accb.  Also
 // writes next, the next bitmap and the discoveries, and clears the dead
 // frontier buffer.
-template <int VPT, bool SUM>
+template <int VPT, bool SUM, bool CONSEC>
 __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
   constexpr int TV = VPT * BLOCK;
   extern __shared__ u32 s_sum[];
@@ -531,6 +535,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // uniform per workgroup
     u64 vw[VPT], need[VPT], acc[VPT];
     int len[VPT], b[VPT], d[VPT];
+    bool heavy[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tile * TV + j * BLOCK + t;
@@ -540,6 +545,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       len[j] = 0;
       b[j] = 0;
       d[j] = 0;
+      heavy[j] = false;
     }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
@@ -555,6 +561,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       if (!need[j]) continue;
       const int v = tile * TV + j * BLOCK + t;
       if (d[j] > MS_HEAVY) {
+        heavy[j] = true;
         acc[j] = a.accb[v];
         if (acc[j]) a.accb[v] = 0ull;  // ready for the next bottom-up level
         continue;
@@ -599,74 +606,121 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       }
       if (t == 0) s_off[TV] = total;
       __syncthreads();
-      for (int c0 = 0; c0 < total; c0 += MS_EPT * BLOCK) {  // uniform per workgroup
-        // thread t takes MS_EPT consecutive positions of the laid-out lists:
-        // one binary search for the first owner, then a linear advance
-        const int e0 = c0 + t * MS_EPT;
-        int o = -1, next_off = 0, base_j = 0;
-        bool skip = true;
-        if (e0 < total) {
-          int lo = 0, hi = TV;  // s_off[lo] <= e0 < s_off[hi]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_off[mid] <= e0) lo = mid; else hi = mid;
-          }
-          o = lo;
-          next_off = s_off[o + 1];
-          base_j = s_beg[o] - s_off[o];
-          const u64 nd = s_need[o];
-          skip = (s_acc[o] & nd) == nd;  // lanes already complete: no more gathers for o
-        }
-        int own[MS_EPT], u[MS_EPT];
-#pragma unroll
-        for (int i = 0; i < MS_EPT; ++i) {
-          const int e = e0 + i;
-          own[i] = -1;
-          u[i] = -1;
-          if (o >= 0 && e < total) {
-            while (e >= next_off) {  // next owner with edges left (s_off[TV] = total > e)
-              ++o;
-              next_off = s_off[o + 1];
-              base_j = s_beg[o] - s_off[o];
-              const u64 nd = s_need[o];
-              skip = (s_acc[o] & nd) == nd;
+      if (CONSEC) {
+        for (int c0 = 0; c0 < total; c0 += MS_EPT * BLOCK) {  // uniform per workgroup
+          // thread t takes MS_EPT consecutive positions of the laid-out lists:
+          // one binary search for the first owner, then a linear advance
+          const int e0 = c0 + t * MS_EPT;
+          int o = -1, next_off = 0, base_j = 0;
+          bool skip = true;
+          if (e0 < total) {
+            int lo = 0, hi = TV;  // s_off[lo] <= e0 < s_off[hi]
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if (s_off[mid] <= e0) lo = mid; else hi = mid;
             }
-            own[i] = o;
-            if (!skip) {
-              u[i] = a.cx[base_j + e];
-              st.c[C_SCAN] += 1;
+            o = lo;
+            next_off = s_off[o + 1];
+            base_j = s_beg[o] - s_off[o];
+            const u64 nd = s_need[o];
+            skip = (s_acc[o] & nd) == nd;  // lanes already complete: no more gathers for o
+          }
+          int own[MS_EPT], u[MS_EPT];
+  #pragma unroll
+          for (int i = 0; i < MS_EPT; ++i) {
+            const int e = e0 + i;
+            own[i] = -1;
+            u[i] = -1;
+            if (o >= 0 && e < total) {
+              while (e >= next_off) {  // next owner with edges left (s_off[TV] = total > e)
+                ++o;
+                next_off = s_off[o + 1];
+                base_j = s_beg[o] - s_off[o];
+                const u64 nd = s_need[o];
+                skip = (s_acc[o] & nd) == nd;
+              }
+              own[i] = o;
+              if (!skip) {
+                u[i] = a.cx[base_j + e];
+                st.c[C_SCAN] += 1;
+              }
             }
           }
-        }
-        bool hit[MS_EPT];
-#pragma unroll
-        for (int i = 0; i < MS_EPT; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
-        // OR per owner inside the thread; a segment that ends inside the thread
-        // is posted directly, the thread's last segment goes through one
-        // segmented scan over the wave (equal owners in neighbouring lanes merge)
-        u64 run = 0ull;
-        int ro = own[0];
-#pragma unroll
-        for (int i = 0; i < MS_EPT; ++i) {
-          const u64 f = hit[i] ? a.front[u[i]] : 0ull;
-          st.c[C_HITS] += hit[i] ? 1 : 0;
-          if (own[i] != ro) {
-            if (run) atomicOr(&s_acc[ro], run);
-            run = 0ull;
-            ro = own[i];
+          bool hit[MS_EPT];
+  #pragma unroll
+          for (int i = 0; i < MS_EPT; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
+          // OR per owner inside the thread; a segment that ends inside the thread
+          // is posted directly, the thread's last segment goes through one
+          // segmented scan over the wave (equal owners in neighbouring lanes merge)
+          u64 run = 0ull;
+          int ro = own[0];
+  #pragma unroll
+          for (int i = 0; i < MS_EPT; ++i) {
+            const u64 f = hit[i] ? a.front[u[i]] : 0ull;
+            st.c[C_HITS] += hit[i] ? 1 : 0;
+            if (own[i] != ro) {
+              if (run) atomicOr(&s_acc[ro], run);
+              run = 0ull;
+              ro = own[i];
+            }
+            run |= f;
           }
-          run |= f;
-        }
-        if (__ballot(run != 0ull)) {
-#pragma unroll
-          for (int dd = 1; dd < WAVE; dd <<= 1) {
-            const u64 y = __shfl_up(run, (unsigned)dd);
-            const int oy = __shfl_up(ro, (unsigned)dd);
-            if (lane() >= dd && oy == ro) run |= y;
+          if (__ballot(run != 0ull)) {
+  #pragma unroll
+            for (int dd = 1; dd < WAVE; dd <<= 1) {
+              const u64 y = __shfl_up(run, (unsigned)dd);
+              const int oy = __shfl_up(ro, (unsigned)dd);
+              if (lane() >= dd && oy == ro) run |= y;
+            }
+            const int on = __shfl_down(ro, 1u);
+            const bool tail = lane() == WAVE - 1 || on != ro;
+            if (tail && run) atomicOr(&s_acc[ro], run);
           }
-          const int on = __shfl_down(ro, 1u);
-          const bool tail = lane() == WAVE - 1 || on != ro;
-          if (tail && run) atomicOr(&s_acc[ro], run);
+        }
+      } else {
+        for (int c0 = 0; c0 < total; c0 += MS_EPT * BLOCK) {  // uniform per workgroup
+          // position i * BLOCK + t of the batch: one owner search per edge, the
+          // done-check per edge, one segmented scan per position
+          int own[MS_EPT], u[MS_EPT];
+  #pragma unroll
+          for (int i = 0; i < MS_EPT; ++i) {
+            const int e = c0 + i * BLOCK + t;
+            own[i] = -1;
+            u[i] = -1;
+            if (e < total) {
+              int lo = 0, hi = TV;  // s_off[lo] <= e < s_off[hi]
+              while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[mid] <= e) lo = mid; else hi = mid;
+              }
+              own[i] = lo;
+              const u64 nd = s_need[lo];
+              if ((s_acc[lo] & nd) != nd) {
+                u[i] = a.cx[s_beg[lo] + (e - s_off[lo])];
+                st.c[C_SCAN] += 1;
+              }
+            }
+          }
+          bool hit[MS_EPT];
+  #pragma unroll
+          for (int i = 0; i < MS_EPT; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
+  #pragma unroll
+          for (int i = 0; i < MS_EPT; ++i) {
+            u64 f = hit[i] ? a.front[u[i]] : 0ull;
+            st.c[C_HITS] += hit[i] ? 1 : 0;
+            if (__ballot(f != 0ull)) {
+              const int oi = own[i];
+  #pragma unroll
+              for (int dd = 1; dd < WAVE; dd <<= 1) {
+                const u64 y = __shfl_up(f, (unsigned)dd);
+                const int oy = __shfl_up(oi, (unsigned)dd);
+                if (lane() >= dd && oy == oi) f |= y;
+              }
+              const int on = __shfl_down(oi, 1u);
+              const bool tail = lane() == WAVE - 1 || on != oi;
+              if (tail && f) atomicOr(&s_acc[oi], f);
+            }
+          }
         }
       }
       __syncthreads();
@@ -688,6 +742,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
         nw = acc[j] & need[j];
         a.next[v] = nw;
         if (nw) ms_discover(a, v, vw[j], nw, st);
+        if (heavy[j] && (need[j] & ~nw)) st.c[C_HPEND] += 1;
       }
       const u64 nb = __ballot(nw != 0ull);
       const int w0 = tile * TV + j * BLOCK + (t & ~(WAVE - 1));
@@ -973,6 +1028,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     reached += L;
     int msdir = 0;
     long long prev_nf = -1;
+    bool heavy_done = false;  // after a bottom-up level left no heavy vertex missing a lane
     int lev = 0;
     for (;;) {
       int dir;
@@ -1025,7 +1081,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           hipLaunchKernelGGL(k_ms_summary, dim3(MS_SUM_WORDS / BLOCK), dim3(BLOCK), 0, s, (const u64 *)a.fbits,
                              (n + 63) / 64, W.fsum, a.sshift);
         const size_t lds = sum ? MS_SUM_WORDS * sizeof(u32) : 0;
-        if (a.hchunks > 0) {
+        if (a.hchunks > 0 && !heavy_done) {
           const int gh = std::min(sum ? MS_SUM_GRID : 4096, (a.hchunks + 3) / 4);
           if (sum)
             hipLaunchKernelGGL(k_ms_pull_heavy<true>, dim3(gh), dim3(BLOCK), lds, s, a);
@@ -1035,17 +1091,25 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         // one vertex per thread while many in-edges remain to be scanned (more
         // workgroups in flight); four when few do (fixed costs amortised)
         if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[0], s));
-        if (eu > 2 * (long long)n) {
-          if (sum)
-            hipLaunchKernelGGL((k_ms_pull_tile<1, true>), dim3(std::min(grid_t1, MS_SUM_GRID)), dim3(BLOCK), lds, s, a);
+        const bool rounds = a.cap0 < (1 << 30);  // dense frontier: per-position walk
+        const bool wide = eu > 2 * (long long)n;
+        const dim3 gt(wide ? (sum ? std::min(grid_t1, MS_SUM_GRID) : grid_t1)
+                           : (sum ? std::min(grid_t4, MS_SUM_GRID) : grid_t4));
+        if (sum) {
+          if (wide)
+            hipLaunchKernelGGL((k_ms_pull_tile<1, true, true>), gt, dim3(BLOCK), lds, s, a);
           else
-            hipLaunchKernelGGL((k_ms_pull_tile<1, false>), dim3(grid_t1), dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, true, true>), gt, dim3(BLOCK), lds, s, a);
+        } else if (wide) {
+          if (rounds)
+            hipLaunchKernelGGL((k_ms_pull_tile<1, false, false>), gt, dim3(BLOCK), 0, s, a);
+          else
+            hipLaunchKernelGGL((k_ms_pull_tile<1, false, true>), gt, dim3(BLOCK), 0, s, a);
         } else {
-          if (sum)
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, true>), dim3(std::min(grid_t4, MS_SUM_GRID)), dim3(BLOCK),
-                               lds, s, a);
+          if (rounds)
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false>), gt, dim3(BLOCK), 0, s, a);
           else
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false>), dim3(grid_t4), dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true>), gt, dim3(BLOCK), 0, s, a);
         }
         if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[1], s));
       } else {
@@ -1088,6 +1152,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           st->level_ms[r] = ms;
         }
       }
+      if (dir == 1 && c.hpend == 0) heavy_done = true;  // visited words only grow
       ++lev;
       if (c.newbits == 0) break;
       reached += (long long)c.newbits;
