@@ -73,6 +73,11 @@ int bfs_version(void);
  *                  scans its in-neighbours and stops at the first frontier
  *                  member (Sec. "From Push to Pull BFS": reassociate, commute,
  *                  reassociate, loop order d -> s)
+ *  PULL_VIS        bottom-up with the visited set as the frontier (Table 3,
+ *                  variant 25): an unvisited vertex's reached in-neighbours
+ *                  all lie at the current depth, so the visited bitmap (bits
+ *                  of never-reachable vertices told apart by their depth, -1)
+ *                  serves as the frontier; new bits are merged after the step
  * Every step emits the next frontier both as a queue and as a bitmap, so the
  * format of the next level is a free choice.
  */
@@ -83,7 +88,8 @@ int bfs_version(void);
 #define BFS_V_PUSH_B_NOATOMIC 4
 #define BFS_V_PUSH_Q_NOATOMIC 5
 #define BFS_V_PULL_B 6
-#define BFS_NUM_VARIANTS 7
+#define BFS_V_PULL_VIS 7         /* same depths, parents and scan lengths as BFS_V_PULL_B */
+#define BFS_NUM_VARIANTS 8
 /* Per-level choice modes. */
 #define BFS_AUTO_HEURISTIC 100 /* Beamer direction-optimising rule (alpha 14, beta 24) */
 #define BFS_AUTO_LEARNED 101   /* selector network on device; heuristic fallback */

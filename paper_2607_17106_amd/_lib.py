@@ -26,7 +26,8 @@ PUSH_B_ATOMIC = 3
 PUSH_B_NOATOMIC = 4
 PUSH_Q_NOATOMIC = 5
 PULL_B = 6
-NUM_VARIANTS = 7
+PULL_VIS = 7
+NUM_VARIANTS = 8
 AUTO_HEURISTIC = 100
 AUTO_LEARNED = 101
 SCHEDULE = 102
@@ -34,7 +35,7 @@ SCHEDULE = 102
 VARIANT_NAMES = {
     PUSH_Q_THREAD: "push_q_thread", PUSH_Q_BLOCK: "push_q_block", PUSH_Q_MERGE: "push_q_merge",
     PUSH_B_ATOMIC: "push_b_atomic", PUSH_B_NOATOMIC: "push_b_noatomic",
-    PUSH_Q_NOATOMIC: "push_q_noatomic", PULL_B: "pull_b",
+    PUSH_Q_NOATOMIC: "push_q_noatomic", PULL_B: "pull_b", PULL_VIS: "pull_vis",
     AUTO_HEURISTIC: "heuristic", AUTO_LEARNED: "learned", SCHEDULE: "schedule",
 }
 

@@ -17,6 +17,8 @@ Per variant (p = 4 when parents are written, else 0):
   push, atomic-free (q or b in)   [4nF | n/8] + 8nF + 4eF + eF/8 + (4+p)nN
                                   + update pass: n/8 + 4nU + 2n/8 + 4nN
   pull, bitmap                    n/8 + 8nU + 4scan + scan/8 + 2n/8 + (8+p)nN
+  pull, visited as frontier       n/8 + 8nU + 4scan + scan/8 + n/8 + (8+p)nN
+                                  + merge pass 3n/8
 """
 from __future__ import annotations
 
@@ -38,6 +40,8 @@ def step_bytes(variant: int, n: int, nF: int, eF: int, nU: int, nN: int, scan: i
         return head + 8.0 * nF + 4.0 * eF + eF / 8.0 + (4 + p) * nN + bm + 4.0 * nU + 2 * bm + 4.0 * nN
     if variant == L.PULL_B:
         return bm + 8.0 * nU + 4.0 * scan + scan / 8.0 + 2 * bm + (8 + p) * nN
+    if variant == L.PULL_VIS:  # probes read the visited bitmap; merge pass reads next, updates visited
+        return bm + 8.0 * nU + 4.0 * scan + scan / 8.0 + bm + (8 + p) * nN + 3 * bm
     raise ValueError(variant)
 
 

@@ -160,6 +160,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs A) {
         s_efn = 0ull;
       }
       __syncthreads();
+      u64 my_efn = 0;  // out-edges of the vertices this thread discovers (reduced per wave below)
       if (dir == 0) {
         // ---- top-down over the frontier queue, flattened chunk by chunk
         const int CH = A.chunk;
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs A) {
             if (!(vis[v >> 6] & bit)) win = !(or_wg(vis + (v >> 6), bit) & bit);
             if (win) {
               lv[v] = k + 1;
-              atomicAdd(&s_efn, (unsigned long long)(rp[v + 1] - rp[v]));
+              my_efn += (u64)(rp[v + 1] - rp[v]);
             }
             lds_append(win, v, qn, &s_qn);
           }
@@ -253,11 +254,15 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs A) {
             if (lane() == 0) vis[w] = vw | m;
             if (found) {
               lv[v] = k + 1;
-              atomicAdd(&s_efn, (unsigned long long)(rp[v + 1] - rp[v]));
+              my_efn += (u64)(rp[v + 1] - rp[v]);
             }
             lds_append(found, v, qn, &s_qn);
           }
         }
+      }
+      {
+        const u64 we = wave_sum_u64(my_efn);
+        if (lane() == 0 && we) atomicAdd(&s_efn, (unsigned long long)we);
       }
       __syncthreads();
       nF = s_qn;

@@ -159,8 +159,13 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs P) {
         ok = ok && grid_sync(P.bar, epoch);
         if (ok) body_noatom_update(a);
         break;
+      case BFS_V_PULL_VIS:
+        body_pull<true>(a);
+        ok = grid_sync(P.bar, epoch);
+        if (ok) body_merge_vis(a);
+        break;
       default:  // BFS_V_PULL_B
-        body_pull(a);
+        body_pull<false>(a);
         break;
     }
     if (!ok || !grid_sync(P.bar, epoch)) break;

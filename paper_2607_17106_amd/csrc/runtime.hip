@@ -154,7 +154,7 @@ void HeuristicState::step(long long n, long long nF, long long eF, long long eU)
   prev_nf = nF;
 }
 
-static bool is_pull(int v) { return v == BFS_V_PULL_B; }
+static bool is_pull(int v) { return v == BFS_V_PULL_B || v == BFS_V_PULL_VIS; }
 
 // Device wall-clock rate in kHz (ticks per millisecond).
 static double wall_khz() {

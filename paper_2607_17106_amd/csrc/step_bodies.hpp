@@ -514,7 +514,20 @@ __device__ __forceinline__ void body_noatom_update(const StepArgs &a) {
 // none is in the frontier), i.e. the sequential early-exit scan length.
 constexpr int PULL_T = 4;
 
+// FROM_VIS (Table 3, variant 25: visited as frontier): the
+// in-neighbour test reads the visited set P_k instead of the frontier.  Every
+// member of P_k that is an in-neighbour of a vertex still unvisited after
+// level k is at depth k (one at depth j < k would have reached it at j + 1),
+// so the first visited in-neighbour is the first frontier in-neighbour: same
+// depths, same parents, same scan lengths.  The visited bitmap also holds
+// vertices marked only because they can never be reached (in-degree 0, or
+// unreachable in a restored state); their depth is -1, so a bitmap hit counts
+// only when the depth is set.  P_k must stay fixed during the step, so the
+// new bits go to the next bitmap only and body_merge_vis folds them into the
+// visited bitmap afterwards.
+template <bool FROM_VIS>
 __device__ __forceinline__ void body_pull(const StepArgs &a) {
+  const u64 *front = FROM_VIS ? a.vis : a.fb_cur;
   NewStats st;
   const int wv = threadIdx.x / WAVE;
   const int gw = blockIdx.x * (BLOCK / WAVE) + wv;
@@ -534,11 +547,18 @@ __device__ __forceinline__ void body_pull(const StepArgs &a) {
       for (int t = 0; t < PULL_T; ++t) u[t] = (t < d) ? a.cx[b + t] : -1;
       u64 wd[PULL_T];
 #pragma unroll
-      for (int t = 0; t < PULL_T; ++t) wd[t] = (u[t] >= 0) ? a.fb_cur[u[t] >> 6] : 0ull;
+      for (int t = 0; t < PULL_T; ++t) wd[t] = (u[t] >= 0) ? front[u[t] >> 6] : 0ull;
+      bool hb[PULL_T];
+#pragma unroll
+      for (int t = 0; t < PULL_T; ++t) hb[t] = u[t] >= 0 && ((wd[t] >> (u[t] & 63)) & 1ull);
+      if (FROM_VIS) {
+#pragma unroll
+        for (int t = 0; t < PULL_T; ++t) hb[t] = hb[t] && a.levels[u[t]] >= 0;
+      }
       int pos = -1;
 #pragma unroll
       for (int t = PULL_T - 1; t >= 0; --t)
-        if (u[t] >= 0 && ((wd[t] >> (u[t] & 63)) & 1ull)) pos = t;
+        if (hb[t]) pos = t;
       if (pos >= 0) {
         found = true;
         par = u[0];
@@ -563,7 +583,8 @@ __device__ __forceinline__ void body_pull(const StepArgs &a) {
         bool hit = false;
         if (j < ve) {
           uu = a.cx[j];
-          hit = test_bit(a.fb_cur, uu);
+          hit = test_bit(front, uu);
+          if (FROM_VIS && hit) hit = a.levels[uu] >= 0;
         }
         const u64 hm = __ballot(hit);
         if (hm) {
@@ -581,7 +602,7 @@ __device__ __forceinline__ void body_pull(const StepArgs &a) {
     }
     const u64 m = __ballot(found);
     if (lane() == 0) {
-      if (m) a.vis[w] = vw | m;
+      if (m && !FROM_VIS) a.vis[w] = vw | m;
       a.fb_next[w] = m;
     }
     if (m) {
@@ -594,6 +615,14 @@ __device__ __forceinline__ void body_pull(const StepArgs &a) {
     }
   }
   st.flush(a.sh_next);
+}
+
+// After a visited-as-frontier pull: P_{k+1} = P_k OR F_{k+1}.
+__device__ __forceinline__ void body_merge_vis(const StepArgs &a) {
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < a.W; w += gridDim.x * blockDim.x) {
+    const u64 m = a.fb_next[w];
+    if (m) a.vis[w] |= m;
+  }
 }
 
 }  // namespace bfs

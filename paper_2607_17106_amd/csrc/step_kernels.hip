@@ -114,10 +114,16 @@ __global__ __launch_bounds__(BLOCK) void k_noatom_update(StepArgs a) {
   body_noatom_update(a);
 }
 
+template <bool FROM_VIS>
 __global__ __launch_bounds__(BLOCK) void k_pull(StepArgs a) {
   clear_dead(a);
   if (gated_off(a)) return;
-  body_pull(a);
+  body_pull<FROM_VIS>(a);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_merge_vis(StepArgs a) {
+  if (gated_off(a)) return;
+  body_merge_vis(a);
 }
 
 // --------------------------------------------- state restore from depths
@@ -306,7 +312,11 @@ hipError_t launch_step(int variant, const StepArgs &a, int count, long long edge
       hipLaunchKernelGGL(k_noatom_update, dim3(gw), dim3(BLOCK), 0, s, a);
       break;
     case BFS_V_PULL_B:
-      hipLaunchKernelGGL(k_pull, dim3(std::max(g0, gw)), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL(k_pull<false>, dim3(std::max(g0, gw)), dim3(BLOCK), 0, s, a);
+      break;
+    case BFS_V_PULL_VIS:
+      hipLaunchKernelGGL(k_pull<true>, dim3(std::max(g0, gw)), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL(k_merge_vis, dim3(clampi(cdiv(a.W, BLOCK), 1, GMAX)), dim3(BLOCK), 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;

@@ -193,16 +193,19 @@ def test_error_codes():
     np.testing.assert_array_equal(lv.cpu().numpy(), oracle.bfs(g.row_ptr, g.col_idx, int(s))[0])
 
 
-def test_pull_scan_length_and_first_parent():
+@pytest.mark.parametrize("variant", [B.PULL_B, B.PULL_VIS])
+def test_pull_scan_length_and_first_parent(variant):
     """Bottom-up steps examine exactly the sequential early-exit scan length
-    (oracle eScan) and pick the first frontier in-neighbour in CSC order."""
+    (oracle eScan) and pick the first frontier in-neighbour in CSC order; with
+    the visited set as the frontier (every visited in-neighbour of an
+    unvisited vertex lies at the current depth) the result is the same."""
     for g in (gg.workload("rmat14"), gg.directed_random(3000, 40000, seed=12)):
         g.with_csc()
         dg = B.DeviceGraph.from_graph(g)
         (s,) = gg.pick_sources(g, 1, 21)
         ref, _, nl = oracle.bfs(g.row_ptr, g.col_idx, int(s))
         prof = oracle.level_profile(g.row_ptr, g.csc_ptr, g.csc_idx, ref)
-        lv, par, st = _run(dg, g, s, B.PULL_B, level_stats=True)
+        lv, par, st = _run(dg, g, s, variant, level_stats=True)
         np.testing.assert_array_equal(lv, ref)
         np.testing.assert_array_equal(st["scanned"], prof["eScan"])
         for v in np.nonzero(ref > 0)[0][:2000]:
@@ -236,7 +239,7 @@ def test_device_loop_every_variant(variant):
             assert st["num_levels"] == nl == st_h["num_levels"]
             for key in ("variant", "frontier", "frontier_edges", "unvisited", "unvisited_edges", "next"):
                 np.testing.assert_array_equal(st[key], st_h[key], err_msg=key)
-            if variant == B.PULL_B:
+            if variant in (B.PULL_B, B.PULL_VIS):
                 np.testing.assert_array_equal(st["scanned"], st_h["scanned"])
             assert st["host_syncs"] <= 1 + nl // 16 + 1
 
