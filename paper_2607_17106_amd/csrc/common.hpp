@@ -127,10 +127,15 @@ struct HostCtx {
   u64 *pinned_u64 = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t lev_ev[64] = {};  // per-level timing in the device loop (2 per level)
+  u64 seq = 0;                 // last sequence number a kernel posted to `pinned`
   bool ok = false;
   HostCtx();
 };
 HostCtx &host_ctx();
+// Waits until a kernel on stream s has written `seq` to *flag (pinned host
+// memory), polling it; after 2 ms without it, synchronises the stream (which
+// reports a failed kernel) and fails if the value is still missing.
+int wait_posted(const volatile u64 *flag, u64 seq, hipStream_t s);
 // Library-cached device workspace for callers that pass none (one per device).
 int cached_workspace(size_t bytes, void **out);
 

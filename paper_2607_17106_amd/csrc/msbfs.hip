@@ -59,7 +59,8 @@ struct MsCtr {  // two 64-byte lines per shard
   u64 hscanned;    // the part of `scanned` examined by the heavy-vertex kernel
   u64 hhits;       // the part of `hits` gathered by it
   u64 hpend;       // bottom-up: heavy vertices still missing some lane after the step
-  u64 pad[5];
+  u64 pad[4];
+  u64 seq;         // totals only: sequence number written last (host polling)
 };
 static_assert(sizeof(MsCtr) == 128, "MsCtr is two lines");
 constexpr int MS_NCTR = 16;
@@ -87,6 +88,7 @@ struct MsArgs {
   int *levels;          // row l at levels + l * n
   int base, np, nflush; // output passes: window base, planes in use, flushes so far
   int cap0;             // bottom-up: in-edges per pending vertex in the first merged round
+  u64 *zplane;          // plane for the step kernels to zero for the next level, or null
   const u32 *fsum;      // summary of fbits: bit i set if any vertex in [i << sshift, (i+1) << sshift) is
   int sshift;           // in the frontier; MS_SUM_WORDS words, staged in LDS by bottom-up kernels
                         // when the frontier is sparse
@@ -217,10 +219,16 @@ __device__ __forceinline__ void ms_flush_block(MsStats &st, MsCtr *sh) {
   }
 }
 
+// Clears the dead frontier buffer and, when the host asks for it, the depth
+// plane the next level will use for the first time (zeroed here, one level
+// ahead, instead of by a launch on the host's critical path).
 __device__ __forceinline__ void ms_clear_dead(const MsArgs &a) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nthr = gridDim.x * blockDim.x;
-  for (int i = tid; i < a.n; i += nthr) a.dead[i] = 0ull;
+  for (int i = tid; i < a.n; i += nthr) {
+    a.dead[i] = 0ull;
+    if (a.zplane) a.zplane[i] = 0ull;
+  }
 }
 
 // Records the discovery of `nw` lanes at v (owner thread, so the plane
@@ -863,10 +871,11 @@ __global__ __launch_bounds__(BLOCK) void k_ms_out(MsArgs a, int flush) {
   }
 }
 
-// Reduces the NSH counter shards of a level into *tot (pinned host memory,
-// read by the host after the stream sync) and clears each shard after reading
-// it, ready for the next level.
-__global__ __launch_bounds__(NSH) void k_ms_finish(MsCtr *sh, MsCtr *tot) {
+// Reduces the NSH counter shards of a level into *tot (pinned host memory)
+// and clears each shard after reading it, ready for the next level.  One
+// thread writes the totals, then -- after a system-scope fence -- `seq` into
+// the last word, which the host polls instead of waiting for the stream.
+__global__ __launch_bounds__(NSH) void k_ms_finish(MsCtr *sh, MsCtr *tot, u64 seq) {
   __shared__ u64 s_red[MS_NCTR][NSH / WAVE];
   const int t = threadIdx.x;
   u64 *f = reinterpret_cast<u64 *>(sh + t);
@@ -876,10 +885,15 @@ __global__ __launch_bounds__(NSH) void k_ms_finish(MsCtr *sh, MsCtr *tot) {
   }
   for (int j = 0; j < MS_NCTR; ++j) f[j] = 0ull;
   __syncthreads();
-  if (t < MS_NCTR) {
-    u64 r = 0;
-    for (int i = 0; i < NSH / WAVE; ++i) r += s_red[t][i];
-    reinterpret_cast<u64 *>(tot)[t] = r;
+  if (t == 0) {
+    u64 *o = reinterpret_cast<u64 *>(tot);
+    for (int j = 0; j < MS_NCTR - 1; ++j) {
+      u64 r = 0;
+      for (int i = 0; i < NSH / WAVE; ++i) r += s_red[j][i];
+      o[j] = r;
+    }
+    __threadfence_system();
+    o[MS_NCTR - 1] = seq;
   }
 }
 
@@ -1059,8 +1073,15 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         a.np = 0;
       }
       a.rel = lev + 1 - a.base;
-      while ((a.rel >> a.np) != 0) {  // zero each plane on its first use in the window
+      while ((a.rel >> a.np) != 0) {  // a plane not zeroed ahead (window start): zero it now
         hipLaunchKernelGGL(k_ms_fill, dim3(grid_v), dim3(BLOCK), 0, s, a.planes + (size_t)a.np * n, n);
+        ++a.np;
+      }
+      // the next level stores relative depth rel + 1: if that needs a new plane,
+      // this level's step kernels zero it (they clear the dead buffer anyway)
+      a.zplane = nullptr;
+      if (((a.rel + 1) >> a.np) != 0 && a.np < MS_PLANES) {
+        a.zplane = a.planes + (size_t)a.np * n;
         ++a.np;
       }
       a.k = lev;
@@ -1121,9 +1142,12 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
       }
       if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));
-      hipLaunchKernelGGL(k_ms_finish, dim3(1), dim3(NSH), 0, s, sh, reinterpret_cast<MsCtr *>(hc.pinned));
+      MsCtr *tot_host = reinterpret_cast<MsCtr *>(hc.pinned);
+      const u64 seq = ++hc.seq;
+      hipLaunchKernelGGL(k_ms_finish, dim3(1), dim3(NSH), 0, s, sh, tot_host, seq);
       BFS_HIP(hipGetLastError());
-      BFS_HIP(hipStreamSynchronize(s));
+      rc = wait_posted(&tot_host->seq, seq, s);
+      if (rc) return rc;
       ++syncs;
       MsCtr c;
       memcpy(&c, hc.pinned, sizeof(c));

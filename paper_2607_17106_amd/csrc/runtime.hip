@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -77,13 +79,34 @@ Workspace carve_single(void *base, int n) {
 
 // ------------------------------------------------- per-thread host context
 HostCtx::HostCtx() {
-  if (hipHostMalloc((void **)&pinned, 64 * sizeof(LevelCtr), hipHostMallocDefault) != hipSuccess) return;
+  // coherent (fine-grained): a kernel's stores reach the host while it still
+  // runs, so the host can poll the sequence word a level's last kernel posts
+  if (hipHostMalloc((void **)&pinned, 64 * sizeof(LevelCtr), hipHostMallocCoherent) != hipSuccess) return;
   pinned_u64 = reinterpret_cast<u64 *>(pinned + 32);
+  // ev[0] / ev[1] bracket a whole call (the host waits on ev[1]); the others
+  // only time steps, so they skip the system-scope cache writeback and
+  // invalidate a default event performs when it is recorded
   for (int i = 0; i < 4; ++i)
-    if (hipEventCreate(&ev[i]) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&ev[i], i < 2 ? hipEventDefault : hipEventDisableSystemFence) != hipSuccess) return;
   for (int i = 0; i < 64; ++i)
-    if (hipEventCreate(&lev_ev[i]) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&lev_ev[i], hipEventDisableSystemFence) != hipSuccess) return;
   ok = true;
+}
+
+int wait_posted(const volatile u64 *flag, u64 seq, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (unsigned spin = 0; *flag != seq; ++spin) {
+    if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+      BFS_HIP(hipStreamSynchronize(s));
+      if (*flag != seq) {
+        set_error("level totals were not posted by the device");
+        return BFS_EHIP;
+      }
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return BFS_OK;
 }
 
 HostCtx &host_ctx() {
