@@ -29,26 +29,31 @@ __global__ __launch_bounds__(64) void k_select(SelDevice sd, RingSlot *ring, int
 }
 
 // The per-level counter reduction (body_finish) followed, in the same
-// workgroup, by the choice for the next level: one launch per level instead
-// of two.
-// of two.  With `host` (pinned host memory) the level's totals, decision
-// included, are also written there for the host loop to read after its sync.
+// workgroup, by the choice for the next level (when `select`): one launch per
+// level instead of two.  With `host` (pinned host memory) the level's totals,
+// decision included, are also copied there, and then -- after a system-scope
+// fence -- `seq` is written to *host_seq for the host loop to poll.
 __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl,
-                                                       SelDevice sd, RingSlot *ring, int n, int nnz, int use_net,
-                                                       LevelCtr *host) {
+                                                       SelDevice sd, RingSlot *ring, int n, int nnz, int select,
+                                                       int use_net, LevelCtr *host, u64 *host_seq, u64 seq) {
   __shared__ __align__(16) char smem[SM_FINISH + SM_SELECT];
   __shared__ int4 s_wt[SEL_W16];
   body_finish(slot, qcap, k, log, ctl, smem);
   __syncthreads();
   __threadfence_block();
-  if (threadIdx.x < WAVE) body_select(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH, s_wt);
-  if (threadIdx.x == 0 && host) *host = slot->tot;  // lane 0 wrote the decision above
+  if (select && threadIdx.x < WAVE) body_select(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH, s_wt);
+  if (threadIdx.x == 0 && host) {  // lane 0 wrote the decision above
+    *host = slot->tot;
+    __threadfence_system();
+    *host_seq = seq;
+  }
 }
 
 hipError_t launch_finish_select(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl, const SelDevice &sd,
-                                RingSlot *ring, int n, int nnz, bool use_net, LevelCtr *host, hipStream_t s) {
+                                RingSlot *ring, int n, int nnz, bool select, bool use_net, LevelCtr *host,
+                                u64 *host_seq, u64 seq, hipStream_t s) {
   hipLaunchKernelGGL(k_finish_select, dim3(1), dim3(NSH), 0, s, slot, qcap, k, log, ctl, sd, ring, n, nnz,
-                     (use_net && sd.use_net) ? 1 : 0, host);
+                     select ? 1 : 0, (use_net && sd.use_net) ? 1 : 0, host, host_seq, seq);
   return hipGetLastError();
 }
 

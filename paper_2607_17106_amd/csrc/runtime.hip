@@ -428,14 +428,14 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
       if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
       BFS_HIP(launch_step(v, a, (int)cnt, eF, s));
       if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));
-      if (device_decides) {
+      {
+        u64 *seq_word = hc.pinned_u64 + 255;
+        const u64 seq = ++hc.seq;
         BFS_HIP(launch_finish_select(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, seldev, w.ring, g->n,
-                                     g->nnz, learned, hc.pinned, s));
-      } else {
-        BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, s));
-        BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[(k + 1) % RING].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
+                                     g->nnz, device_decides, learned, hc.pinned, seq_word, seq, s));
+        rc = wait_posted(seq_word, seq, s);
+        if (rc) return rc;
       }
-      BFS_HIP(hipStreamSynchronize(s));
       ++syncs;
       if (timing) {
         float ms = 0.f;
@@ -477,11 +477,8 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
           BFS_HIP(launch_step(v, a, -1, -1, s));
         }
         if (timing) BFS_HIP(hipEventRecord(evs[2 * i + 1], s));
-        if (device_decides)
-          BFS_HIP(launch_finish_select(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, seldev, w.ring, g->n,
-                                       g->nnz, learned, nullptr, s));
-        else
-          BFS_HIP(launch_finish(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, s));
+        BFS_HIP(launch_finish_select(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, seldev, w.ring, g->n,
+                                     g->nnz, device_decides, learned, nullptr, nullptr, 0, s));
       }
       BFS_HIP(hipMemcpyAsync(hc.pinned_u64, w.ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
       BFS_HIP(hipStreamSynchronize(s));
