@@ -130,6 +130,11 @@ typedef struct bfs_options {
   void *workspace;               /* device scratch, or NULL for a library-cached buffer */
   size_t workspace_bytes;
   int64_t graph_ld, graph_ld2;   /* with BFS_F_GRAPH_SUMS: the values bfs_graph_sums returned */
+  const int32_t *vertex_map;     /* device [n] or NULL.  Set: the graph is a renumbered copy
+                                    (bfs_reorder_degree) and vertex_map[v] is the new id of
+                                    original vertex v (its new_of_old); sources and depths are
+                                    then in the original numbering.  bfs_multi only: the other
+                                    calls return BFS_ENOTSUP when it is set */
 } bfs_options;
 
 typedef struct bfs_stats {
@@ -169,6 +174,25 @@ typedef struct bfs_stats {
  * BFS_F_GRAPH_SUMS.  ld, ld2: host outputs.  Synchronises the stream. */
 int bfs_graph_sums(const bfs_graph *g, int64_t *ld, int64_t *ld2, void *stream);
 
+/* Renumbers the vertices by decreasing out-degree, ties by increasing id: a
+ * preprocessing step (the paper renumbers every graph before timing, with
+ * reverse Cuthill-McKee; Sec. "Experiment Setup").  New id i is the vertex
+ * with the i-th largest out-degree, so the frontier words that bottom-up
+ * steps read most often share few cache lines, and each ascending in-edge
+ * list starts with its most connected in-neighbours (earlier exits).
+ * Outputs, device, caller-allocated: out_row_ptr [n+1] and out_col_idx [nnz]
+ * hold the renumbered CSR (edge (u, v) becomes (new u, new v)), rows
+ * ascending; for a graph with its own CSC (csc_ptr set and != row_ptr)
+ * out_csc_ptr [n+1] and out_csc_idx [nnz] hold the renumbered CSC (else they
+ * are ignored: the result is symmetric too and its CSR serves as CSC);
+ * new_of_old [n] and old_of_new [n] are the two directions of the map.
+ * Validates the graph first (BFS_EGRAPH if malformed).  Allocates about
+ * 16 * max(n, nnz) bytes of temporary device memory and synchronises the
+ * stream. */
+int bfs_reorder_degree(const bfs_graph *g, int32_t *out_row_ptr, int32_t *out_col_idx,
+                       int32_t *out_csc_ptr, int32_t *out_csc_idx, int32_t *new_of_old,
+                       int32_t *old_of_new, void *stream);
+
 /* Workspace bytes for a graph of n vertices.  lanes = 1 for bfs_levels /
  * bfs_parents, 2..64 for bfs_multi (bit-packed lanes, u64 words per vertex). */
 int bfs_workspace_size(int32_t n, int32_t lanes, size_t *bytes);
@@ -205,7 +229,11 @@ int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *pa
  * level_frontier_ld = vertices with a lane found; level_frontier_ld2 = examined
  * edges whose source vertex is in the frontier (frontier words gathered);
  * level_ms = step time.  Depths are written to `levels` once, by an output
- * pass after each group's last level (and by a flush pass every 255 levels). */
+ * pass after each group's last level (and by a flush pass every 255 levels).
+ * With options.vertex_map (a graph from bfs_reorder_degree), sources_host
+ * and the columns of `levels` are original vertex ids: the sources are
+ * mapped on the device and the output pass reads each original vertex's
+ * state at its new id. */
 int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_t *levels,
               const bfs_options *opt, bfs_stats *st, void *stream);
 

@@ -13,5 +13,5 @@ from ._lib import (  # noqa: F401
 from .api import (  # noqa: F401
     DeviceGraph, DeviceBatch, bfs_levels, bfs_parents, bfs_multi, bfs_batch, bfs_batch_autotune,
     workspace_size, selector_set, selector_clear, selector_loaded, mlp_forward, mlp_loss_grad, mlp_adam,
-    mlp_predict, level_features, step_time,
+    mlp_predict, level_features, step_time, reorder_degree,
 )

@@ -60,7 +60,7 @@ class BfsOptions(ctypes.Structure):
     _fields_ = [("variant", c_int32), ("flags", c_int32), ("schedule_host", POINTER(c_int32)),
                 ("schedule_len", c_int32), ("max_levels", c_int32), ("heuristic_push", c_int32),
                 ("heuristic_pull", c_int32), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
-                ("graph_ld", c_int64), ("graph_ld2", c_int64)]
+                ("graph_ld", c_int64), ("graph_ld2", c_int64), ("vertex_map", c_void_p)]
 
 
 class BfsStats(ctypes.Structure):
@@ -93,6 +93,7 @@ SIGNATURES = {
     "bfs_last_error": (ctypes.c_char_p, []),
     "bfs_version": (c_int32, []),
     "bfs_workspace_size": (c_int32, [c_int32, c_int32, POINTER(c_size_t)]),
+    "bfs_reorder_degree": (c_int32, [POINTER(BfsGraph)] + [c_void_p] * 7),
     "bfs_graph_sums": (c_int32, [POINTER(BfsGraph), POINTER(c_int64), POINTER(c_int64), c_void_p]),
     "bfs_levels": (c_int32, [POINTER(BfsGraph), c_int32, c_void_p, POINTER(BfsOptions), POINTER(BfsStats),
                              c_void_p]),

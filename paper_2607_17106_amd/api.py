@@ -75,6 +75,28 @@ class DeviceGraph:
         return self._gsums
 
 
+def reorder_degree(g: DeviceGraph, stream=None):
+    """bfs_reorder_degree: the graph renumbered by decreasing out-degree.
+    Returns (renumbered DeviceGraph, new_of_old, old_of_new), the maps as
+    device int32 tensors; pass new_of_old as bfs_multi's vertex_map."""
+    dev = g.row_ptr.device
+    i32 = dict(dtype=torch.int32, device=dev)
+    rp, ci = torch.empty(g.n + 1, **i32), torch.empty(max(g.nnz, 1), **i32)
+    own_csc = g.csc_ptr is not None and not g.symmetric
+    cp = torch.empty(g.n + 1, **i32) if own_csc else None
+    cx = torch.empty(max(g.nnz, 1), **i32) if own_csc else None
+    new_of_old, old_of_new = torch.empty(g.n, **i32), torch.empty(g.n, **i32)
+    rc = L.load().bfs_reorder_degree(g.c, _ptr(rp), _ptr(ci), _ptr(cp), _ptr(cx), _ptr(new_of_old),
+                                     _ptr(old_of_new), _stream(stream))
+    L.check(rc, "bfs_reorder_degree")
+    ci = ci[:g.nnz]
+    if own_csc:
+        out = DeviceGraph(g.n, rp, ci, cp, cx[:g.nnz], symmetric=False, device=dev)
+    else:
+        out = DeviceGraph(g.n, rp, ci, symmetric=g.symmetric, device=dev)
+    return out, new_of_old, old_of_new
+
+
 def workspace_size(n: int, lanes: int = 1) -> int:
     b = ctypes.c_size_t(0)
     L.check(L.load().bfs_workspace_size(n, lanes, ctypes.byref(b)), "bfs_workspace_size")
@@ -200,8 +222,11 @@ def bfs_parents(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, fl
 
 
 def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: int = 0, workspace=None,
-              levels=None, stream=None, level_stats: bool = False, stats_capacity: int = 1 << 14):
-    """Depths [k][n] from k sources in 64-lane bit-packed groups."""
+              levels=None, stream=None, level_stats: bool = False, stats_capacity: int = 1 << 14,
+              vertex_map=None):
+    """Depths [k][n] from k sources in 64-lane bit-packed groups.  vertex_map:
+    the new_of_old of reorder_degree when g is the renumbered graph (sources
+    and depth columns then use the original ids)."""
     lib = L.load()
     src = np.ascontiguousarray(sources, dtype=np.int32)
     k = int(src.size)
@@ -213,6 +238,10 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
         flags |= L.F_LEVEL_STATS
     sb = _StatsBuf(stats_capacity if level_stats else 0)
     opt, keep = _options(variant, flags, None, workspace, 0, None)
+    if vertex_map is not None:
+        if vertex_map.dtype != torch.int32 or vertex_map.numel() != g.n or not vertex_map.is_contiguous():
+            raise ValueError("vertex_map must be a contiguous int32 tensor of n entries")
+        opt.vertex_map = vertex_map.data_ptr()
     rc = lib.bfs_multi(g.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k, _ptr(levels),
                        ctypes.byref(opt), ctypes.byref(sb.s), _stream(stream))
     L.check(rc, "bfs_multi")

@@ -306,6 +306,8 @@ hipError_t launch_finish(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl
 hipError_t launch_state_from_depths(const StepArgs &a, const int *depths, RingSlot *ring, hipStream_t s);
 hipError_t launch_graph_ld(int n, const int *rp, u64 *gsum, hipStream_t s);
 hipError_t launch_validate(int n, int nnz, const int *ptr, const int *idx, u64 *flag, hipStream_t s);
+// Checks offsets and ids of the CSR (and CSC); BFS_EGRAPH if malformed.  Synchronises.
+int validate_graph(const bfs_graph *g, u64 *flag_dev, hipStream_t s);
 int min_first_grid(int W);
 
 }  // namespace bfs

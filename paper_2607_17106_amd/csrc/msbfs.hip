@@ -45,6 +45,17 @@ constexpr int MS_CAP0 = 32;        // in-edges per pending vertex in the first m
 constexpr int MS_HB = 1024;        // vertices per workgroup in the heavy-list build
 constexpr int MS_SUM_WORDS = 8192; // frontier summary: 2^18 bits = 32 KB of LDS
 constexpr int MS_SUM_GRID = 1024;  // persistent workgroups of the summary-filtered bottom-up kernels
+// Bottom-up tiles: runs of whole 64-vertex chunks.  A chunk weighs the larger
+// of MS_TALPHA per vertex and the in-degrees of its light (not heavy-listed)
+// vertices, and tile t takes the chunks whose running weight starts in
+// [t, t + 1) * MS_TWEIGHT: BLOCK vertices where in-degrees are low, fewer
+// where they are high (a graph ordered by degree puts those together), so no
+// tile walks many more in-edges than MS_TWEIGHT + 64 * MS_HEAVY.
+constexpr int MS_TALPHA = 64;
+constexpr long long MS_TWEIGHT = (long long)BLOCK * MS_TALPHA;
+// tiles for n vertices and any int32 edge count (a chunk weighs at most
+// 64 * MS_TALPHA plus its in-edges)
+constexpr long long ms_tile_cap(long long n) { return n / BLOCK + (1ll << 31) / MS_TWEIGHT + 4; }
 static_assert(MS_HCHUNK <= MS_HEAVY, "a heavy list is longer than one chunk");
 
 struct MsCtr {  // two 64-byte lines per shard
@@ -86,9 +97,12 @@ struct MsArgs {
   const int *opre;
   int ocount, ochunks;
   int *levels;          // row l at levels + l * n
+  const int *vmap;      // or null: column v of `levels` is vertex vmap[v] of the (renumbered) graph
   int base, np, nflush; // output passes: window base, planes in use, flushes so far
   int cap0;             // bottom-up: in-edges per pending vertex in the first merged round
   u64 *zplane;          // plane for the step kernels to zero for the next level, or null
+  const int *tstart;    // bottom-up tile t covers vertices [tstart[t], tstart[t + 1])
+  int ntiles;
   const u32 *fsum;      // summary of fbits: bit i set if any vertex in [i << sshift, (i+1) << sshift) is
   int sshift;           // in the frontier; MS_SUM_WORDS words, staged in LDS by bottom-up kernels
                         // when the frontier is sparse
@@ -98,7 +112,8 @@ struct MsArgs {
 struct MsCarve {
   u64 *fr[3], *vis, *flushed, *accb, *planes, *fb[2];
   u32 *fsum;
-  int *hv, *hpre, *ov, *opre, *bcnt, *bchk;
+  int *hv, *hpre, *ov, *opre, *bcnt, *bchk, *tstart;
+  long long *bwt;       // per heavy-list block: tile weight of its chunks, then their exclusive prefix
   MsCtr *sh, *tot;
   int *src;             // [64] sources of the group, [64] their degrees, [2] heavy totals
   size_t bytes;
@@ -129,6 +144,10 @@ static MsCarve ms_carve(uintptr_t p, int n) {
   off += nb;
   c.bchk = reinterpret_cast<int *>(p + off);
   off += nb;
+  c.tstart = reinterpret_cast<int *>(p + off);
+  off += al((size_t)ms_tile_cap(n) * 4);
+  c.bwt = reinterpret_cast<long long *>(p + off);
+  off += al(((size_t)n / MS_HB + 2) * 8);
   c.planes = reinterpret_cast<u64 *>(p + off);
   off += al((size_t)MS_PLANES * n * 8);
   for (int i = 0; i < 2; ++i, off += bb) c.fb[i] = reinterpret_cast<u64 *>(p + off);
@@ -254,11 +273,11 @@ __device__ __forceinline__ void ms_discover(const MsArgs &a, int v, u64 vis_old,
 // planes are split into 32-bit halves so one bit-field extract per plane
 // gives a lane's bit.
 template <int NP>
-__device__ __forceinline__ void ms_store_depths(const MsArgs &a, int v, bool valid, u64 vw, u64 skip) {
+__device__ __forceinline__ void ms_store_depths(const MsArgs &a, int v, int m, bool valid, u64 vw, u64 skip) {
   uint32_t pl[2][NP];
 #pragma unroll
   for (int b = 0; b < NP; ++b) {
-    const u64 w = valid ? a.planes[(size_t)b * a.n + v] : 0ull;
+    const u64 w = (valid && vw) ? a.planes[(size_t)b * a.n + m] : 0ull;
     pl[0][b] = (uint32_t)w;
     pl[1][b] = (uint32_t)(w >> 32);
   }
@@ -280,15 +299,16 @@ __device__ __forceinline__ void ms_store_depths(const MsArgs &a, int v, bool val
 template <int NP>
 __device__ __forceinline__ void ms_out_body(const MsArgs &a, int flush) {
   for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {  // uniform per wave
-    const int v = base + threadIdx.x;
+    const int v = base + threadIdx.x;  // output column; flushed is indexed by it too
     const bool valid = v < a.n;
-    const u64 vw = valid ? a.vis[v] & a.full : 0ull;
+    const int m = valid && a.vmap ? a.vmap[v] : v;
+    const u64 vw = valid ? a.vis[m] & a.full : 0ull;
     const u64 fl = (valid && a.nflush) ? a.flushed[v] : 0ull;
     if (flush) {
-      ms_store_depths<NP>(a, v, valid, vw, ~(vw & ~fl));
+      ms_store_depths<NP>(a, v, m, valid, vw, ~(vw & ~fl));
       if (valid) a.flushed[v] = vw;
     } else {
-      ms_store_depths<NP>(a, v, valid, vw, fl);
+      ms_store_depths<NP>(a, v, m, valid, vw, fl);
     }
   }
 }
@@ -306,6 +326,11 @@ __global__ __launch_bounds__(BLOCK) void k_ms_init(MsArgs a, u64 *f0, u64 *f1, u
 
 // One thread per lane: sets the source bit (duplicates OR); depth 0 is
 // relative depth 0, which the zeroed planes already hold.
+// Sources given in the original numbering become ids of the renumbered graph.
+__global__ void k_ms_map_sources(int *src, int L, const int *vmap) {
+  if ((int)threadIdx.x < L) src[threadIdx.x] = vmap[src[threadIdx.x]];
+}
+
 __global__ void k_ms_sources(MsArgs a, const int *src, u64 *f0, u64 *b0) {
   const int l = threadIdx.x;
   if (l < a.L) {
@@ -329,28 +354,77 @@ __device__ __forceinline__ int ms_heavy_chunks(const int *cp, int v) {
   return d > MS_HEAVY ? (d + MS_HCHUNK - 1) / MS_HCHUNK : 0;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, int *bcnt, int *bchk) {
+// Tile weight of the 64-vertex chunk this wave covers (vertices v0 .. v0 + 63,
+// those below n; see MS_TALPHA), the same value in every lane.
+__device__ __forceinline__ long long ms_chunk_weight(const int *cp, int v0, int n) {
+  const int v = v0 + lane();
+  const int d = v < n ? cp[v + 1] - cp[v] : 0;
+  const u64 light = wave_sum_u64(d <= MS_HEAVY ? (u64)d : 0ull);
+  const long long floor_w = (long long)min(n - v0, WAVE) * MS_TALPHA;
+  return max(floor_w, (long long)light);
+}
+
+__device__ __forceinline__ long long block_excl_scan_ll(long long x, long long *total, long long *s_w) {
+  const int w = threadIdx.x / WAVE;
+  long long incl = x;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const long long y = __shfl_up(incl, (unsigned)o);
+    if (lane() >= o) incl += y;
+  }
+  if (lane() == WAVE - 1) s_w[w] = incl;
+  __syncthreads();
+  long long off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < BLOCK / WAVE; ++i) {
+    off += (i < w) ? s_w[i] : 0;
+    tot += s_w[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - x;
+}
+
+// Per MS_HB vertices: heavy vertices, their chunks and (bwt given) the tile
+// weight of the 64-vertex chunks.
+__global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, int *bcnt, int *bchk,
+                                                          long long *bwt) {
   __shared__ int s_w[BLOCK / WAVE];
+  __shared__ long long s_wl[BLOCK / WAVE];
   const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
   int c = 0, k = 0;
-  for (int v = v0 + threadIdx.x; v < v1; v += BLOCK) {
-    const int h = ms_heavy_chunks(cp, v);
+  long long wt = 0;
+  for (int vb = v0; vb < v1; vb += BLOCK) {  // uniform per workgroup; wave w covers one chunk
+    const int v = vb + threadIdx.x;
+    const int h = v < v1 ? ms_heavy_chunks(cp, v) : 0;
     c += h ? 1 : 0;
     k += h;
+    const int cw = vb + (threadIdx.x & ~(WAVE - 1));
+    if (bwt && cw < v1) {  // uniform per wave
+      const long long w = ms_chunk_weight(cp, cw, n);
+      if (lane() == 0) wt += w;
+    }
   }
   int tc, tk;
+  long long tw;
   block_excl_scan(c, &tc, s_w);
   block_excl_scan(k, &tk, s_w);
+  block_excl_scan_ll(wt, &tw, s_wl);
   if (threadIdx.x == 0) {
     bcnt[blockIdx.x] = tc;
     bchk[blockIdx.x] = tk;
+    if (bwt) bwt[blockIdx.x] = tw;
   }
 }
 
-// In place: bcnt/bchk become exclusive offsets; tot = {heavy vertices, chunks}.
-__global__ __launch_bounds__(BLOCK) void k_ms_heavy_scan(int nb, int *bcnt, int *bchk, int *tot) {
+// In place: bcnt/bchk (and bwt) become exclusive offsets; tot = {heavy
+// vertices, chunks}, *tiles = bottom-up tiles (total weight / MS_TWEIGHT + 1).
+__global__ __launch_bounds__(BLOCK) void k_ms_heavy_scan(int nb, int *bcnt, int *bchk, int *tot, long long *bwt,
+                                                         int *tiles) {
   __shared__ int s_w[BLOCK / WAVE];
+  __shared__ long long s_wl[BLOCK / WAVE];
   int rc = 0, rk = 0;
+  long long rw = 0;
   for (int base = 0; base < nb; base += BLOCK) {
     const int i = base + threadIdx.x;
     const int c = i < nb ? bcnt[i] : 0, k = i < nb ? bchk[i] : 0;
@@ -363,20 +437,33 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_scan(int nb, int *bcnt, int 
     }
     rc += tc;
     rk += tk;
+    if (bwt) {  // uniform
+      long long tw;
+      const long long ow = block_excl_scan_ll(i < nb ? bwt[i] : 0, &tw, s_wl);
+      if (i < nb) bwt[i] = rw + ow;
+      rw += tw;
+    }
   }
   if (threadIdx.x == 0) {
     tot[0] = rc;
     tot[1] = rk;
+    if (bwt) *tiles = (int)(rw / MS_TWEIGHT) + 1;
   }
 }
 
 // Also clears accb of every heavy vertex (the only entries the pull uses)
 // when accb is given.
+// With bwt: chunk c starting at running weight key writes tstart[t] = its end
+// for each tile t whose first weight t * MS_TWEIGHT lies in (key, key + w_c]
+// (tiles inside one chunk's span are empty); tstart[0] = 0, tstart[tiles] = n.
 __global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, const int *bcnt, const int *bchk,
-                                                          int *hv, int *hpre, u64 *accb, const int *tot) {
+                                                          int *hv, int *hpre, u64 *accb, const int *tot,
+                                                          const long long *bwt, int *tstart, const int *tiles) {
   __shared__ int s_w[BLOCK / WAVE];
+  __shared__ long long s_wl[BLOCK / WAVE];
   const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
   int rc = bcnt[blockIdx.x], rk = bchk[blockIdx.x];
+  long long rw = bwt ? bwt[blockIdx.x] : 0;
   for (int vb = v0; vb < v1; vb += BLOCK) {  // uniform per workgroup
     const int v = vb + threadIdx.x;
     const int h = v < v1 ? ms_heavy_chunks(cp, v) : 0;
@@ -390,8 +477,26 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, 
     }
     rc += tc;
     rk += tk;
+    if (bwt) {  // uniform
+      const int cw = vb + (threadIdx.x & ~(WAVE - 1));
+      const long long w = cw < v1 ? ms_chunk_weight(cp, cw, n) : 0;  // cw < v1 uniform per wave
+      long long tw;
+      const long long ow = block_excl_scan_ll(lane() == 0 ? w : 0, &tw, s_wl);
+      if (lane() == 0 && cw < v1) {
+        const long long key = rw + ow;
+        const int e = min(cw + WAVE, n), last = *tiles - 1;
+        for (long long t = key / MS_TWEIGHT + 1; t <= (key + w) / MS_TWEIGHT && t <= last; ++t) tstart[t] = e;
+      }
+      rw += tw;
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) hpre[tot[0]] = tot[1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hpre[tot[0]] = tot[1];
+    if (bwt) {
+      tstart[0] = 0;
+      tstart[*tiles] = n;
+    }
+  }
 }
 
 // ------------------------------------------------------------------ pull
@@ -539,15 +644,19 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
   ms_stage_summary<SUM>(a, s_sum);
   MsStats st;
   const int t = threadIdx.x;
-  const int ntiles = (a.n + TV - 1) / TV;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // uniform per workgroup
+  const int ngroups = (a.ntiles + VPT - 1) / VPT;
+  for (int tile = blockIdx.x; tile < ngroups; tile += gridDim.x) {  // uniform per workgroup
+    // VPT consecutive tiles: at most TV vertices, the first a multiple of 64
+    const int vb = min(max(a.tstart[tile * VPT], 0), a.n);
+    const int ve = min(min(a.tstart[min(tile * VPT + VPT, a.ntiles)], a.n), vb + TV);
+    if (vb >= ve) continue;
     u64 vw[VPT], need[VPT], acc[VPT];
     int len[VPT], b[VPT], d[VPT];
     bool heavy[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
-      const int v = tile * TV + j * BLOCK + t;
-      vw[j] = v < a.n ? a.vis[v] : ~0ull;
+      const int v = vb + j * BLOCK + t;
+      vw[j] = v < ve ? a.vis[v] : ~0ull;
       need[j] = a.full & ~vw[j];
       acc[j] = 0ull;
       len[j] = 0;
@@ -558,7 +667,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       if (need[j]) {
-        const int v = tile * TV + j * BLOCK + t;
+        const int v = vb + j * BLOCK + t;
         st.c[C_UNVIS] += 1;
         b[j] = a.cp[v];
         d[j] = a.cp[v + 1] - b[j];
@@ -567,7 +676,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       if (!need[j]) continue;
-      const int v = tile * TV + j * BLOCK + t;
+      const int v = vb + j * BLOCK + t;
       if (d[j] > MS_HEAVY) {
         heavy[j] = true;
         acc[j] = a.accb[v];
@@ -744,17 +853,17 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
     }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
-      const int v = tile * TV + j * BLOCK + t;
+      const int v = vb + j * BLOCK + t;
       u64 nw = 0ull;
-      if (v < a.n) {
+      if (v < ve) {
         nw = acc[j] & need[j];
         a.next[v] = nw;
         if (nw) ms_discover(a, v, vw[j], nw, st);
         if (heavy[j] && (need[j] & ~nw)) st.c[C_HPEND] += 1;
       }
       const u64 nb = __ballot(nw != 0ull);
-      const int w0 = tile * TV + j * BLOCK + (t & ~(WAVE - 1));
-      if (lane() == 0 && w0 < a.n) a.nbits[w0 / WAVE] = nb;
+      const int w0 = vb + j * BLOCK + (t & ~(WAVE - 1));
+      if (lane() == 0 && w0 < ve) a.nbits[w0 / WAVE] = nb;
     }
   }
   ms_flush_block(st, a.sh);
@@ -916,8 +1025,8 @@ using namespace bfs;
 extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, int32_t *levels,
                          const bfs_options *opt, bfs_stats *st, void *stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (!g || g->n <= 0 || !g->row_ptr || (!g->col_idx && g->nnz > 0) || !sources || !levels || k < 1) {
-    set_error("bfs_multi: invalid argument (null pointer, n <= 0 or k < 1)");
+  if (!g || g->n <= 0 || g->nnz < 0 || !g->row_ptr || (!g->col_idx && g->nnz > 0) || !sources || !levels || k < 1) {
+    set_error("bfs_multi: invalid argument (null pointer, n <= 0, nnz < 0 or k < 1)");
     return BFS_EINVAL;
   }
   if (!g->csc_ptr || !g->csc_idx) {
@@ -950,25 +1059,28 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   HostCtx &hc = host_ctx();
   const int grid_v = std::min(4096, (n + BLOCK - 1) / BLOCK);
   const int grid_w = std::min(4096, ((n + WAVE - 1) / WAVE + 3) / 4);
-  const int grid_t1 = std::min(65536, (n + BLOCK - 1) / BLOCK);
-  const int grid_t4 = std::min(65536, (n + MS_VPT_SPARSE * BLOCK - 1) / (MS_VPT_SPARSE * BLOCK));
   // heavy in-degree vertices and their chunk prefix (read back with the first group's sync)
   const int nbh = (n + MS_HB - 1) / MS_HB;
   int *htot_dev = src_dev + 192;
   int *htot_host = reinterpret_cast<int *>(hc.pinned_u64 + 64);
-  hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk);
-  hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev);
+  // with the bottom-up tiles (their count in htot[4])
+  hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.bwt);
+  hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev, W.bwt,
+                     htot_dev + 4);
   hipLaunchKernelGGL(k_ms_heavy_write, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.hv, W.hpre,
-                     W.accb, htot_dev);
+                     W.accb, htot_dev, (const long long *)W.bwt, W.tstart, (const int *)(htot_dev + 4));
   // the same over out-degrees for the top-down step (a symmetric graph passes one array twice)
   if (g->row_ptr != g->csc_ptr) {
-    hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk);
-    hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev + 2);
+    hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk,
+                       (long long *)nullptr);
+    hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev + 2,
+                       (long long *)nullptr, (int *)nullptr);
     hipLaunchKernelGGL(k_ms_heavy_write, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk, W.ov, W.opre,
-                       (u64 *)nullptr, htot_dev + 2);
+                       (u64 *)nullptr, htot_dev + 2, (const long long *)nullptr, (int *)nullptr,
+                       (const int *)nullptr);
   }
   BFS_HIP(hipGetLastError());
-  BFS_HIP(hipMemcpyAsync(htot_host, htot_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  BFS_HIP(hipMemcpyAsync(htot_host, htot_dev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
   long long reached = 0, comp = 0;
   int max_levels = 0, syncs = 0;
   const int flags = opt ? opt->flags : 0;
@@ -993,10 +1105,12 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.accb = W.accb;
     a.hv = W.hv;
     a.hpre = W.hpre;
+    a.tstart = W.tstart;
     a.fsum = W.fsum;
     a.sshift = 4;
     while (((long long)n >> a.sshift) > (long long)MS_SUM_WORDS * 32) ++a.sshift;
     a.levels = levels + (size_t)g0 * n;
+    a.vmap = opt ? opt->vertex_map : nullptr;
     a.sh = sh;
     a.base = 0;
     a.np = 0;
@@ -1004,6 +1118,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     hipLaunchKernelGGL(k_ms_init, dim3(grid_v), dim3(BLOCK), 0, s, a, fr[0], fr[1], W.fb[0]);
     hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(BLOCK), 0, s, sh);  // k_ms_finish keeps them clear afterwards
     BFS_HIP(hipMemcpyAsync(src_dev, sources + g0, L * sizeof(int), hipMemcpyHostToDevice, s));
+    if (a.vmap) hipLaunchKernelGGL(k_ms_map_sources, dim3(1), dim3(64), 0, s, src_dev, L, a.vmap);
     hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, s, a, (const int *)src_dev, fr[0], W.fb[0]);
     // counts of F_0 for the direction rule: distinct source vertices and their degrees
     hipLaunchKernelGGL(k_ms_src_deg, dim3(1), dim3(64), 0, s, g->row_ptr, (const int *)src_dev, L, src_dev + 64);
@@ -1013,6 +1128,9 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     BFS_HIP(hipStreamSynchronize(s));
     a.hcount = htot_host[0];
     a.hchunks = htot_host[1];
+    a.ntiles = htot_host[4];
+    const int grid_t1 = std::min(65536, a.ntiles);
+    const int grid_t4 = std::min(65536, (a.ntiles + MS_VPT_SPARSE - 1) / MS_VPT_SPARSE);
     if (g->row_ptr != g->csc_ptr) {
       a.ov = W.ov;
       a.opre = W.opre;
@@ -1097,14 +1215,17 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         a.cap0 = ef * 4 > eu ? MS_CAP0 : (1 << 30);
         // a sparse frontier is tested against its LDS summary first: most
         // in-neighbours are rejected without touching the bitmap
-        const bool sum = (nf << a.sshift) * 64 < (long long)n;
+        // (the heavy pass, which exits early per chunk, gains from it only
+        // at much lower densities than the tile pass)
+        const bool sum = (nf << a.sshift) * 8 < (long long)n;
+        const bool hsum = (nf << a.sshift) * 64 < (long long)n;
         if (sum)
           hipLaunchKernelGGL(k_ms_summary, dim3(MS_SUM_WORDS / BLOCK), dim3(BLOCK), 0, s, (const u64 *)a.fbits,
                              (n + 63) / 64, W.fsum, a.sshift);
         const size_t lds = sum ? MS_SUM_WORDS * sizeof(u32) : 0;
         if (a.hchunks > 0 && !heavy_done) {
-          const int gh = std::min(sum ? MS_SUM_GRID : 4096, (a.hchunks + 3) / 4);
-          if (sum)
+          const int gh = std::min(hsum ? MS_SUM_GRID : 4096, (a.hchunks + 3) / 4);
+          if (hsum)
             hipLaunchKernelGGL(k_ms_pull_heavy<true>, dim3(gh), dim3(BLOCK), lds, s, a);
           else
             hipLaunchKernelGGL(k_ms_pull_heavy<false>, dim3(gh), dim3(BLOCK), 0, s, a);

@@ -254,6 +254,10 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     set_error("source %d out of range [0, %d)", src, g->n);
     return BFS_EINVAL;
   }
+  if (opt_in && opt_in->vertex_map) {
+    set_error("options.vertex_map is honoured by bfs_multi only");
+    return BFS_ENOTSUP;
+  }
   bfs_options dflt;
   memset(&dflt, 0, sizeof(dflt));
   dflt.variant = selector_loaded() ? BFS_AUTO_LEARNED : BFS_AUTO_HEURISTIC;
@@ -580,6 +584,10 @@ static int step_time(const bfs_graph *g, const int *depths, int k, int variant, 
   if (!depths || !scratch || !ms_out || reps <= 0 || k < 0 || variant < 0 || variant >= BFS_NUM_VARIANTS) {
     set_error("invalid bfs_step_time arguments");
     return BFS_EINVAL;
+  }
+  if (opt && opt->vertex_map) {
+    set_error("options.vertex_map is honoured by bfs_multi only");
+    return BFS_ENOTSUP;
   }
   if (is_pull(variant) && !g->csc_ptr) {
     set_error("pull variant needs CSC arrays");

@@ -1,0 +1,141 @@
+"""GPU parity of the degree renumbering (bfs_reorder_degree) and of the
+multi-source search run on a renumbered graph through options.vertex_map.
+
+* the maps and the renumbered CSR / CSC equal the oracle's (oracle/reorder.py)
+  element by element: the order and the sorted rows are unique;
+* bfs_multi on the renumbered graph with vertex_map returns, row for row, the
+  oracle's depths on the ORIGINAL graph from the original sources;
+* the launch the benchmark times (R-MAT scale 22, 64 sources, renumbered)
+  against the oracle on sampled rows;
+* errors: vertex_map on the other entry points, malformed graphs.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from oracle import reorder as ro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2607_17106_amd as B  # noqa: E402
+
+MODES = [B.AUTO_HEURISTIC, B.PUSH_Q_BLOCK, B.PULL_B]
+
+
+def _graphs():
+    yield "rmat12", gg.rmat(12, seed=77)
+    yield "directed", gg.directed_random(3000, 15000, seed=4, self_loops=True, duplicates=True)
+    yield "lattice", gg.lattice(90, seed=3)
+    yield "isolated", gg.from_edge_list(5, [(1, 2)], True)
+    yield "one_vertex", gg.from_edge_list(1, [], True)
+    yield "ragged", gg.rmat(9, seed=2)  # 512 vertices, many of degree 0
+    yield "path701", gg.from_edge_list(701, [(i, i + 1) for i in range(700)], True)
+
+
+@pytest.mark.parametrize("name,g", list(_graphs()))
+def test_reorder_matches_oracle(name, g):
+    dg = B.DeviceGraph.from_graph(g)
+    rg, new_of_old, old_of_new = B.reorder_degree(dg)
+    n2o, o2n = ro.degree_order(g.row_ptr)
+    np.testing.assert_array_equal(new_of_old.cpu().numpy(), n2o, err_msg=name)
+    np.testing.assert_array_equal(old_of_new.cpu().numpy(), o2n, err_msg=name)
+    rp, ci = ro.renumber(g.row_ptr, g.col_idx, n2o)
+    np.testing.assert_array_equal(rg.row_ptr.cpu().numpy(), rp, err_msg=name)
+    np.testing.assert_array_equal(rg.col_idx.cpu().numpy(), ci, err_msg=name)
+    if not g.symmetric:
+        g.with_csc()
+        cp, cx = ro.renumber(g.csc_ptr, g.csc_idx, n2o)
+        np.testing.assert_array_equal(rg.csc_ptr.cpu().numpy(), cp, err_msg=name)
+        np.testing.assert_array_equal(rg.csc_idx.cpu().numpy(), cx, err_msg=name)
+    else:
+        assert rg.csc_ptr.data_ptr() == rg.row_ptr.data_ptr()
+
+
+def _check_mapped(g, srcs, variant):
+    dg = B.DeviceGraph.from_graph(g)
+    rg, new_of_old, _ = B.reorder_degree(dg)
+    lv, st = B.bfs_multi(rg, srcs, variant=variant, vertex_map=new_of_old)
+    lv = lv.cpu().numpy()
+    ref = oracle.multi(g.row_ptr, g.col_idx, srcs)
+    for i in range(len(srcs)):
+        np.testing.assert_array_equal(lv[i], ref[i], err_msg=f"lane {i} source {srcs[i]} mode {variant}")
+    assert st["reached"] == int((ref >= 0).sum())
+    assert st["component_edges"] == sum(oracle.edges_in_component(g.row_ptr, ref[i]) for i in range(len(srcs)))
+
+
+@pytest.mark.parametrize("variant", MODES)
+def test_mapped_multi_matches_oracle(variant):
+    g = gg.workload("rmat14")
+    _check_mapped(g, gg.pick_sources(g, 64, 5), variant)
+    g = gg.rmat(12, seed=77)
+    srcs = gg.pick_sources(g, 50, 6)
+    _check_mapped(g, np.concatenate([srcs, srcs[:20]]), variant)  # two groups, duplicates
+    _check_mapped(g, srcs[:1], variant)
+    g = gg.directed_random(3000, 15000, seed=4, self_loops=True, duplicates=True)
+    _check_mapped(g, np.arange(0, 3000, 47)[:64], variant)
+    g = gg.from_edge_list(5, [(1, 2)], True)
+    _check_mapped(g, np.array([0, 1, 4]), variant)
+
+
+@pytest.mark.parametrize("variant", MODES)
+def test_mapped_long_paths(variant):
+    """Depths above 255 (flush passes, whose bookkeeping is per output column)."""
+    for n in (700, 701):
+        g = gg.from_edge_list(n, [(i, i + 1) for i in range(n - 1)], True)
+        _check_mapped(g, np.array([0, n - 1, 350, 100, 0, 3]), variant)
+
+
+def test_vertex_map_rejected_elsewhere():
+    import ctypes
+    g = gg.rmat(10, seed=3)
+    dg = B.DeviceGraph.from_graph(g)
+    rg, new_of_old, _ = B.reorder_degree(dg)
+    lib = B.load()
+    opt = B._lib.BfsOptions()
+    opt.variant = B.AUTO_HEURISTIC
+    opt.heuristic_push = opt.heuristic_pull = -1
+    opt.vertex_map = new_of_old.data_ptr()
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = lib.bfs_levels(rg.c, 0, ctypes.c_void_p(lv.data_ptr()), ctypes.byref(opt), None, stream)
+    assert rc == -7
+    rc = lib.bfs_parents(rg.c, 0, ctypes.c_void_p(lv.data_ptr()), ctypes.c_void_p(lv.data_ptr()),
+                         ctypes.byref(opt), None, stream)
+    assert rc == -7
+
+
+def test_reorder_rejects_malformed_graph():
+    g = gg.rmat(8, seed=1)
+    bad = g.col_idx.copy()
+    bad[3] = g.n + 5
+    dg = B.DeviceGraph(g.n, g.row_ptr, bad, symmetric=True)
+    with pytest.raises(B.BfsError) as e:
+        B.reorder_degree(dg)
+    assert e.value.code == -2
+
+
+def test_rmat22_64_sources_renumbered_sampled_rows():
+    """The benchmark's launch: R-MAT scale 22, its 64 sources, the renumbered
+    graph with vertex_map, default heuristic; rows sampled against the oracle
+    on the original graph, every row against depth invariants of its edges."""
+    g = gg.workload("rmat22")
+    nsrc, sseed = gg.WORKLOAD_SOURCES["rmat22"]
+    srcs = gg.pick_sources(g, nsrc, sseed)
+    dg = B.DeviceGraph.from_graph(g)
+    rg, new_of_old, _ = B.reorder_degree(dg)
+    del dg
+    lv, st = B.bfs_multi(rg, srcs, vertex_map=new_of_old)
+    lv = lv.cpu().numpy()
+    for i in (0, 21, 63):
+        np.testing.assert_array_equal(lv[i], oracle.bfs(g.row_ptr, g.col_idx, int(srcs[i]), want_parents=False)[0],
+                                      err_msg=f"row {i}")
+    src_of_edge = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.row_ptr))
+    for i in range(0, 64, 9):
+        row = lv[i]
+        a, b = row[src_of_edge], row[g.col_idx]
+        assert row[srcs[i]] == 0
+        assert np.all((a < 0) == (b < 0)), f"row {i}: an edge leaves the reached set (symmetric graph)"
+        reached = a >= 0
+        assert np.all(np.abs(a[reached] - b[reached]) <= 1), f"row {i}: an edge spans two levels"
