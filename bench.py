@@ -6,7 +6,12 @@ Workload: R-MAT scale 22 (4,194,304 vertices, edge factor 16, a,b,c,d =
 removed; 128,307,516 CSR entries) and 64 seeded sources from its largest
 component.  One step = the depths from all 64 sources, computed by the
 64-lane bit-packed multi-source search (bfs_multi) -- the batched form of this
-job.  Inputs are resident in HBM before the timed region.  The same JSON line
+job -- on the graph renumbered by decreasing out-degree (bfs_reorder_degree,
+a preprocessing step like the paper's own renumbering of every graph; its
+time is reported as config.reorder_ms), with sources and depths in the
+original numbering (options.vertex_map).  The same search on the graph as
+generated is reported as input_order.  Inputs are resident in HBM before the
+timed region.  The same JSON line
 also reports, on the same graph and sources, the single-source forms (learned
 per-level selector, direction heuristic, every fixed variant) and the
 512-instance batched launch against instance-by-instance runs.
@@ -35,7 +40,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of k_ms_pull_tile on this workload: two rocprofv3 --pmc runs of
-# `bench.py --steps 3 --warmup 1 --no-sweep --no-batch --no-cpu` (FETCH_SIZE,
+# `bench.py --steps 3 --warmup 1 --no-sweep --no-batch --no-cpu --no-input-order` (FETCH_SIZE,
 # then WRITE_SIZE, KiB per dispatch averaged over the kernel's 16 dispatches),
 # each scaled by what the same counter reads for a plain copy of 1 GiB
 # (`bench.py --copy-calibration 1073741824`: FETCH_SIZE 524300 KiB -> x2.0,
@@ -43,10 +48,10 @@ HBM_PEAK_GBS = 8000.0
 # (comments and whitespace aside) hashes to the values the counters were taken with.
 TILE_TRAFFIC = {
     "sources_sha256": {
-        "paper_2607_17106_amd/csrc/msbfs.hip": "65027428b69a865ebc1b7af610c0ca9b4869ca545efc542b199321ff4fca668d",
-        "paper_2607_17106_amd/csrc/common.hpp": "082bff47601a629526c148d9adef7ccc3acce82260afacd87a666552aa9fb4cf",
+        "paper_2607_17106_amd/csrc/msbfs.hip": "2a05a83ed8765be9fc8b12dba417b7a4aad031716f8f335cc36d1282ad191c32",
+        "paper_2607_17106_amd/csrc/common.hpp": "6e8a2114d3d2cc4c774668c53444e4a657d7449b3c846475ba232df551526fad",
     },
-    "fetch_kib": 677585.9, "write_kib": 121227.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 175400.6, "write_kib": 107502.0, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
@@ -128,6 +133,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip single-source modes and fixed variants")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch")
     ap.add_argument("--sweep-sources", type=int, default=16)
+    ap.add_argument("--no-input-order", action="store_true",
+                    help="skip the comparison run on the graph as generated (profiles see the timed step only)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times): the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters, then exit")
@@ -159,11 +166,15 @@ def main():
     dg = B.DeviceGraph.from_graph(g)
     lv_multi = torch.empty((len(sources), g.n), dtype=torch.int32, device="cuda")
     ws_multi = torch.empty(B.workspace_size(g.n, 64), dtype=torch.uint8, device="cuda")
+    # preprocessing: renumbering by decreasing out-degree (second call timed)
+    B.reorder_degree(dg)
+    (rg, new_of_old, _), reorder_s = timed(lambda: B.reorder_degree(dg))
+    log(f"[bench] renumbered by out-degree in {reorder_s * 1e3:.1f} ms")
 
     # ---------------------------------------------------------- timed step
-    def step(timing):
-        return B.bfs_multi(dg, sources, flags=B.F_LEVEL_TIMING if timing else 0, workspace=ws_multi,
-                           levels=lv_multi)[1]
+    def step(timing, graph=rg, vmap=new_of_old):
+        return B.bfs_multi(graph, sources, flags=B.F_LEVEL_TIMING if timing else 0, workspace=ws_multi,
+                           levels=lv_multi, vertex_map=vmap)[1]
 
     for _ in range(args.warmup):
         step(False)
@@ -176,6 +187,19 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     gteps = sum(st["component_edges"] for st in stats) / 2 / elapsed / 1e9
+
+    # the same search on the graph as generated (no renumbering), for comparison
+    input_order = None
+    if not args.no_input_order:
+        step(False, dg, None)
+        torch.cuda.synchronize()
+        t_in = time.perf_counter()
+        st_in = [step(False, dg, None) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        el_in = time.perf_counter() - t_in
+        input_order = {"gteps": round(sum(st["component_edges"] for st in st_in) / 2 / el_in / 1e9, 3),
+                       "ms_per_step": round(el_in * 1e3 / args.steps, 3)}
+        log(f"[bench] input order: {input_order}")
 
     # roofline of the dominant kernel: the bottom-up tile kernel (k_ms_pull_tile),
     # timed alone by the library's HIP events on its stream, priced by its own
@@ -217,8 +241,11 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
            "config": {"workload": f"{args.workload}-{len(sources)}src", "graph": "R-MAT scale 22, edge factor 16, "
                       "a,b,c,d=.57,.19,.19,.05, symmetrised", "n": g.n, "nnz": g.nnz, "sources": len(sources),
-                      "method": "64-lane bit-packed multi-source BFS (bfs_multi)", "output": "depths [64][n]"},
-           "roofline": roof}
+                      "method": "64-lane bit-packed multi-source BFS (bfs_multi)", "output": "depths [64][n]",
+                      "vertex_order": "renumbered by decreasing out-degree (bfs_reorder_degree, preprocessing, "
+                                      "outside the timed region); sources and depths in the original numbering",
+                      "reorder_ms": round(reorder_s * 1e3, 2)},
+           "roofline": roof, "input_order": input_order}
 
     # ------------------------------------------- single-source comparisons
     if not args.no_sweep:

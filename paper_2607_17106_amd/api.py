@@ -7,6 +7,7 @@ numpy arrays.
 from __future__ import annotations
 
 import ctypes
+import threading
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -104,6 +105,30 @@ def workspace_size(n: int, lanes: int = 1) -> int:
 
 
 class _StatsBuf:
+    """Host arrays the library fills with per-level statistics.  One buffer
+    per thread and capacity is kept and reused (get()): building the ctypes
+    view costs far more than a short search's host work."""
+    _local = threading.local()
+
+    @classmethod
+    def get(cls, cap: int) -> "_StatsBuf":
+        cache = getattr(cls._local, "bufs", None)
+        if cache is None:
+            cache = cls._local.bufs = {}
+        buf = cache.get(cap)
+        if buf is None:
+            buf = cache[cap] = cls(cap)
+        # a call fills only the fields its path knows: clear what the last
+        # call may have written (every entry, if it never reached as_dict)
+        s = buf.s
+        s.num_levels = s.fell_back = s.host_syncs = 0
+        s.reached = s.component_edges = s.graph_ld = s.graph_ld2 = 0
+        s.elapsed_ms = 0.0
+        for a in buf._arrays:
+            a[:buf._dirty] = 0
+        buf._dirty = cap
+        return buf
+
     def __init__(self, cap: int):
         self.cap = cap
         self.variant = np.zeros(cap, np.int32)
@@ -120,6 +145,10 @@ class _StatsBuf:
         self.ms_main = np.zeros(cap, np.float32)
         self.scan_aux = np.zeros(cap, np.int64)
         self.hits_aux = np.zeros(cap, np.int64)
+        self._arrays = (self.variant, self.frontier, self.frontier_edges, self.unvisited, self.unvisited_edges,
+                        self.fallback, self.fld, self.fld2, self.scanned, self.nxt, self.ms, self.ms_main,
+                        self.scan_aux, self.hits_aux)
+        self._dirty = 0
         P32, P64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
         self.s = L.BfsStats()
         self.s.level_capacity = cap
@@ -143,8 +172,9 @@ class _StatsBuf:
         d = dict(num_levels=s.num_levels, fell_back=s.fell_back, reached=s.reached,
                  component_edges=s.component_edges, elapsed_ms=s.elapsed_ms, host_syncs=s.host_syncs,
                  graph_ld=s.graph_ld, graph_ld2=s.graph_ld2)
+        self._dirty = min(max(s.num_levels, 0), self.cap)
         if per_level:
-            k = min(s.num_levels, self.cap)
+            k = self._dirty
             d.update(variant=self.variant[:k].copy(), frontier=self.frontier[:k].copy(),
                      frontier_edges=self.frontier_edges[:k].copy(), unvisited=self.unvisited[:k].copy(),
                      unvisited_edges=self.unvisited_edges[:k].copy(), fallback=self.fallback[:k].copy(),
@@ -186,7 +216,7 @@ def _run_single(fn_name, g: DeviceGraph, source, want_parents, variant, flags, s
         level_stats = True
     if level_stats:
         flags |= L.F_LEVEL_STATS
-    sb = _StatsBuf(stats_capacity if level_stats else 0)
+    sb = _StatsBuf.get(stats_capacity if level_stats else 0)
     opt, keep = _options(variant, flags, schedule, workspace, max_levels, heuristic_push)
     if variant == L.AUTO_LEARNED or level_stats:
         opt.graph_ld, opt.graph_ld2 = g.graph_sums(stream)
@@ -236,7 +266,7 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
         level_stats = True
     if level_stats:
         flags |= L.F_LEVEL_STATS
-    sb = _StatsBuf(stats_capacity if level_stats else 0)
+    sb = _StatsBuf.get(stats_capacity if level_stats else 0)
     opt, keep = _options(variant, flags, None, workspace, 0, None)
     if vertex_map is not None:
         if vertex_map.dtype != torch.int32 or vertex_map.numel() != g.n or not vertex_map.is_contiguous():
@@ -291,7 +321,7 @@ def bfs_batch(b: DeviceBatch, sources=None, config: Optional[BatchConfig] = None
     src = np.ascontiguousarray(b.sources if sources is None else sources, dtype=np.int32)
     if levels is None:
         levels = torch.empty(b.total_n, dtype=torch.int32, device=b.row_ptr.device)
-    sb = _StatsBuf(0)
+    sb = _StatsBuf.get(0)
     cfg = config.c() if config is not None else None
     rc = lib.bfs_batch(b.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(levels),
                        ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(sb.s), _stream(stream))
