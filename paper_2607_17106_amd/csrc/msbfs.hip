@@ -314,31 +314,49 @@ __device__ __forceinline__ void ms_out_body(const MsArgs &a, int flush) {
 }
 
 // ------------------------------------------------------------------ init
+// Clears a group's state: visited words, two frontier buffers, the first
+// frontier bitmap, depth plane 0 and the counter shards (k_ms_finish keeps
+// those clear afterwards).
 __global__ __launch_bounds__(BLOCK) void k_ms_init(MsArgs a, u64 *f0, u64 *f1, u64 *b0) {
   const int nw = (a.n + 63) / 64;
   for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
     a.vis[v] = 0ull;
     f0[v] = 0ull;
     f1[v] = 0ull;
+    a.planes[v] = 0ull;
     if (v < nw) b0[v] = 0ull;
   }
+  u64 *sh = reinterpret_cast<u64 *>(a.sh);
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < NSH * MS_NCTR; i += gridDim.x * BLOCK) sh[i] = 0ull;
 }
 
 // One thread per lane: sets the source bit (duplicates OR); depth 0 is
 // relative depth 0, which the zeroed planes already hold.
-// Sources given in the original numbering become ids of the renumbered graph.
-__global__ void k_ms_map_sources(int *src, int L, const int *vmap) {
-  if ((int)threadIdx.x < L) src[threadIdx.x] = vmap[src[threadIdx.x]];
-}
+struct MsSources {
+  int v[64];
+};
 
-__global__ void k_ms_sources(MsArgs a, const int *src, u64 *f0, u64 *b0) {
+// One thread per lane: maps the lane's source to the graph's numbering (a
+// renumbered graph), sets its bit (duplicates OR; depth 0 is relative depth 0,
+// which the zeroed planes already hold), and posts to host memory what the
+// host needs before the first level: the sources' out-degrees (post[64 + l])
+// and, copied from `tot`, the heavy-list and tile totals (post[0 .. 4]); then,
+// after system-scope fences, the sequence word.
+__global__ void k_ms_seed(MsArgs a, MsSources src, u64 *f0, u64 *b0, const int *tot, int *post,
+                          u64 *post_seq, u64 seq) {
   const int l = threadIdx.x;
   if (l < a.L) {
-    const int s = src[l];
+    int s = src.v[l];
+    if (a.vmap) s = a.vmap[s];
     atomicOr(a.vis + s, 1ull << l);
     atomicOr(f0 + s, 1ull << l);
     atomicOr(b0 + (s >> 6), 1ull << (s & 63));
+    post[64 + l] = a.rp[s + 1] - a.rp[s];
   }
+  if (l < 5) post[l] = tot[l];
+  __threadfence_system();  // each lane's posts reach the host before the sequence word
+  __syncthreads();
+  if (l == 0) *reinterpret_cast<volatile u64 *>(post_seq) = seq;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_ms_fill(u64 *p, int n) {
@@ -1006,17 +1024,6 @@ __global__ __launch_bounds__(NSH) void k_ms_finish(MsCtr *sh, MsCtr *tot, u64 se
   }
 }
 
-__global__ void k_ms_zero(MsCtr *sh) {
-  u64 *f = reinterpret_cast<u64 *>(sh);
-  for (int i = threadIdx.x; i < NSH * MS_NCTR; i += blockDim.x) f[i] = 0ull;
-}
-
-// Out-degree of each lane's source (for the F_0 counts and the component
-// edge total).
-__global__ void k_ms_src_deg(const int *rp, const int *src, int L, int *deg) {
-  const int l = threadIdx.x;
-  if (l < L) deg[l] = rp[src[l] + 1] - rp[src[l]];
-}
 
 }  // namespace bfs
 
@@ -1062,7 +1069,11 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   // heavy in-degree vertices and their chunk prefix (read back with the first group's sync)
   const int nbh = (n + MS_HB - 1) / MS_HB;
   int *htot_dev = src_dev + 192;
-  int *htot_host = reinterpret_cast<int *>(hc.pinned_u64 + 64);
+  // k_ms_seed posts the totals and the sources' degrees here (coherent host memory)
+  int *post_host = reinterpret_cast<int *>(hc.pinned_u64 + 64);
+  u64 *post_seq = hc.pinned_u64 + 200;
+  const int *htot_host = post_host;
+  const int *deg_host = post_host + 64;
   // with the bottom-up tiles (their count in htot[4])
   hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.bwt);
   hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev, W.bwt,
@@ -1080,7 +1091,6 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
                        (const int *)nullptr);
   }
   BFS_HIP(hipGetLastError());
-  BFS_HIP(hipMemcpyAsync(htot_host, htot_dev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
   long long reached = 0, comp = 0;
   int max_levels = 0, syncs = 0;
   const int flags = opt ? opt->flags : 0;
@@ -1113,19 +1123,20 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.vmap = opt ? opt->vertex_map : nullptr;
     a.sh = sh;
     a.base = 0;
-    a.np = 0;
+    a.np = 1;  // plane 0 is cleared by k_ms_init
     a.nflush = 0;
     hipLaunchKernelGGL(k_ms_init, dim3(grid_v), dim3(BLOCK), 0, s, a, fr[0], fr[1], W.fb[0]);
-    hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(BLOCK), 0, s, sh);  // k_ms_finish keeps them clear afterwards
-    BFS_HIP(hipMemcpyAsync(src_dev, sources + g0, L * sizeof(int), hipMemcpyHostToDevice, s));
-    if (a.vmap) hipLaunchKernelGGL(k_ms_map_sources, dim3(1), dim3(64), 0, s, src_dev, L, a.vmap);
-    hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, s, a, (const int *)src_dev, fr[0], W.fb[0]);
-    // counts of F_0 for the direction rule: distinct source vertices and their degrees
-    hipLaunchKernelGGL(k_ms_src_deg, dim3(1), dim3(64), 0, s, g->row_ptr, (const int *)src_dev, L, src_dev + 64);
+    // sources by value; the seed kernel posts the counts of F_0 for the
+    // direction rule (distinct source vertices and their degrees) and the
+    // heavy-list and tile totals, which the host polls for
+    MsSources sv;
+    for (int i = 0; i < 64; ++i) sv.v[i] = i < L ? sources[g0 + i] : 0;
+    const u64 seed_seq = ++hc.seq;
+    hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, a, sv, fr[0], W.fb[0], (const int *)htot_dev, post_host,
+                       post_seq, seed_seq);
     BFS_HIP(hipGetLastError());
-    int *deg_host = reinterpret_cast<int *>(hc.pinned_u64);
-    BFS_HIP(hipMemcpyAsync(deg_host, src_dev + 64, L * sizeof(int), hipMemcpyDeviceToHost, s));
-    BFS_HIP(hipStreamSynchronize(s));
+    rc = wait_posted(post_seq, seed_seq, s);
+    if (rc) return rc;
     a.hcount = htot_host[0];
     a.hchunks = htot_host[1];
     a.ntiles = htot_host[4];
@@ -1216,9 +1227,13 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         // a sparse frontier is tested against its LDS summary first: most
         // in-neighbours are rejected without touching the bitmap
         // (the heavy pass, which exits early per chunk, gains from it only
-        // at much lower densities than the tile pass)
-        const bool sum = (nf << a.sshift) * 8 < (long long)n;
-        const bool hsum = (nf << a.sshift) * 64 < (long long)n;
+        // at much lower densities than the tile pass).  Not on a graph
+        // renumbered by degree: there most in-edges come from the first few
+        // hundred KB of bitmap, which stay in cache, and the 32 KB of LDS per
+        // workgroup would cost more in occupancy than the filter saves.
+        const bool filt = a.vmap == nullptr;
+        const bool sum = filt && (nf << a.sshift) * 8 < (long long)n;
+        const bool hsum = filt && (nf << a.sshift) * 64 < (long long)n;
         if (sum)
           hipLaunchKernelGGL(k_ms_summary, dim3(MS_SUM_WORDS / BLOCK), dim3(BLOCK), 0, s, (const u64 *)a.fbits,
                              (n + 63) / 64, W.fsum, a.sshift);
