@@ -39,7 +39,10 @@ constexpr long long MS_ALPHA = 7;  // bottom-up when frontier out-edges exceed 1
 constexpr int MS_PLANES = 8;       // relative depths 0..255 per window
 constexpr int MS_HEAVY = 1024;     // in-degree above which a vertex's in-edges are split over waves
 constexpr int MS_HCHUNK = 1024;    // in-edges per wave in the heavy pass (<= MS_HEAVY)
-constexpr int MS_EPT = 8;          // in-edges per thread per tile iteration
+constexpr int MS_EPT = 8;          // in-edges per thread per tile iteration (a multiple of 4)
+struct __attribute__((packed, aligned(4))) I4u {  // four ints at any 4-byte-aligned address
+  int x, y, z, w;
+};
 constexpr int MS_VPT_SPARSE = 4;   // vertices per thread in the bottom-up tile when few in-edges remain
 constexpr int MS_CAP0 = 32;        // in-edges per pending vertex in the first merged round (dense frontiers)
 constexpr int MS_HB = 1024;        // vertices per workgroup in the heavy-list build
@@ -761,23 +764,45 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
             skip = (s_acc[o] & nd) == nd;  // lanes already complete: no more gathers for o
           }
           int own[MS_EPT], u[MS_EPT];
+          if (o >= 0 && e0 + MS_EPT <= next_off) {
+            // all MS_EPT positions in owner o's list: two 16-byte loads
+            // (4-byte aligned) instead of MS_EPT scalar ones
   #pragma unroll
-          for (int i = 0; i < MS_EPT; ++i) {
-            const int e = e0 + i;
-            own[i] = -1;
-            u[i] = -1;
-            if (o >= 0 && e < total) {
-              while (e >= next_off) {  // next owner with edges left (s_off[TV] = total > e)
-                ++o;
-                next_off = s_off[o + 1];
-                base_j = s_beg[o] - s_off[o];
-                const u64 nd = s_need[o];
-                skip = (s_acc[o] & nd) == nd;
+            for (int i = 0; i < MS_EPT; ++i) own[i] = o;
+            if (!skip) {
+              const I4u *p = reinterpret_cast<const I4u *>(a.cx + base_j + e0);
+  #pragma unroll
+              for (int q = 0; q < MS_EPT / 4; ++q) {
+                const I4u w = p[q];
+                u[4 * q] = w.x;
+                u[4 * q + 1] = w.y;
+                u[4 * q + 2] = w.z;
+                u[4 * q + 3] = w.w;
               }
-              own[i] = o;
-              if (!skip) {
-                u[i] = a.cx[base_j + e];
-                st.c[C_SCAN] += 1;
+              st.c[C_SCAN] += MS_EPT;
+            } else {
+  #pragma unroll
+              for (int i = 0; i < MS_EPT; ++i) u[i] = -1;
+            }
+          } else {
+  #pragma unroll
+            for (int i = 0; i < MS_EPT; ++i) {
+              const int e = e0 + i;
+              own[i] = -1;
+              u[i] = -1;
+              if (o >= 0 && e < total) {
+                while (e >= next_off) {  // next owner with edges left (s_off[TV] = total > e)
+                  ++o;
+                  next_off = s_off[o + 1];
+                  base_j = s_beg[o] - s_off[o];
+                  const u64 nd = s_need[o];
+                  skip = (s_acc[o] & nd) == nd;
+                }
+                own[i] = o;
+                if (!skip) {
+                  u[i] = a.cx[base_j + e];
+                  st.c[C_SCAN] += 1;
+                }
               }
             }
           }
