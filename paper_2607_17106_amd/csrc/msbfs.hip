@@ -35,6 +35,7 @@ namespace bfs {
 
 constexpr int MS_T = 4;   // in-edges per lane before the wave-cooperative scan (push)
 constexpr int MS_HEAD = 8; // in-edges a light vertex's own thread reads before the merged walk (pull)
+static_assert(MS_HEAD % 4 == 0, "the head is read in 16-byte pieces");
 constexpr long long MS_ALPHA = 7;  // bottom-up when frontier out-edges exceed 1/7 of eu (and n/8)
 constexpr int MS_PLANES = 8;       // relative depths 0..255 per window
 constexpr int MS_HEAVY = 1024;     // in-degree above which a vertex's in-edges are split over waves
@@ -705,8 +706,20 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
         continue;
       }
       int u[MS_HEAD];
+      if (d[j] >= MS_HEAD) {  // a whole head inside the list: 16-byte loads
+        const I4u *p = reinterpret_cast<const I4u *>(a.cx + b[j]);
 #pragma unroll
-      for (int i = 0; i < MS_HEAD; ++i) u[i] = i < d[j] ? a.cx[b[j] + i] : -1;
+        for (int q = 0; q < MS_HEAD / 4; ++q) {
+          const I4u w = p[q];
+          u[4 * q] = w.x;
+          u[4 * q + 1] = w.y;
+          u[4 * q + 2] = w.z;
+          u[4 * q + 3] = w.w;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < MS_HEAD; ++i) u[i] = i < d[j] ? a.cx[b[j] + i] : -1;
+      }
       bool hit[MS_HEAD];
 #pragma unroll
       for (int i = 0; i < MS_HEAD; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
