@@ -78,6 +78,10 @@ int bfs_version(void);
  *                  all lie at the current depth, so the visited bitmap (bits
  *                  of never-reachable vertices told apart by their depth, -1)
  *                  serves as the frontier; new bits are merged after the step
+ *  PUSH_P3         top-down with three visited arrays (Table 3, variant 26):
+ *                  no frontier array, F_k = P_k AND NOT P_{k-1}; atomic-free
+ *                  expansion as PUSH_B_NOATOMIC, and the owner-computes update
+ *                  keeps P_k as the next level's P_{k-1}
  * Every step emits the next frontier both as a queue and as a bitmap, so the
  * format of the next level is a free choice.
  */
@@ -89,7 +93,8 @@ int bfs_version(void);
 #define BFS_V_PUSH_Q_NOATOMIC 5
 #define BFS_V_PULL_B 6
 #define BFS_V_PULL_VIS 7         /* same depths, parents and scan lengths as BFS_V_PULL_B */
-#define BFS_NUM_VARIANTS 8
+#define BFS_V_PUSH_P3 8
+#define BFS_NUM_VARIANTS 9
 /* Per-level choice modes. */
 #define BFS_AUTO_HEURISTIC 100 /* Beamer direction-optimising rule (alpha 14, beta 24) */
 #define BFS_AUTO_LEARNED 101   /* selector network on device; heuristic fallback */

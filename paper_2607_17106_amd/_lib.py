@@ -27,7 +27,8 @@ PUSH_B_NOATOMIC = 4
 PUSH_Q_NOATOMIC = 5
 PULL_B = 6
 PULL_VIS = 7
-NUM_VARIANTS = 8
+PUSH_P3 = 8
+NUM_VARIANTS = 9
 AUTO_HEURISTIC = 100
 AUTO_LEARNED = 101
 SCHEDULE = 102
@@ -36,6 +37,7 @@ VARIANT_NAMES = {
     PUSH_Q_THREAD: "push_q_thread", PUSH_Q_BLOCK: "push_q_block", PUSH_Q_MERGE: "push_q_merge",
     PUSH_B_ATOMIC: "push_b_atomic", PUSH_B_NOATOMIC: "push_b_noatomic",
     PUSH_Q_NOATOMIC: "push_q_noatomic", PULL_B: "pull_b", PULL_VIS: "pull_vis",
+    PUSH_P3: "push_p3",
     AUTO_HEURISTIC: "heuristic", AUTO_LEARNED: "learned", SCHEDULE: "schedule",
 }
 

@@ -92,6 +92,8 @@ struct Workspace {
   void *bar;           // grid barrier of the persistent kernel
   int *sched;          // device copy of a host schedule (LOGCAP entries)
   u64 *gsum;           // graph-level sums (ld, ld2), selector state, validation flag
+  u64 *vis_prev;       // three-array visited strategy: P_{k-1} (valid while *p3_level == k)
+  int *p3_level;
   int W;               // bitmap words = ceil(n/64)
   int qcap;
 };
@@ -119,6 +121,8 @@ struct StepArgs {
   LevelCtr *sh_next;           // shards of F_{k+1} (producers add)
   LevelCtr *sh_zero;           // shards of F_{k+2} (cleared by the first kernel)
   int *scan, *bsum, *hubs;
+  u64 *vis_prev;               // PUSH_P3: P_{k-1} when *p3_level == k
+  int *p3_level;
 };
 
 // ------------------------------------------------- per-thread host context

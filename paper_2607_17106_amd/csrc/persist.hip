@@ -164,6 +164,13 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs P) {
         ok = grid_sync(P.bar, epoch);
         if (ok) body_merge_vis(a);
         break;
+      case BFS_V_PUSH_P3:
+        body_push_p3(a, smem);
+        ok = grid_sync(P.bar, epoch);
+        if (ok) body_push_hubs<false>(a, smem);
+        ok = ok && grid_sync(P.bar, epoch);
+        if (ok) body_p3_update(a);
+        break;
       default:  // BFS_V_PULL_B
         body_pull<false>(a);
         break;

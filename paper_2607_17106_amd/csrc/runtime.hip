@@ -52,6 +52,8 @@ size_t workspace_bytes_single(int n) {
   b += align256(sizeof(GridBar));                    // bar
   b += align256(LOGCAP * sizeof(int));               // sched
   b += align256(GSUM_WORDS * 8);                     // gsum
+  b += align256(W * 8);                              // vis_prev
+  b += align256(sizeof(int));                        // p3_level
   return b;
 }
 
@@ -72,6 +74,8 @@ Workspace carve_single(void *base, int n) {
   w.bar = take(sizeof(GridBar));
   w.sched = (int *)take(LOGCAP * sizeof(int));
   w.gsum = (u64 *)take(GSUM_WORDS * 8);
+  w.vis_prev = (u64 *)take(W * 8);
+  w.p3_level = (int *)take(sizeof(int));
   w.W = (int)W;
   w.qcap = queue_cap(n);
   return w;
@@ -231,6 +235,8 @@ static StepArgs level_args(const bfs_graph *g, const Workspace &w, int *levels, 
   a.levels = levels;
   a.parents = parents;
   a.vis = w.vis;
+  a.vis_prev = w.vis_prev;
+  a.p3_level = w.p3_level;
   a.fb_cur = w.fb[k % 3];
   a.fb_next = w.fb[(k + 1) % 3];
   a.fb_dead = w.fb[(k + 2) % 3];

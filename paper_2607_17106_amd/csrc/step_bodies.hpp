@@ -52,7 +52,10 @@ __device__ __forceinline__ void body_reset(const StepArgs &a, int src, RingSlot 
   const int per = (int)(sizeof(RingSlot) / sizeof(u32));
   u32 *z = reinterpret_cast<u32 *>(ring);
   for (int i = tid; i < RING * per; i += nthr) z[i] = 0u;
-  if (tid == 0) const_cast<int *>(a.q_cur)[0] = src;
+  if (tid == 0) {
+    const_cast<int *>(a.q_cur)[0] = src;
+    *a.p3_level = -1;  // P_{-1} not kept yet
+  }
 }
 
 // Writes F_0 = {src} into slot 0's total and segment offsets (after k_reset
@@ -502,6 +505,82 @@ __device__ __forceinline__ void body_noatom_update(const StepArgs &a) {
     }
   }
   st.flush(a.sh_next);
+}
+
+// ------------------------------ three visited arrays (Table 3, variant 26)
+// The frontier is not kept as an array of its own: F_k = P_k AND NOT P_{k-1}
+// (the three arrays are P_{k-1}, P_k and the P_{k+1} the update builds in
+// place).  The expansion is atomic-free as in body_push_b<false>; when the
+// previous level was run by another variant P_{k-1} is not at hand and the
+// frontier bitmap every step emits stands in for one level.
+__device__ __forceinline__ void body_push_p3(const StepArgs &a, char *smem) {
+  int *s_incl = reinterpret_cast<int *>(smem), *s_u = s_incl + BLOCK, *s_off = s_u + BLOCK;
+  NewStats st;
+  const int wv = threadIdx.x / WAVE;
+  int *incl = s_incl + wv * WAVE;
+  int *su = s_u + wv * WAVE;
+  int *so = s_off + wv * WAVE;
+  const int gw = blockIdx.x * (BLOCK / WAVE) + wv;
+  const int nw = gridDim.x * (BLOCK / WAVE);
+  const bool derive = *a.p3_level == a.k;
+  for (int w = gw; w < a.W; w += nw) {
+    const u64 fw = derive ? (a.vis[w] & ~a.vis_prev[w]) : a.fb_cur[w];
+    if (fw == 0ull) continue;  // wave-uniform
+    const int v = w * WAVE + lane();
+    int beg = 0, d = 0;
+    if ((fw >> lane()) & 1ull) {
+      beg = a.rp[v];
+      d = a.rp[v + 1] - beg;
+    }
+    const bool hub = d > a.hub;
+    int pos = wave_append(hub, &a.c_cur->nhub);
+    if (hub) {
+      a.hubs[pos] = v;
+      d = 0;
+    }
+    int in = wave_incl_scan(d);
+    const int total = __shfl(in, WAVE - 1);
+    incl[lane()] = in;
+    su[lane()] = v;
+    so[lane()] = beg - (in - d);
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane(); e < total; e += WAVE) {
+      int j = find_owner(incl, WAVE, e);
+      visit_edge<false>(a, su[j], a.ci[so[j] + e], st);
+      st.scanned++;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  st.flush(a.sh_next);
+}
+
+// Owner computes, as body_noatom_update, and keeps P_k as the next level's
+// P_{k-1}: every word of vis_prev is rewritten, then the level tag.
+__device__ __forceinline__ void body_p3_update(const StepArgs &a) {
+  NewStats st;
+  const int wv = threadIdx.x / WAVE;
+  const int gw = blockIdx.x * (BLOCK / WAVE) + wv;
+  const int nw = gridDim.x * (BLOCK / WAVE);
+  for (int w = gw; w < a.W; w += nw) {
+    const u64 vw = a.vis[w];
+    const int v = w * WAVE + lane();
+    bool nw_ = false;
+    if (vw != ~0ull && !((vw >> lane()) & 1ull)) nw_ = (a.levels[v] == a.k + 1);
+    const u64 m = __ballot(nw_);
+    if (lane() == 0) {
+      a.vis_prev[w] = vw;
+      if (m) {
+        a.vis[w] = vw | m;
+        a.fb_next[w] = m;
+      }
+    }
+    if (m) {
+      if (nw_) st.add_vertex(a, v);
+      queue_push(nw_, v, a);
+    }
+  }
+  st.flush(a.sh_next);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.p3_level = a.k + 1;
 }
 
 // ---------------------------------------------------- pull over CSC, bitmap

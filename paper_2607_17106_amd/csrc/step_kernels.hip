@@ -114,6 +114,18 @@ __global__ __launch_bounds__(BLOCK) void k_noatom_update(StepArgs a) {
   body_noatom_update(a);
 }
 
+__global__ __launch_bounds__(BLOCK) void k_push_p3(StepArgs a) {
+  __shared__ __align__(16) char smem[SM_PUSH_B];
+  clear_dead(a);
+  if (gated_off(a)) return;
+  body_push_p3(a, smem);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_p3_update(StepArgs a) {
+  if (gated_off(a)) return;
+  body_p3_update(a);
+}
+
 template <bool FROM_VIS>
 __global__ __launch_bounds__(BLOCK) void k_pull(StepArgs a) {
   clear_dead(a);
@@ -146,10 +158,14 @@ __global__ __launch_bounds__(BLOCK) void k_state_from_depths(StepArgs a, const i
       if (a.parents) a.parents[v] = (dv == 0) ? v : -1;
     }
     const bool dead = (v < a.n) && a.cp && (a.cp[v + 1] == a.cp[v]) && dv != 0;
-    u64 pm = __ballot(in_p || dead), fm = __ballot(in_f);
-    if (w == a.W - 1 && tail) pm |= ~0ull << tail;
+    u64 pm = __ballot(in_p || dead), fm = __ballot(in_f), qm = __ballot((in_p && !in_f) || dead);
+    if (w == a.W - 1 && tail) {
+      pm |= ~0ull << tail;
+      qm |= ~0ull << tail;
+    }
     if (lane() == 0) {
       a.vis[w] = pm;
+      a.vis_prev[w] = qm;  // P_{k-1}, for the three-array variant
       const_cast<u64 *>(a.fb_cur)[w] = fm;
       a.fb_next[w] = 0;
       a.fb_dead[w] = 0;
@@ -159,6 +175,7 @@ __global__ __launch_bounds__(BLOCK) void k_state_from_depths(StepArgs a, const i
   }
   st.scanned = 0;
   st.flush(a.sh_next);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.p3_level = a.k;
 }
 
 __global__ void k_zero_u32(u32 *p, int n) {
@@ -313,6 +330,11 @@ hipError_t launch_step(int variant, const StepArgs &a, int count, long long edge
       break;
     case BFS_V_PULL_B:
       hipLaunchKernelGGL(k_pull<false>, dim3(std::max(g0, gw)), dim3(BLOCK), 0, s, a);
+      break;
+    case BFS_V_PUSH_P3:
+      hipLaunchKernelGGL(k_push_p3, dim3(std::max(g0, gw)), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL(k_push_hubs<false>, dim3(ghub), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL(k_p3_update, dim3(gw), dim3(BLOCK), 0, s, a);
       break;
     case BFS_V_PULL_VIS:
       hipLaunchKernelGGL(k_pull<true>, dim3(std::max(g0, gw)), dim3(BLOCK), 0, s, a);

@@ -218,7 +218,7 @@ def test_push_scanned_equals_frontier_edges():
     g = gg.workload("rmat14")
     dg = B.DeviceGraph.from_graph(g)
     (s,) = gg.pick_sources(g, 1, 1402)
-    for v in (B.PUSH_Q_THREAD, B.PUSH_Q_BLOCK, B.PUSH_Q_MERGE, B.PUSH_B_ATOMIC, B.PUSH_B_NOATOMIC):
+    for v in (B.PUSH_Q_THREAD, B.PUSH_Q_BLOCK, B.PUSH_Q_MERGE, B.PUSH_B_ATOMIC, B.PUSH_B_NOATOMIC, B.PUSH_P3):
         _, _, st = _run(dg, g, s, v, level_stats=True)
         np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
         np.testing.assert_array_equal(st["next"][:-1], st["frontier"][1:])
