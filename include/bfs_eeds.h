@@ -82,6 +82,12 @@ int bfs_version(void);
  *                  no frontier array, F_k = P_k AND NOT P_{k-1}; atomic-free
  *                  expansion as PUSH_B_NOATOMIC, and the owner-computes update
  *                  keeps P_k as the next level's P_{k-1}
+ *  PUSH_Q_FILTER   top-down, queue, advance before the depth update (Table 3,
+ *                  variant 13): a merge-path pass writes every out-neighbour of
+ *                  F_k with its source to a temporary list (no visited test, no
+ *                  atomics), then a filter pass claims each entry as the atomic
+ *                  push does; the list holds tmp_entries(n) entries (n clamped
+ *                  to [2^16, 2^22]), larger frontiers go in chunks
  * Every step emits the next frontier both as a queue and as a bitmap, so the
  * format of the next level is a free choice.
  */
@@ -94,7 +100,8 @@ int bfs_version(void);
 #define BFS_V_PULL_B 6
 #define BFS_V_PULL_VIS 7         /* same depths, parents and scan lengths as BFS_V_PULL_B */
 #define BFS_V_PUSH_P3 8
-#define BFS_NUM_VARIANTS 9
+#define BFS_V_PUSH_Q_FILTER 9
+#define BFS_NUM_VARIANTS 10
 /* Per-level choice modes. */
 #define BFS_AUTO_HEURISTIC 100 /* Beamer direction-optimising rule (alpha 14, beta 24) */
 #define BFS_AUTO_LEARNED 101   /* selector network on device; heuristic fallback */

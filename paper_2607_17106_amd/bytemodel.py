@@ -21,6 +21,8 @@ Per variant (p = 4 when parents are written, else 0):
                                   + merge pass 3n/8
   push, three visited arrays      2n/8 (F = P_k AND NOT P_{k-1}) + 8nF + 4eF + eF/8
                                   + (4+p)nN + update pass: n/8 + 4nU + 3n/8 + 4nN
+  push, advance then filter       20nF (queue, offsets, degree scan) + 4eF + 8eF (list
+                                  written) + 8eF (read back) + eF/8 + (8+p)nN + nN/8
 """
 from __future__ import annotations
 
@@ -44,6 +46,8 @@ def step_bytes(variant: int, n: int, nF: int, eF: int, nU: int, nN: int, scan: i
         return bm + 8.0 * nU + 4.0 * scan + scan / 8.0 + 2 * bm + (8 + p) * nN
     if variant == L.PULL_VIS:  # probes read the visited bitmap; merge pass reads next, updates visited
         return bm + 8.0 * nU + 4.0 * scan + scan / 8.0 + bm + (8 + p) * nN + 3 * bm
+    if variant == L.PUSH_Q_FILTER:  # neighbours and sources go through the temporary list
+        return 20.0 * nF + 4.0 * eF + 16.0 * eF + eF / 8.0 + (8 + p) * nN + nN / 8.0
     if variant == L.PUSH_P3:  # frontier from two visited arrays; update also writes P_{k-1}
         return 2 * bm + 8.0 * nF + 4.0 * eF + eF / 8.0 + (4 + p) * nN + bm + 4.0 * nU + 3 * bm + 4.0 * nN
     raise ValueError(variant)

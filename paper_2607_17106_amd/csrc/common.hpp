@@ -19,6 +19,7 @@ constexpr int RING = 4;                  // per-level counter slots in flight
 constexpr int SCAN_CHUNK = 1024;         // merge path: entries per scan block
 constexpr int MERGE_TILE = 2048;         // merge path: edges per tile
 constexpr int MERGE_STAGE = 2304;        // merge path: frontier entries staged per tile
+
 constexpr int DEFAULT_HUB = 2048;        // block variant: degree above which a vertex is split grid-wide
 
 // Counters of one frontier F_k.  Producers add into one of NSH shards (chosen
@@ -77,6 +78,12 @@ struct alignas(64) LoopCtl {
 // Frontier queue: NSH segments of qcap entries, then an overflow area of n.
 inline int queue_cap(int n) { return (n + NSH - 1) / NSH; }
 inline size_t queue_entries(int n) { return (size_t)queue_cap(n) * NSH + (size_t)n; }
+// advance-then-filter: temporary list entries, n clamped to [2^16, 2^22] and
+// rounded up to whole merge tiles (chunks of the list start on a tile)
+inline int tmp_entries(int n) {
+  const int c = n < (1 << 16) ? (1 << 16) : (n > (1 << 22) ? (1 << 22) : n);
+  return (c + MERGE_TILE - 1) / MERGE_TILE * MERGE_TILE;
+}
 
 // Single-source workspace, carved from one caller buffer.
 struct Workspace {
@@ -94,6 +101,7 @@ struct Workspace {
   u64 *gsum;           // graph-level sums (ld, ld2), selector state, validation flag
   u64 *vis_prev;       // three-array visited strategy: P_{k-1} (valid while *p3_level == k)
   int *p3_level;
+  int *tmp_v, *tmp_u;  // advance-then-filter: temporary list (tmp_entries(n) entries)
   int W;               // bitmap words = ceil(n/64)
   int qcap;
 };
@@ -106,6 +114,7 @@ Workspace carve_single(void *base, int n);
 // discovers get depth k+1.
 struct StepArgs {
   int n, W, k, hub, qcap;
+  int nnz;                     // edges (bounds the advance-then-filter chunks when F_k's are unknown)
   int gate;                    // -1: always run (host loop); -2: run while F_k is non-empty;
                                // >= 0: run only if F_k is non-empty and its device decision is `gate`
   const int *rp, *ci;          // CSR
@@ -123,6 +132,8 @@ struct StepArgs {
   int *scan, *bsum, *hubs;
   u64 *vis_prev;               // PUSH_P3: P_{k-1} when *p3_level == k
   int *p3_level;
+  int *tmp_v, *tmp_u;          // PUSH_Q_FILTER: neighbours and their sources
+  int tmpcap;                  // their entries (tmp_entries(n))
 };
 
 // ------------------------------------------------- per-thread host context

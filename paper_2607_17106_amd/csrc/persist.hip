@@ -164,6 +164,20 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs P) {
         ok = grid_sync(P.bar, epoch);
         if (ok) body_merge_vis(a);
         break;
+      case BFS_V_PUSH_Q_FILTER: {
+        body_merge_scan_local(a, smem);
+        ok = grid_sync(P.bar, epoch);
+        if (ok) body_merge_scan_chunks(a, smem);
+        ok = ok && grid_sync(P.bar, epoch);
+        const int chunks = ok ? (int)(((long long)a.c_cur->total_e + a.tmpcap - 1) / a.tmpcap) : 0;
+        for (int r = 0; ok && r < chunks; ++r) {  // uniform: every workgroup read the same total
+          body_push_merge<true, true>(a, smem, r);
+          ok = grid_sync(P.bar, epoch);
+          if (ok) body_filter_tmp(a, r);
+          ok = ok && grid_sync(P.bar, epoch);
+        }
+        break;
+      }
       case BFS_V_PUSH_P3:
         body_push_p3(a, smem);
         ok = grid_sync(P.bar, epoch);

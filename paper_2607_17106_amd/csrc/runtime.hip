@@ -54,6 +54,7 @@ size_t workspace_bytes_single(int n) {
   b += align256(GSUM_WORDS * 8);                     // gsum
   b += align256(W * 8);                              // vis_prev
   b += align256(sizeof(int));                        // p3_level
+  b += 2 * align256((size_t)tmp_entries(n) * 4);     // tmp_v, tmp_u
   return b;
 }
 
@@ -76,6 +77,8 @@ Workspace carve_single(void *base, int n) {
   w.gsum = (u64 *)take(GSUM_WORDS * 8);
   w.vis_prev = (u64 *)take(W * 8);
   w.p3_level = (int *)take(sizeof(int));
+  w.tmp_v = (int *)take((size_t)tmp_entries(n) * 4);
+  w.tmp_u = (int *)take((size_t)tmp_entries(n) * 4);
   w.W = (int)W;
   w.qcap = queue_cap(n);
   return w;
@@ -237,6 +240,10 @@ static StepArgs level_args(const bfs_graph *g, const Workspace &w, int *levels, 
   a.vis = w.vis;
   a.vis_prev = w.vis_prev;
   a.p3_level = w.p3_level;
+  a.tmp_v = w.tmp_v;
+  a.tmp_u = w.tmp_u;
+  a.tmpcap = tmp_entries(g->n);
+  a.nnz = g->nnz;
   a.fb_cur = w.fb[k % 3];
   a.fb_next = w.fb[(k + 1) % 3];
   a.fb_dead = w.fb[(k + 2) % 3];

@@ -376,17 +376,23 @@ __device__ __forceinline__ int wave_search_gt(const StepArgs &a, int count, int 
 
 // Pass 3: each tile of MERGE_TILE edges stages its frontier entries in LDS
 // and gives every lane an even share of the tile's edges.
-template <bool ATOM>
-__device__ __forceinline__ void body_push_merge(const StepArgs &a, char *smem) {
+// TMP (advance before the depth update, Table 3, variant 13): only the edges
+// [chunk * tmpcap, (chunk + 1) * tmpcap) of the flattened list, each written
+// with its source to the temporary list at its offset in the chunk; no
+// visited test and no atomics.
+template <bool ATOM, bool TMP = false>
+__device__ __forceinline__ void body_push_merge(const StepArgs &a, char *smem, int chunk = 0) {
   int *s_incl = reinterpret_cast<int *>(smem), *s_u = s_incl + MERGE_STAGE, *s_off = s_u + MERGE_STAGE;
   int *s_seg = s_off + MERGE_STAGE;
   int &s_i0 = s_seg[NSH + 2], &s_m = s_seg[NSH + 3];
   stage_seg(s_seg, a.seg_cur);
   NewStats st;
   const int count = (int)a.c_cur->count;
-  const int total = (int)a.c_cur->total_e;
-  const int ntiles = (int)a.c_cur->ntiles;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const int e_lo = TMP ? chunk * a.tmpcap : 0;
+  const int total = TMP ? (int)min((long long)a.c_cur->total_e, (long long)e_lo + a.tmpcap) : (int)a.c_cur->total_e;
+  const int t_lo = e_lo / MERGE_TILE;
+  const int ntiles = TMP ? (total > e_lo ? (total + MERGE_TILE - 1) / MERGE_TILE : t_lo) : (int)a.c_cur->ntiles;
+  for (int t = t_lo + blockIdx.x; t < ntiles; t += gridDim.x) {
     const int e0 = t * MERGE_TILE;
     const int e1 = min(total, e0 + MERGE_TILE);
     if (threadIdx.x < WAVE) {
@@ -427,11 +433,27 @@ __device__ __forceinline__ void body_push_merge(const StepArgs &a, char *smem) {
         int inc = merge_incl(a, lo);
         pos = a.rp[u] + e - (inc - (a.rp[u + 1] - a.rp[u]));
       }
-      visit_edge<ATOM>(a, u, a.ci[pos], st);
+      if (TMP) {
+        a.tmp_v[e - e_lo] = a.ci[pos];
+        a.tmp_u[e - e_lo] = u;
+      } else {
+        visit_edge<ATOM>(a, u, a.ci[pos], st);
+      }
       st.scanned++;
     }
     __syncthreads();
   }
+  st.flush(a.sh_next);
+}
+
+// Filter of variant 13: claims the entries of one chunk of the temporary list
+// as the atomic push claims an edge (visited test, depth, parent, F_{k+1}).
+__device__ __forceinline__ void body_filter_tmp(const StepArgs &a, int chunk) {
+  NewStats st;
+  const long long e_lo = (long long)chunk * a.tmpcap;
+  const int len = (int)max(0ll, min((long long)a.c_cur->total_e - e_lo, (long long)a.tmpcap));
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < len; i += gridDim.x * BLOCK)
+    visit_edge<true>(a, a.tmp_u[i], a.tmp_v[i], st);
   st.flush(a.sh_next);
 }
 

@@ -114,6 +114,18 @@ __global__ __launch_bounds__(BLOCK) void k_noatom_update(StepArgs a) {
   body_noatom_update(a);
 }
 
+// advance then filter (Table 3, variant 13), one chunk of the temporary list
+__global__ __launch_bounds__(BLOCK) void k_adv_tmp(StepArgs a, int chunk) {
+  __shared__ __align__(16) char smem[SM_MERGE];
+  if (gated_off(a)) return;
+  body_push_merge<true, true>(a, smem, chunk);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_filter_tmp(StepArgs a, int chunk) {
+  if (gated_off(a)) return;
+  body_filter_tmp(a, chunk);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_push_p3(StepArgs a) {
   __shared__ __align__(16) char smem[SM_PUSH_B];
   clear_dead(a);
@@ -331,6 +343,22 @@ hipError_t launch_step(int variant, const StepArgs &a, int count, long long edge
     case BFS_V_PULL_B:
       hipLaunchKernelGGL(k_pull<false>, dim3(std::max(g0, gw)), dim3(BLOCK), 0, s, a);
       break;
+    case BFS_V_PUSH_Q_FILTER: {
+      // chunks of the temporary list: F_k's edge total when the host knows it,
+      // else every chunk the graph could need (those past the total exit at once)
+      int nchunk = cdiv(count, SCAN_CHUNK);
+      hipLaunchKernelGGL(k_merge_scan_local, dim3(std::max(g0, clampi(nchunk, 1, GMAX))), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL(k_merge_scan_chunks, dim3(1), dim3(BLOCK), 0, s, a);
+      const long long span = dev ? (long long)a.nnz : edges;
+      const int chunks = (int)std::max(1ll, (span + a.tmpcap - 1) / a.tmpcap);
+      const int ge = clampi(cdiv(std::min(span, (long long)a.tmpcap), MERGE_TILE), 1, GMAX);
+      const int gf = clampi(cdiv(std::min(span, (long long)a.tmpcap), BLOCK), 1, GMAX);
+      for (int r = 0; r < chunks; ++r) {
+        hipLaunchKernelGGL(k_adv_tmp, dim3(ge), dim3(BLOCK), 0, s, a, r);
+        hipLaunchKernelGGL(k_filter_tmp, dim3(gf), dim3(BLOCK), 0, s, a, r);
+      }
+      break;
+    }
     case BFS_V_PUSH_P3:
       hipLaunchKernelGGL(k_push_p3, dim3(std::max(g0, gw)), dim3(BLOCK), 0, s, a);
       hipLaunchKernelGGL(k_push_hubs<false>, dim3(ghub), dim3(BLOCK), 0, s, a);

@@ -218,7 +218,8 @@ def test_push_scanned_equals_frontier_edges():
     g = gg.workload("rmat14")
     dg = B.DeviceGraph.from_graph(g)
     (s,) = gg.pick_sources(g, 1, 1402)
-    for v in (B.PUSH_Q_THREAD, B.PUSH_Q_BLOCK, B.PUSH_Q_MERGE, B.PUSH_B_ATOMIC, B.PUSH_B_NOATOMIC, B.PUSH_P3):
+    for v in (B.PUSH_Q_THREAD, B.PUSH_Q_BLOCK, B.PUSH_Q_MERGE, B.PUSH_B_ATOMIC, B.PUSH_B_NOATOMIC, B.PUSH_P3,
+              B.PUSH_Q_FILTER):
         _, _, st = _run(dg, g, s, v, level_stats=True)
         np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
         np.testing.assert_array_equal(st["next"][:-1], st["frontier"][1:])
@@ -272,3 +273,17 @@ def test_device_loop_timing_fills_level_ms():
     for fl in (0, B.F_DEVICE_LOOP):
         _, st = B.bfs_levels(dg, int(s), variant=B.AUTO_HEURISTIC, flags=B.F_LEVEL_TIMING | fl)
         assert (st["ms"] > 0).all() and len(st["ms"]) == st["num_levels"]
+
+
+def test_filter_variant_many_chunks():
+    """Advance then filter with frontiers whose edges fill the temporary list
+    many times over (R-MAT 16: 65,536 entries against levels of ~1.5M edges),
+    host loop and device loop; scanned edges are the frontier's out-edges."""
+    g = gg.rmat(16, seed=1616)
+    dg = B.DeviceGraph.from_graph(g)
+    (s,) = gg.pick_sources(g, 1, 17)
+    for flags in (0, B.F_DEVICE_LOOP):
+        lv, par, st = _run(dg, g, s, B.PUSH_Q_FILTER, flags=flags, level_stats=True)
+        _check(g, s, lv, par, f"flags {flags}")
+        assert int(st["frontier_edges"].max()) > 8 * 65536
+        np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
