@@ -118,6 +118,10 @@ int bfs_version(void);
 #define BFS_F_GRAPH_SUMS 32      /* options.graph_ld / graph_ld2 hold the graph-wide
                                     feature sums (from bfs_graph_sums): the call uses
                                     them instead of recomputing them over all vertices */
+#define BFS_F_HUB_ORDER 64       /* bfs_multi: the graph is numbered by decreasing degree
+                                    (bfs_reorder_degree), so the frontier bits its
+                                    bottom-up steps read most often stay in cache and
+                                    they skip the LDS frontier summary (speed only) */
 
 /* ----------------------------------------------------------------- types */
 typedef struct bfs_graph {
@@ -143,7 +147,7 @@ typedef struct bfs_options {
   size_t workspace_bytes;
   int64_t graph_ld, graph_ld2;   /* with BFS_F_GRAPH_SUMS: the values bfs_graph_sums returned */
   const int32_t *vertex_map;     /* device [n] or NULL.  Set: the graph is a renumbered copy
-                                    (bfs_reorder_degree) and vertex_map[v] is the new id of
+                                    (bfs_reorder_degree, bfs_reorder_rcm) and vertex_map[v] is the new id of
                                     original vertex v (its new_of_old); sources and depths are
                                     then in the original numbering.  bfs_multi only: the other
                                     calls return BFS_ENOTSUP when it is set */
@@ -204,6 +208,21 @@ int bfs_graph_sums(const bfs_graph *g, int64_t *ld, int64_t *ld2, void *stream);
 int bfs_reorder_degree(const bfs_graph *g, int32_t *out_row_ptr, int32_t *out_col_idx,
                        int32_t *out_csc_ptr, int32_t *out_csc_idx, int32_t *new_of_old,
                        int32_t *old_of_new, void *stream);
+
+/* The same outputs for reverse Cuthill-McKee, the renumbering the paper
+ * applies to every graph (Sec. "Experiment Setup").  The paper does not
+ * state its variant; this one works on the undirected structure (out-edges,
+ * plus in-edges for a graph with its own CSC), deg(v) = the number of such
+ * entries of v, and takes vertices in (deg, id) order: each component
+ * starts at its remaining vertex first in that order, each visited vertex
+ * appends its unvisited neighbours in that order (breadth first), and the
+ * whole order is reversed.  The ordering pass runs on the host (one pass over
+ * a copy of the graph); the rest, and the renumbering, on the GPU.
+ * Validates the graph first; allocates as bfs_reorder_degree does, plus host
+ * memory for a copy of the graph; synchronises the stream. */
+int bfs_reorder_rcm(const bfs_graph *g, int32_t *out_row_ptr, int32_t *out_col_idx,
+                    int32_t *out_csc_ptr, int32_t *out_csc_idx, int32_t *new_of_old,
+                    int32_t *old_of_new, void *stream);
 
 /* Workspace bytes for a graph of n vertices.  lanes = 1 for bfs_levels /
  * bfs_parents, 2..64 for bfs_multi (bit-packed lanes, u64 words per vertex). */

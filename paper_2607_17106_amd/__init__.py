@@ -8,10 +8,10 @@ does, and fails loudly when it is not built.
 from ._lib import (  # noqa: F401
     PUSH_Q_THREAD, PUSH_Q_BLOCK, PUSH_Q_MERGE, PUSH_B_ATOMIC, PUSH_B_NOATOMIC, PUSH_Q_NOATOMIC, PULL_B, PULL_VIS, PUSH_P3, PUSH_Q_FILTER,
     NUM_VARIANTS, AUTO_HEURISTIC, AUTO_LEARNED, SCHEDULE, VARIANT_NAMES, F_VALIDATE, F_STRICT_SELECTOR,
-    F_LEVEL_STATS, F_DEVICE_LOOP, F_LEVEL_TIMING, BfsError, load,
+    F_LEVEL_STATS, F_DEVICE_LOOP, F_LEVEL_TIMING, F_GRAPH_SUMS, F_HUB_ORDER, BfsError, load,
 )
 from .api import (  # noqa: F401
     DeviceGraph, DeviceBatch, bfs_levels, bfs_parents, bfs_multi, bfs_batch, bfs_batch_autotune,
     workspace_size, selector_set, selector_clear, selector_loaded, mlp_forward, mlp_loss_grad, mlp_adam,
-    mlp_predict, level_features, step_time, reorder_degree,
+    mlp_predict, level_features, step_time, reorder_degree, reorder_rcm,
 )

@@ -48,6 +48,7 @@ F_LEVEL_STATS = 4
 F_DEVICE_LOOP = 8
 F_LEVEL_TIMING = 16
 F_GRAPH_SUMS = 32
+F_HUB_ORDER = 64
 
 MLP_NPARAM = 5252
 MLP_NFEAT = 12
@@ -97,6 +98,7 @@ SIGNATURES = {
     "bfs_version": (c_int32, []),
     "bfs_workspace_size": (c_int32, [c_int32, c_int32, POINTER(c_size_t)]),
     "bfs_reorder_degree": (c_int32, [POINTER(BfsGraph)] + [c_void_p] * 7),
+    "bfs_reorder_rcm": (c_int32, [POINTER(BfsGraph)] + [c_void_p] * 7),
     "bfs_graph_sums": (c_int32, [POINTER(BfsGraph), POINTER(c_int64), POINTER(c_int64), c_void_p]),
     "bfs_levels": (c_int32, [POINTER(BfsGraph), c_int32, c_void_p, POINTER(BfsOptions), POINTER(BfsStats),
                              c_void_p]),

@@ -76,10 +76,7 @@ class DeviceGraph:
         return self._gsums
 
 
-def reorder_degree(g: DeviceGraph, stream=None):
-    """bfs_reorder_degree: the graph renumbered by decreasing out-degree.
-    Returns (renumbered DeviceGraph, new_of_old, old_of_new), the maps as
-    device int32 tensors; pass new_of_old as bfs_multi's vertex_map."""
+def _reorder(fn_name, g: DeviceGraph, stream):
     dev = g.row_ptr.device
     i32 = dict(dtype=torch.int32, device=dev)
     rp, ci = torch.empty(g.n + 1, **i32), torch.empty(max(g.nnz, 1), **i32)
@@ -87,15 +84,31 @@ def reorder_degree(g: DeviceGraph, stream=None):
     cp = torch.empty(g.n + 1, **i32) if own_csc else None
     cx = torch.empty(max(g.nnz, 1), **i32) if own_csc else None
     new_of_old, old_of_new = torch.empty(g.n, **i32), torch.empty(g.n, **i32)
-    rc = L.load().bfs_reorder_degree(g.c, _ptr(rp), _ptr(ci), _ptr(cp), _ptr(cx), _ptr(new_of_old),
-                                     _ptr(old_of_new), _stream(stream))
-    L.check(rc, "bfs_reorder_degree")
+    rc = getattr(L.load(), fn_name)(g.c, _ptr(rp), _ptr(ci), _ptr(cp), _ptr(cx), _ptr(new_of_old),
+                                    _ptr(old_of_new), _stream(stream))
+    L.check(rc, fn_name)
     ci = ci[:g.nnz]
     if own_csc:
         out = DeviceGraph(g.n, rp, ci, cp, cx[:g.nnz], symmetric=False, device=dev)
     else:
         out = DeviceGraph(g.n, rp, ci, symmetric=g.symmetric, device=dev)
     return out, new_of_old, old_of_new
+
+
+def reorder_degree(g: DeviceGraph, stream=None):
+    """bfs_reorder_degree: the graph renumbered by decreasing out-degree.
+    Returns (renumbered DeviceGraph, new_of_old, old_of_new), the maps as
+    device int32 tensors; pass new_of_old as bfs_multi's vertex_map.  The
+    returned graph is marked hub_order (bfs_multi then sets F_HUB_ORDER)."""
+    out, n2o, o2n = _reorder("bfs_reorder_degree", g, stream)
+    out.hub_order = True
+    return out, n2o, o2n
+
+
+def reorder_rcm(g: DeviceGraph, stream=None):
+    """bfs_reorder_rcm: the graph renumbered by reverse Cuthill-McKee (same
+    return values as reorder_degree)."""
+    return _reorder("bfs_reorder_rcm", g, stream)
 
 
 def workspace_size(n: int, lanes: int = 1) -> int:
@@ -267,6 +280,8 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
     if level_stats:
         flags |= L.F_LEVEL_STATS
     sb = _StatsBuf.get(stats_capacity if level_stats else 0)
+    if getattr(g, "hub_order", False):
+        flags |= L.F_HUB_ORDER
     opt, keep = _options(variant, flags, None, workspace, 0, None)
     if vertex_map is not None:
         if vertex_map.dtype != torch.int32 or vertex_map.numel() != g.n or not vertex_map.is_contiguous():

@@ -1269,7 +1269,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         // renumbered by degree: there most in-edges come from the first few
         // hundred KB of bitmap, which stay in cache, and the 32 KB of LDS per
         // workgroup would cost more in occupancy than the filter saves.
-        const bool filt = a.vmap == nullptr;
+        const bool filt = !(flags & BFS_F_HUB_ORDER);
         const bool sum = filt && (nf << a.sshift) * 8 < (long long)n;
         const bool hsum = filt && (nf << a.sshift) * 64 < (long long)n;
         if (sum)

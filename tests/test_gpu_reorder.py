@@ -1,5 +1,5 @@
-"""GPU parity of the degree renumbering (bfs_reorder_degree) and of the
-multi-source search run on a renumbered graph through options.vertex_map.
+"""GPU parity of the renumberings (bfs_reorder_degree, bfs_reorder_rcm) and of
+the multi-source search run on a renumbered graph through options.vertex_map.
 
 * the maps and the renumbered CSR / CSC equal the oracle's (oracle/reorder.py)
   element by element: the order and the sorted rows are unique;
@@ -139,3 +139,56 @@ def test_rmat22_64_sources_renumbered_sampled_rows():
         assert np.all((a < 0) == (b < 0)), f"row {i}: an edge leaves the reached set (symmetric graph)"
         reached = a >= 0
         assert np.all(np.abs(a[reached] - b[reached]) <= 1), f"row {i}: an edge spans two levels"
+
+
+# ------------------------------------------------------------- RCM
+@pytest.mark.parametrize("name,g", list(_graphs()))
+def test_rcm_matches_oracle(name, g):
+    dg = B.DeviceGraph.from_graph(g)
+    rg, new_of_old, old_of_new = B.reorder_rcm(dg)
+    if g.symmetric:
+        n2o, o2n = ro.rcm_order(g.row_ptr, g.col_idx)
+    else:
+        g.with_csc()
+        n2o, o2n = ro.rcm_order(g.row_ptr, g.col_idx, g.csc_ptr, g.csc_idx)
+    np.testing.assert_array_equal(old_of_new.cpu().numpy(), o2n, err_msg=name)
+    np.testing.assert_array_equal(new_of_old.cpu().numpy(), n2o, err_msg=name)
+    rp, ci = ro.renumber(g.row_ptr, g.col_idx, n2o)
+    np.testing.assert_array_equal(rg.row_ptr.cpu().numpy(), rp, err_msg=name)
+    np.testing.assert_array_equal(rg.col_idx.cpu().numpy(), ci, err_msg=name)
+    if not g.symmetric:
+        cp, cx = ro.renumber(g.csc_ptr, g.csc_idx, n2o)
+        np.testing.assert_array_equal(rg.csc_ptr.cpu().numpy(), cp, err_msg=name)
+        np.testing.assert_array_equal(rg.csc_idx.cpu().numpy(), cx, err_msg=name)
+    assert not getattr(rg, "hub_order", False)
+
+
+@pytest.mark.parametrize("variant", MODES)
+def test_rcm_mapped_multi_matches_oracle(variant):
+    for g, srcs in ((gg.rmat(12, seed=77), None), (gg.directed_random(3000, 15000, seed=4), np.arange(0, 3000, 47)[:64]),
+                    (gg.lattice(90, seed=3), None)):
+        if srcs is None:
+            srcs = gg.pick_sources(g, 64, 6)
+        dg = B.DeviceGraph.from_graph(g)
+        rg, new_of_old, _ = B.reorder_rcm(dg)
+        lv, st = B.bfs_multi(rg, srcs, variant=variant, vertex_map=new_of_old)
+        ref = oracle.multi(g.row_ptr, g.col_idx, srcs)
+        np.testing.assert_array_equal(lv.cpu().numpy(), ref)
+
+
+def test_rcm_rmat22_sampled_rows():
+    """R-MAT scale 22 renumbered by RCM, its 64 sources through vertex_map:
+    rows sampled against the oracle on the original graph."""
+    g = gg.workload("rmat22")
+    nsrc, sseed = gg.WORKLOAD_SOURCES["rmat22"]
+    srcs = gg.pick_sources(g, nsrc, sseed)
+    dg = B.DeviceGraph.from_graph(g)
+    rg, new_of_old, old_of_new = B.reorder_rcm(dg)
+    del dg
+    o2n = old_of_new.cpu().numpy()
+    assert np.array_equal(np.sort(o2n), np.arange(g.n))
+    lv, st = B.bfs_multi(rg, srcs, vertex_map=new_of_old)
+    lv = lv.cpu().numpy()
+    for i in (0, 40):
+        np.testing.assert_array_equal(lv[i], oracle.bfs(g.row_ptr, g.col_idx, int(srcs[i]), want_parents=False)[0],
+                                      err_msg=f"row {i}")
