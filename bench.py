@@ -10,7 +10,8 @@ job -- on the graph renumbered by decreasing out-degree (bfs_reorder_degree,
 a preprocessing step like the paper's own renumbering of every graph; its
 time is reported as config.reorder_ms), with sources and depths in the
 original numbering (options.vertex_map).  The same search on the graph as
-generated is reported as input_order.  Inputs are resident in HBM before the
+generated is reported as input_order, and on the graph renumbered by reverse
+Cuthill-McKee (the paper's own preprocessing) as rcm_order.  Inputs are resident in HBM before the
 timed region.  The same JSON line
 also reports, on the same graph and sources, the single-source forms (learned
 per-level selector, direction heuristic, every fixed variant) and the
@@ -48,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 # (comments and whitespace aside) hashes to the values the counters were taken with.
 TILE_TRAFFIC = {
     "sources_sha256": {
-        "paper_2607_17106_amd/csrc/msbfs.hip": "2a05a83ed8765be9fc8b12dba417b7a4aad031716f8f335cc36d1282ad191c32",
-        "paper_2607_17106_amd/csrc/common.hpp": "6e8a2114d3d2cc4c774668c53444e4a657d7449b3c846475ba232df551526fad",
+        "paper_2607_17106_amd/csrc/msbfs.hip": "55621361af98d60f0a2aedb762112dc75a6cb482b09889d12a13cefc4de87574",
+        "paper_2607_17106_amd/csrc/common.hpp": "75fd6210cda1c9516901c13c241ebfdff41a6944840c36e3bbf27a58f0bdc9de",
     },
-    "fetch_kib": 175400.6, "write_kib": 107502.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 176772.2, "write_kib": 107713.5, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
@@ -134,7 +135,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch")
     ap.add_argument("--sweep-sources", type=int, default=16)
     ap.add_argument("--no-input-order", action="store_true",
-                    help="skip the comparison run on the graph as generated (profiles see the timed step only)")
+                    help="skip the comparison runs on the graph as generated and renumbered by RCM "
+                         "(profiles see the timed step only)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times): the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters, then exit")
@@ -189,7 +191,7 @@ def main():
     gteps = sum(st["component_edges"] for st in stats) / 2 / elapsed / 1e9
 
     # the same search on the graph as generated (no renumbering), for comparison
-    input_order = None
+    input_order = rcm_order = None
     if not args.no_input_order:
         step(False, dg, None)
         torch.cuda.synchronize()
@@ -200,6 +202,18 @@ def main():
         input_order = {"gteps": round(sum(st["component_edges"] for st in st_in) / 2 / el_in / 1e9, 3),
                        "ms_per_step": round(el_in * 1e3 / args.steps, 3)}
         log(f"[bench] input order: {input_order}")
+        # and on the graph renumbered by reverse Cuthill-McKee
+        (cg, cmap, _), rcm_s = timed(lambda: B.reorder_rcm(dg))
+        step(False, cg, cmap)
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        st_c = [step(False, cg, cmap) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        el_c = time.perf_counter() - t_c
+        rcm_order = {"gteps": round(sum(st["component_edges"] for st in st_c) / 2 / el_c / 1e9, 3),
+                     "ms_per_step": round(el_c * 1e3 / args.steps, 3), "reorder_ms": round(rcm_s * 1e3, 1)}
+        log(f"[bench] rcm order: {rcm_order}")
+        del cg, cmap
 
     # roofline of the dominant kernel: the bottom-up tile kernel (k_ms_pull_tile),
     # timed alone by the library's HIP events on its stream, priced by its own
@@ -245,7 +259,7 @@ def main():
                       "vertex_order": "renumbered by decreasing out-degree (bfs_reorder_degree, preprocessing, "
                                       "outside the timed region); sources and depths in the original numbering",
                       "reorder_ms": round(reorder_s * 1e3, 2)},
-           "roofline": roof, "input_order": input_order}
+           "roofline": roof, "input_order": input_order, "rcm_order": rcm_order}
 
     # ------------------------------------------- single-source comparisons
     if not args.no_sweep:
