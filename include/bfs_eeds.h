@@ -88,6 +88,8 @@ int bfs_version(void);
  *                  atomics), then a filter pass claims each entry as the atomic
  *                  push does; the list holds tmp_entries(n) entries (n clamped
  *                  to [2^16, 2^22]), larger frontiers go in chunks
+ *  PUSH_B_FILTER   the same with a bitmap frontier (Table 3, variant 14): the
+ *                  edge space is flattened word by word over the bitmap
  * Every step emits the next frontier both as a queue and as a bitmap, so the
  * format of the next level is a free choice.
  */
@@ -101,7 +103,8 @@ int bfs_version(void);
 #define BFS_V_PULL_VIS 7         /* same depths, parents and scan lengths as BFS_V_PULL_B */
 #define BFS_V_PUSH_P3 8
 #define BFS_V_PUSH_Q_FILTER 9
-#define BFS_NUM_VARIANTS 10
+#define BFS_V_PUSH_B_FILTER 10
+#define BFS_NUM_VARIANTS 11
 /* Per-level choice modes. */
 #define BFS_AUTO_HEURISTIC 100 /* Beamer direction-optimising rule (alpha 14, beta 24) */
 #define BFS_AUTO_LEARNED 101   /* selector network on device; heuristic fallback */

@@ -29,7 +29,8 @@ PULL_B = 6
 PULL_VIS = 7
 PUSH_P3 = 8
 PUSH_Q_FILTER = 9
-NUM_VARIANTS = 10
+PUSH_B_FILTER = 10
+NUM_VARIANTS = 11
 AUTO_HEURISTIC = 100
 AUTO_LEARNED = 101
 SCHEDULE = 102
@@ -38,7 +39,7 @@ VARIANT_NAMES = {
     PUSH_Q_THREAD: "push_q_thread", PUSH_Q_BLOCK: "push_q_block", PUSH_Q_MERGE: "push_q_merge",
     PUSH_B_ATOMIC: "push_b_atomic", PUSH_B_NOATOMIC: "push_b_noatomic",
     PUSH_Q_NOATOMIC: "push_q_noatomic", PULL_B: "pull_b", PULL_VIS: "pull_vis",
-    PUSH_P3: "push_p3", PUSH_Q_FILTER: "push_q_filter",
+    PUSH_P3: "push_p3", PUSH_Q_FILTER: "push_q_filter", PUSH_B_FILTER: "push_b_filter",
     AUTO_HEURISTIC: "heuristic", AUTO_LEARNED: "learned", SCHEDULE: "schedule",
 }
 

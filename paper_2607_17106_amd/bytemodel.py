@@ -23,6 +23,7 @@ Per variant (p = 4 when parents are written, else 0):
                                   + (4+p)nN + update pass: n/8 + 4nU + 3n/8 + 4nN
   push, advance then filter       20nF (queue, offsets, degree scan) + 4eF + 8eF (list
                                   written) + 8eF (read back) + eF/8 + (8+p)nN + nN/8
+  (bitmap frontier)               2n/8 + 16nF + 4W (word scan) + the same per edge and nN
 """
 from __future__ import annotations
 
@@ -48,6 +49,8 @@ def step_bytes(variant: int, n: int, nF: int, eF: int, nU: int, nN: int, scan: i
         return bm + 8.0 * nU + 4.0 * scan + scan / 8.0 + bm + (8 + p) * nN + 3 * bm
     if variant == L.PUSH_Q_FILTER:  # neighbours and sources go through the temporary list
         return 20.0 * nF + 4.0 * eF + 16.0 * eF + eF / 8.0 + (8 + p) * nN + nN / 8.0
+    if variant == L.PUSH_B_FILTER:  # word weights scanned, then the same list
+        return 2 * bm + 16.0 * nF + 4.0 * (n / 64.0) + 4.0 * eF + 16.0 * eF + eF / 8.0 + (8 + p) * nN + nN / 8.0
     if variant == L.PUSH_P3:  # frontier from two visited arrays; update also writes P_{k-1}
         return 2 * bm + 8.0 * nF + 4.0 * eF + eF / 8.0 + (4 + p) * nN + bm + 4.0 * nU + 3 * bm + 4.0 * nN
     raise ValueError(variant)

@@ -178,6 +178,20 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs P) {
         }
         break;
       }
+      case BFS_V_PUSH_B_FILTER: {
+        body_wscan_local(a, smem);
+        ok = grid_sync(P.bar, epoch);
+        if (ok) body_merge_scan_chunks(a, smem, true);
+        ok = ok && grid_sync(P.bar, epoch);
+        const int chunks = ok ? (int)(((long long)a.c_cur->total_e + a.tmpcap - 1) / a.tmpcap) : 0;
+        for (int r = 0; ok && r < chunks; ++r) {  // uniform: every workgroup read the same total
+          body_adv_tmp_b(a, smem, r);
+          ok = grid_sync(P.bar, epoch);
+          if (ok) body_filter_tmp(a, r);
+          ok = ok && grid_sync(P.bar, epoch);
+        }
+        break;
+      }
       case BFS_V_PUSH_P3:
         body_push_p3(a, smem);
         ok = grid_sync(P.bar, epoch);

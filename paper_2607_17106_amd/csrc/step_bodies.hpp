@@ -16,6 +16,7 @@ constexpr int SM_SCAN_LOCAL = (BLOCK / WAVE + NSH + 2) * 4;
 constexpr int SM_SCAN_CHUNKS = (BLOCK / WAVE) * 4;
 constexpr int SM_MERGE = (3 * MERGE_STAGE + NSH + 2 + 2) * 4;
 constexpr int SM_PUSH_B = 3 * BLOCK * 4;
+constexpr int SM_ADV_B = (3 * BLOCK + 2) * 4;
 constexpr int SM_FINISH = 5 * (NSH / WAVE) * 8 + (NSH / WAVE) * 4;
 constexpr int SM_MAX = SM_MERGE;
 static_assert(SM_MERGE >= SM_BLOCK && SM_MERGE >= SM_FINISH, "SM_MAX must cover every body");
@@ -321,13 +322,47 @@ __device__ __forceinline__ void body_merge_scan_local(const StepArgs &a, char *s
   }
 }
 
+// Pass 1 over bitmap words instead (advance then filter with a bitmap
+// frontier, Table 3, variant 14): entry w weighs the out-degrees of the
+// frontier members in word w of F_k.
+__device__ __forceinline__ void body_wscan_local(const StepArgs &a, char *smem) {
+  int *s_w = reinterpret_cast<int *>(smem);
+  constexpr int IT = SCAN_CHUNK / BLOCK;
+  const int nchunk = (a.W + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  for (int c = blockIdx.x; c < nchunk; c += gridDim.x) {
+    const int base = c * SCAN_CHUNK + threadIdx.x * IT;
+    int d[IT];
+    int run = 0;
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+      const int w = base + t;
+      int dd = 0;
+      if (w < a.W) {
+        for (u64 fw = a.fb_cur[w]; fw; fw &= fw - 1) {
+          const int v = w * WAVE + __ffsll((long long)fw) - 1;
+          dd += a.rp[v + 1] - a.rp[v];
+        }
+      }
+      run += dd;
+      d[t] = run;
+    }
+    int total;
+    int off = block_excl_scan(run, &total, s_w);
+#pragma unroll
+    for (int t = 0; t < IT; ++t)
+      if (base + t < a.W) a.scan[base + t] = off + d[t];
+    if (threadIdx.x == 0) a.bsum[c] = total;
+  }
+}
+
 // Pass 2 (one workgroup): exclusive prefix of the chunk totals, the frontier's
-// edge total and the tile count.
+// edge total and the tile count, over `count` entries (queue entries, or
+// bitmap words when count < 0).
 // Runs in workgroup 0 only (other workgroups return at once).
-__device__ __forceinline__ void body_merge_scan_chunks(const StepArgs &a, char *smem) {
+__device__ __forceinline__ void body_merge_scan_chunks(const StepArgs &a, char *smem, bool words = false) {
   if (blockIdx.x != 0) return;
   int *s_w = reinterpret_cast<int *>(smem);
-  const int count = (int)a.c_cur->count;
+  const int count = words ? a.W : (int)a.c_cur->count;
   const int nchunk = (count + SCAN_CHUNK - 1) / SCAN_CHUNK;
   int carry = 0;
   for (int c0 = 0; c0 < nchunk; c0 += BLOCK) {
@@ -440,6 +475,67 @@ __device__ __forceinline__ void body_push_merge(const StepArgs &a, char *smem, i
         visit_edge<ATOM>(a, u, a.ci[pos], st);
       }
       st.scanned++;
+    }
+    __syncthreads();
+  }
+  st.flush(a.sh_next);
+}
+
+// Advance of variant 14: the edges [chunk * tmpcap, (chunk + 1) * tmpcap) of
+// the flattened list of the bitmap frontier's out-edges (word by word, bits
+// in order) go to the temporary list at their offset in the chunk.  A tile of
+// MERGE_TILE edges finds its first and last word by the 64-ary wave search;
+// its waves take those words in turn and write only the tile's positions of
+// each, so a word holding a hub is split across as many tiles as it spans.
+__device__ __forceinline__ void body_adv_tmp_b(const StepArgs &a, char *smem, int chunk) {
+  int *s_incl = reinterpret_cast<int *>(smem), *s_u = s_incl + BLOCK, *s_off = s_u + BLOCK;
+  int *s_rng = s_off + BLOCK;
+  NewStats st;
+  const int wv = threadIdx.x / WAVE;
+  int *incl = s_incl + wv * WAVE;
+  int *su = s_u + wv * WAVE;
+  int *so = s_off + wv * WAVE;
+  const int e_lo = chunk * a.tmpcap;
+  const int total = (int)min((long long)a.c_cur->total_e, (long long)e_lo + a.tmpcap);
+  const int t_lo = e_lo / MERGE_TILE;
+  const int ntiles = total > e_lo ? (total + MERGE_TILE - 1) / MERGE_TILE : t_lo;
+  for (int t = t_lo + blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int e0 = t * MERGE_TILE;
+    const int e1 = min(total, e0 + MERGE_TILE);
+    if (threadIdx.x < WAVE) {
+      const int w0 = wave_search_gt(a, a.W, e0);
+      const int w1 = wave_search_gt(a, a.W, e1 - 1);
+      if (lane() == 0) {
+        s_rng[0] = w0;
+        s_rng[1] = w1;
+      }
+    }
+    __syncthreads();
+    const int w0 = s_rng[0], w1 = s_rng[1];
+    for (int w = w0 + wv; w <= w1; w += BLOCK / WAVE) {  // uniform per wave
+      const u64 fw = a.fb_cur[w];
+      const int wend = merge_incl(a, w);  // flattened edges before the end of word w
+      const int v = w * WAVE + lane();
+      int beg = 0, d = 0;
+      if ((fw >> lane()) & 1ull) {
+        beg = a.rp[v];
+        d = a.rp[v + 1] - beg;
+      }
+      const int in = wave_incl_scan(d);
+      const int wt = __shfl(in, WAVE - 1);
+      const int wbase = wend - wt;
+      incl[lane()] = in;
+      su[lane()] = v;
+      so[lane()] = beg - (in - d);
+      __builtin_amdgcn_wave_barrier();
+      const int lo = max(e0, wbase) - wbase, hi = min(e1, wend) - wbase;
+      for (int e = lo + lane(); e < hi; e += WAVE) {
+        const int j = find_owner(incl, WAVE, e);
+        a.tmp_v[wbase + e - e_lo] = a.ci[so[j] + e];
+        a.tmp_u[wbase + e - e_lo] = su[j];
+        st.scanned++;
+      }
+      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
   }

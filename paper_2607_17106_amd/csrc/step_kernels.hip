@@ -88,6 +88,25 @@ __global__ __launch_bounds__(BLOCK) void k_merge_scan_local(StepArgs a) {
   body_merge_scan_local(a, smem);
 }
 
+__global__ __launch_bounds__(BLOCK) void k_wscan_local(StepArgs a) {
+  __shared__ __align__(16) char smem[SM_SCAN_LOCAL];
+  clear_dead(a);
+  if (gated_off(a)) return;
+  body_wscan_local(a, smem);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_wscan_chunks(StepArgs a) {
+  __shared__ __align__(16) char smem[SM_SCAN_CHUNKS];
+  if (gated_off(a)) return;
+  body_merge_scan_chunks(a, smem, true);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adv_tmp_b(StepArgs a, int chunk) {
+  __shared__ __align__(16) char smem[SM_ADV_B];
+  if (gated_off(a)) return;
+  body_adv_tmp_b(a, smem, chunk);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_merge_scan_chunks(StepArgs a) {
   __shared__ __align__(16) char smem[SM_SCAN_CHUNKS];
   if (gated_off(a)) return;
@@ -355,6 +374,21 @@ hipError_t launch_step(int variant, const StepArgs &a, int count, long long edge
       const int gf = clampi(cdiv(std::min(span, (long long)a.tmpcap), BLOCK), 1, GMAX);
       for (int r = 0; r < chunks; ++r) {
         hipLaunchKernelGGL(k_adv_tmp, dim3(ge), dim3(BLOCK), 0, s, a, r);
+        hipLaunchKernelGGL(k_filter_tmp, dim3(gf), dim3(BLOCK), 0, s, a, r);
+      }
+      break;
+    }
+    case BFS_V_PUSH_B_FILTER: {
+      // as PUSH_Q_FILTER, the edge space flattened over bitmap words
+      const int nwchunk = cdiv(a.W, SCAN_CHUNK);
+      hipLaunchKernelGGL(k_wscan_local, dim3(std::max(g0, clampi(nwchunk, 1, GMAX))), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL(k_wscan_chunks, dim3(1), dim3(BLOCK), 0, s, a);
+      const long long span = dev ? (long long)a.nnz : edges;
+      const int chunks = (int)std::max(1ll, (span + a.tmpcap - 1) / a.tmpcap);
+      const int ge = clampi(cdiv(std::min(span, (long long)a.tmpcap), MERGE_TILE), 1, GMAX);
+      const int gf = clampi(cdiv(std::min(span, (long long)a.tmpcap), BLOCK), 1, GMAX);
+      for (int r = 0; r < chunks; ++r) {
+        hipLaunchKernelGGL(k_adv_tmp_b, dim3(ge), dim3(BLOCK), 0, s, a, r);
         hipLaunchKernelGGL(k_filter_tmp, dim3(gf), dim3(BLOCK), 0, s, a, r);
       }
       break;

@@ -219,7 +219,7 @@ def test_push_scanned_equals_frontier_edges():
     dg = B.DeviceGraph.from_graph(g)
     (s,) = gg.pick_sources(g, 1, 1402)
     for v in (B.PUSH_Q_THREAD, B.PUSH_Q_BLOCK, B.PUSH_Q_MERGE, B.PUSH_B_ATOMIC, B.PUSH_B_NOATOMIC, B.PUSH_P3,
-              B.PUSH_Q_FILTER):
+              B.PUSH_Q_FILTER, B.PUSH_B_FILTER):
         _, _, st = _run(dg, g, s, v, level_stats=True)
         np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
         np.testing.assert_array_equal(st["next"][:-1], st["frontier"][1:])
@@ -275,7 +275,8 @@ def test_device_loop_timing_fills_level_ms():
         assert (st["ms"] > 0).all() and len(st["ms"]) == st["num_levels"]
 
 
-def test_filter_variant_many_chunks():
+@pytest.mark.parametrize("variant", [B.PUSH_Q_FILTER, B.PUSH_B_FILTER])
+def test_filter_variant_many_chunks(variant):
     """Advance then filter with frontiers whose edges fill the temporary list
     many times over (R-MAT 16: 65,536 entries against levels of ~1.5M edges),
     host loop and device loop; scanned edges are the frontier's out-edges."""
@@ -283,7 +284,7 @@ def test_filter_variant_many_chunks():
     dg = B.DeviceGraph.from_graph(g)
     (s,) = gg.pick_sources(g, 1, 17)
     for flags in (0, B.F_DEVICE_LOOP):
-        lv, par, st = _run(dg, g, s, B.PUSH_Q_FILTER, flags=flags, level_stats=True)
+        lv, par, st = _run(dg, g, s, variant, flags=flags, level_stats=True)
         _check(g, s, lv, par, f"flags {flags}")
         assert int(st["frontier_edges"].max()) > 8 * 65536
         np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
