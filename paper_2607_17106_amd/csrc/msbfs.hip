@@ -102,6 +102,8 @@ struct MsArgs {
   int ocount, ochunks;
   int *levels;          // row l at levels + l * n
   const int *vmap;      // or null: column v of `levels` is vertex vmap[v] of the (renumbered) graph
+  u32 *hsrc;            // top-down: set by k_ms_push when the frontier holds a heavy source, cleared by
+                        // k_ms_push_update; k_ms_push_heavy does nothing while it is 0
   int base, np, nflush; // output passes: window base, planes in use, flushes so far
   int cap0;             // bottom-up: in-edges per pending vertex in the first merged round
   u64 *zplane;          // plane for the step kernels to zero for the next level, or null
@@ -119,7 +121,8 @@ struct MsCarve {
   int *hv, *hpre, *ov, *opre, *bcnt, *bchk, *tstart;
   long long *bwt;       // per heavy-list block: tile weight of its chunks, then their exclusive prefix
   MsCtr *sh, *tot;
-  int *src;             // [64] sources of the group, [64] their degrees, [2] heavy totals
+  int *src;             // [64] sources of the group, [64] their degrees, [192..196] heavy and tile
+                        // totals, [200] the top-down heavy-source flag
   size_t bytes;
 };
 
@@ -319,8 +322,8 @@ __device__ __forceinline__ void ms_out_body(const MsArgs &a, int flush) {
 
 // ------------------------------------------------------------------ init
 // Clears a group's state: visited words, two frontier buffers, the first
-// frontier bitmap, depth plane 0 and the counter shards (k_ms_finish keeps
-// those clear afterwards).
+// frontier bitmap, depth plane 0, the counter shards (k_ms_finish keeps
+// those clear afterwards) and the heavy-source flag.
 __global__ __launch_bounds__(BLOCK) void k_ms_init(MsArgs a, u64 *f0, u64 *f1, u64 *b0) {
   const int nw = (a.n + 63) / 64;
   for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
@@ -332,6 +335,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_init(MsArgs a, u64 *f0, u64 *f1, u
   }
   u64 *sh = reinterpret_cast<u64 *>(a.sh);
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < NSH * MS_NCTR; i += gridDim.x * BLOCK) sh[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.hsrc = 0u;
 }
 
 // One thread per lane: sets the source bit (duplicates OR); depth 0 is
@@ -941,7 +945,10 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
     if (fu) {
       b = a.rp[u];
       e = a.rp[u + 1];
-      if (e - b > MS_HEAVY) e = b;  // heavy source: its chunks go to k_ms_push_heavy
+      if (e - b > MS_HEAVY) {  // heavy source: its chunks go to k_ms_push_heavy
+        e = b;
+        atomicOr(a.hsrc, 1u);
+      }
       const int d = e - b;
 #pragma unroll
       for (int t = 0; t < MS_T; ++t)
@@ -975,6 +982,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
 // heavy source (out-degree > MS_HEAVY) that is in the frontier, so a hub's
 // list is spread over many waves.
 __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
+  if (__hip_atomic_load(a.hsrc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;  // uniform
   MsStats st;
   const int wv = threadIdx.x / WAVE;
   for (int q = blockIdx.x * (BLOCK / WAVE) + wv; q < a.ochunks; q += gridDim.x * (BLOCK / WAVE)) {
@@ -1007,6 +1015,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
 
 // Owner-computes update after a push: F_{k+1}[v] = next[v] (already masked).
 __global__ __launch_bounds__(BLOCK) void k_ms_push_update(MsArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.hsrc = 0u;  // k_ms_push_heavy has finished
   MsStats st;
   for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {  // uniform per wave
     const int v = base + threadIdx.x;
@@ -1159,6 +1168,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     while (((long long)n >> a.sshift) > (long long)MS_SUM_WORDS * 32) ++a.sshift;
     a.levels = levels + (size_t)g0 * n;
     a.vmap = opt ? opt->vertex_map : nullptr;
+    a.hsrc = reinterpret_cast<u32 *>(src_dev + 200);
     a.sh = sh;
     a.base = 0;
     a.np = 1;  // plane 0 is cleared by k_ms_init
