@@ -227,17 +227,26 @@ struct MsStats {
 };
 enum { C_NEW, C_COMP, C_ACTIVE, C_ACTOUT, C_DONEIN, C_SCAN, C_UNVIS, C_HITS, C_HSCAN, C_HHITS, C_HPEND };
 
+// Counters a kernel may touch, as a bit mask of their indices: the flush
+// reduces only those (a 64-lane reduction of a u64 costs some 24 VALU
+// instructions per counter and wave).
+constexpr unsigned ms_bit(int c) { return 1u << c; }
+constexpr unsigned MS_M_FOUND = ms_bit(C_NEW) | ms_bit(C_COMP) | ms_bit(C_ACTIVE) | ms_bit(C_ACTOUT) | ms_bit(C_DONEIN);
+constexpr unsigned MS_M_ALL = (1u << MS_NCTR) - 1;
+
 // Workgroup-level flush: one atomic per counter and workgroup.  Every thread
 // of the workgroup must call it.
+template <unsigned MASK = MS_M_ALL>
 __device__ __forceinline__ void ms_flush_block(MsStats &st, MsCtr *sh) {
   __shared__ u64 s_red[BLOCK / WAVE][MS_NCTR];
 #pragma unroll
   for (int j = 0; j < MS_NCTR; ++j) {
+    if (!((MASK >> j) & 1u)) continue;
     const u64 r = wave_sum_u64(st.c[j]);
     if (lane() == 0) s_red[threadIdx.x / WAVE][j] = r;
   }
   __syncthreads();
-  if (threadIdx.x < MS_NCTR) {
+  if (threadIdx.x < MS_NCTR && ((MASK >> threadIdx.x) & 1u)) {
     u64 r = 0;
 #pragma unroll
     for (int w = 0; w < BLOCK / WAVE; ++w) r += s_red[w][threadIdx.x];
@@ -605,7 +614,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
     }
     if (lane() == 0 && (mine & ~posted & ~known)) atomicOr(a.accb + v, mine);
   }
-  ms_flush_block(st, a.sh);
+  ms_flush_block<ms_bit(C_SCAN) | ms_bit(C_HITS) | ms_bit(C_HSCAN) | ms_bit(C_HHITS)>(st, a.sh);
 }
 
 // Exclusive scans of VPT values per thread at once, in the order
@@ -926,7 +935,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       if (lane() == 0 && w0 < ve) a.nbits[w0 / WAVE] = nb;
     }
   }
-  ms_flush_block(st, a.sh);
+  ms_flush_block<ms_bit(C_UNVIS) | ms_bit(C_SCAN) | ms_bit(C_HITS) | ms_bit(C_HPEND) | MS_M_FOUND>(st, a.sh);
 }
 
 // ------------------------------------------------------------------ push
@@ -975,7 +984,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
       if (lane() == l) st.c[C_SCAN] += (u64)(ve - vb);
     }
   }
-  ms_flush_block(st, a.sh);
+  ms_flush_block<ms_bit(C_SCAN)>(st, a.sh);
 }
 
 // Top-down, heavy part: one wave per chunk of MS_HCHUNK out-edges of a
@@ -1010,7 +1019,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
       st.c[C_HSCAN] += (u64)(se - sb);
     }
   }
-  ms_flush_block(st, a.sh);
+  ms_flush_block<ms_bit(C_SCAN) | ms_bit(C_HSCAN)>(st, a.sh);
 }
 
 // Owner-computes update after a push: F_{k+1}[v] = next[v] (already masked).
@@ -1025,7 +1034,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_update(MsArgs a) {
     const int w = (base + (int)(threadIdx.x & ~(WAVE - 1))) / WAVE;
     if (lane() == 0 && w * WAVE < a.n) a.nbits[w] = nb;
   }
-  ms_flush_block(st, a.sh);
+  ms_flush_block<MS_M_FOUND>(st, a.sh);
 }
 
 // Output pass.  flush = 0: the final pass, every lane not yet written (depth
