@@ -1153,6 +1153,23 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   const bool rec = st && (flags & (BFS_F_LEVEL_STATS | BFS_F_LEVEL_TIMING)) && st->level_capacity > 0;
   const bool timing = rec && (flags & BFS_F_LEVEL_TIMING);
   int recorded = 0;
+  // level timing: the entry whose events are still to be read (-1: none)
+  int tslot = 0, pend_r = -1, pend_slot = 0;
+  auto resolve_timing = [&]() -> int {
+    if (pend_r < 0) return BFS_OK;
+    const hipEvent_t *P = hc.lev_ev + 4 * (pend_slot % 16);
+    float ms = 0.f;
+    if (st->level_ms_main) {
+      BFS_HIP(hipEventElapsedTime(&ms, P[1], P[2]));
+      st->level_ms_main[pend_r] = ms;
+    }
+    if (st->level_ms) {
+      BFS_HIP(hipEventElapsedTime(&ms, P[0], P[3]));
+      st->level_ms[pend_r] = ms;
+    }
+    pend_r = -1;
+    return BFS_OK;
+  };
   BFS_HIP(hipEventRecord(hc.ev[0], s));
   for (int g0 = 0; g0 < k; g0 += 64) {
     const int L = std::min(64, k - g0);
@@ -1276,7 +1293,11 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       a.dead = fr[(lev + 2) % 3];
       a.fbits = W.fb[lev & 1];
       a.nbits = W.fb[(lev + 1) & 1];
-      if (timing) BFS_HIP(hipEventRecord(hc.ev[2], s));
+      // timing: four events per level from a ring of 16 sets (level start,
+      // main kernel start and end, level end); read after the next level is
+      // enqueued, off the path between levels
+      hipEvent_t *E = hc.lev_ev + 4 * (tslot % 16);
+      if (timing) BFS_HIP(hipEventRecord(E[0], s));
       if (dir == 1) {
         // early exits pay for extra rounds only when the frontier carries a
         // large share of the remaining in-edges
@@ -1304,7 +1325,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         }
         // one vertex per thread while many in-edges remain to be scanned (more
         // workgroups in flight); four when few do (fixed costs amortised)
-        if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[0], s));
+        if (timing) BFS_HIP(hipEventRecord(E[1], s));
         const bool rounds = a.cap0 < (1 << 30);  // dense frontier: per-position walk
         const bool wide = eu > 2 * (long long)n;
         const dim3 gt(wide ? (sum ? std::min(grid_t1, MS_SUM_GRID) : grid_t1)
@@ -1325,20 +1346,22 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           else
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true>), gt, dim3(BLOCK), 0, s, a);
         }
-        if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[1], s));
+        if (timing) BFS_HIP(hipEventRecord(E[2], s));
       } else {
-        if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[0], s));
+        if (timing) BFS_HIP(hipEventRecord(E[1], s));
         hipLaunchKernelGGL(k_ms_push, dim3(grid_w), dim3(BLOCK), 0, s, a);
-        if (timing) BFS_HIP(hipEventRecord(hc.lev_ev[1], s));
+        if (timing) BFS_HIP(hipEventRecord(E[2], s));
         if (a.ochunks > 0)
           hipLaunchKernelGGL(k_ms_push_heavy, dim3(std::min(4096, (a.ochunks + 3) / 4)), dim3(BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
       }
-      if (timing) BFS_HIP(hipEventRecord(hc.ev[3], s));
+      if (timing) BFS_HIP(hipEventRecord(E[3], s));
       MsCtr *tot_host = reinterpret_cast<MsCtr *>(hc.pinned);
       const u64 seq = ++hc.seq;
       hipLaunchKernelGGL(k_ms_finish, dim3(1), dim3(NSH), 0, s, sh, tot_host, seq);
       BFS_HIP(hipGetLastError());
+      rc = resolve_timing();  // the previous level's events, while this one runs
+      if (rc) return rc;
       rc = wait_posted(&tot_host->seq, seq, s);
       if (rc) return rc;
       ++syncs;
@@ -1358,17 +1381,11 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         if (st->level_frontier_ld2) st->level_frontier_ld2[r] = (long long)c.hits;
         if (st->level_scanned_aux) st->level_scanned_aux[r] = (long long)c.hscanned;
         if (st->level_hits_aux) st->level_hits_aux[r] = (long long)c.hhits;
-        if (st->level_ms_main) {
-          float ms = 0.f;
-          if (timing) BFS_HIP(hipEventElapsedTime(&ms, hc.lev_ev[0], hc.lev_ev[1]));
-          st->level_ms_main[r] = ms;
-        }
-        if (st->level_ms) {
-          float ms = 0.f;
-          if (timing) BFS_HIP(hipEventElapsedTime(&ms, hc.ev[2], hc.ev[3]));
-          st->level_ms[r] = ms;
-        }
+        if (st->level_ms_main) st->level_ms_main[r] = 0.f;
+        if (st->level_ms) st->level_ms[r] = 0.f;
+        if (timing) pend_r = r, pend_slot = tslot;
       }
+      ++tslot;
       if (dir == 1 && c.hpend == 0) heavy_done = true;  // visited words only grow
       ++lev;
       if (c.newbits == 0) break;
@@ -1386,6 +1403,8 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     hipLaunchKernelGGL(k_ms_out, dim3(grid_v), dim3(BLOCK), 0, s, a, 0);
     BFS_HIP(hipGetLastError());
     max_levels = std::max(max_levels, lev);
+    rc = resolve_timing();
+    if (rc) return rc;
   }
   BFS_HIP(hipEventRecord(hc.ev[1], s));
   BFS_HIP(hipEventSynchronize(hc.ev[1]));

@@ -148,3 +148,20 @@ def test_rmat20_sampled_rows():
     lv = lv.cpu().numpy()
     for i in range(0, 64, 7):
         np.testing.assert_array_equal(lv[i], oracle.bfs(g.row_ptr, g.col_idx, int(srcs[i]))[0])
+
+
+def test_level_timing_fills_ms():
+    """With per-level timing every level of every group gets its step time and
+    its main kernel's time (read back after the next level is enqueued), within
+    the call's own time; more than 16 levels reuse the event ring."""
+    for g, srcs in ((gg.workload("rmat14"), None), (gg.from_edge_list(300, [(i, i + 1) for i in range(299)], True),
+                                                     np.array([0, 299, 150]))):
+        if srcs is None:
+            srcs = gg.pick_sources(g, 70, 5)
+        dg = B.DeviceGraph.from_graph(g)
+        _, st = B.bfs_multi(dg, srcs, flags=B.F_LEVEL_TIMING)
+        k = st["num_levels"]
+        assert k > 0
+        assert np.all(st["ms"][:k] > 0) and np.all(st["ms_main"][:k] > 0)
+        assert np.all(st["ms_main"][:k] <= st["ms"][:k] + 1e-3)
+        assert float(st["ms"][:k].sum()) <= st["elapsed_ms"] + 1e-3
