@@ -287,7 +287,7 @@ def main():
         tb = bytemodel.ms_tile_level_bytes(st, g.n)
         lb = bytemodel.ms_level_bytes(st, g.n)
         for k in range(st["num_levels"]):
-            v = "bottom_up_step" if int(st["variant"][k]) == B.PULL_B else "top_down_step"
+            v = {B.PULL_B: "bottom_up_step", B.MS_SPLIT: "split_step"}.get(int(st["variant"][k]), "top_down_step")
             per_t[v] = per_t.get(v, 0.0) + float(st["ms"][k])
             per_b[v] = per_b.get(v, 0.0) + lb[k]
             if tb[k] is not None:
@@ -311,10 +311,10 @@ def main():
         roof["traffic_over_algorithmic"] = round(traffic / (b_tile / max(n_tile, 1)), 2)
     st0 = stats[0]
     for k in range(st0["num_levels"]):
-        log(f"[bench] ms level {k}: {'pull' if int(st0['variant'][k]) == B.PULL_B else 'push'} "
+        log(f"[bench] ms level {k}: {({B.PULL_B: 'pull', B.MS_SPLIT: 'split'}).get(int(st0['variant'][k]), 'push')} "
             f"active={st0['frontier'][k]} ef={st0['frontier_edges'][k]} eu={st0['unvisited_edges'][k]} "
             f"unvis={st0['unvisited'][k]} scan={st0['scanned'][k]} "
-            f"new={st0['next'][k]} ms={st0['ms'][k]:.4f}")
+            f"new={st0['next'][k]} pushed={st0['scanned_push'][k]} ms={st0['ms'][k]:.4f}")
     out = {"metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",

@@ -105,6 +105,8 @@ int bfs_version(void);
 #define BFS_V_PUSH_Q_FILTER 9
 #define BFS_V_PUSH_B_FILTER 10
 #define BFS_NUM_VARIANTS 11
+/* bfs_multi level_variant only: a split bottom-up level (options.hub_split). */
+#define BFS_MS_SPLIT 200
 /* Per-level choice modes. */
 #define BFS_AUTO_HEURISTIC 100 /* Beamer direction-optimising rule (alpha 14, beta 24) */
 #define BFS_AUTO_LEARNED 101   /* selector network on device; heuristic fallback */
@@ -122,9 +124,11 @@ int bfs_version(void);
                                     feature sums (from bfs_graph_sums): the call uses
                                     them instead of recomputing them over all vertices */
 #define BFS_F_HUB_ORDER 64       /* bfs_multi: the graph is numbered by decreasing degree
-                                    (bfs_reorder_degree), so the frontier bits its
-                                    bottom-up steps read most often stay in cache and
-                                    they skip the LDS frontier summary (speed only) */
+                                    with ascending in-edge lists (bfs_reorder_degree), so
+                                    the frontier bits its bottom-up steps read most often
+                                    stay in cache and they skip the LDS frontier summary,
+                                    and sparse bottom-up levels may be split at the heavy
+                                    vertices (options.hub_split = 0) */
 
 /* ----------------------------------------------------------------- types */
 typedef struct bfs_graph {
@@ -154,6 +158,18 @@ typedef struct bfs_options {
                                     original vertex v (its new_of_old); sources and depths are
                                     then in the original numbering.  bfs_multi only: the other
                                     calls return BFS_ENOTSUP when it is set */
+  int32_t hub_split;             /* bfs_multi only (the other calls ignore it): the split id T of
+                                    split bottom-up levels.  On such a level the in-edges from
+                                    vertices < T are pulled, reading each in-edge list only up to
+                                    its first entry >= T, and the frontier vertices >= T push
+                                    their out-edges first; together they cover every edge, so
+                                    the depths do not depend on T.  0: T = the number of
+                                    vertices of out-degree > 1024 when BFS_F_HUB_ORDER is set
+                                    (they are vertices 0 .. T-1 there), used on the bottom-up
+                                    levels where the frontier is sparse and its out-edges from
+                                    vertices >= T are few; otherwise no split.  > 0: T =
+                                    min(hub_split, n) on every bottom-up level.  < 0: never.
+                                    A split needs every in-edge list in ascending order */
 } bfs_options;
 
 typedef struct bfs_stats {
@@ -185,6 +201,9 @@ typedef struct bfs_stats {
                                   (bottom-up: the tile kernel; top-down: the light-source kernel) */
   int64_t *level_scanned_aux;  /* edges examined by the step's heavy-vertex kernel (part of level_scanned) */
   int64_t *level_hits_aux;     /* frontier words that kernel gathered (part of level_frontier_ld2) */
+  int64_t *level_scanned_push; /* split level: edges examined by the push from vertices >= T
+                                  (part of level_scanned); else 0 */
+  int64_t *level_push_sources; /* split level: frontier vertices >= T that pushed; else 0 */
 } bfs_stats;
 
 /* Graph-wide sums over all vertices of floor(log2(1 + outdeg)) and of its
@@ -254,7 +273,8 @@ int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *pa
  * bottom-up, anything else the per-level heuristic.
  * With BFS_F_LEVEL_STATS (or BFS_F_LEVEL_TIMING) one per-level entry is
  * written per level of each 64-lane group, in order, and st->num_levels is
- * the number of entries: level_variant = BFS_V_PULL_B (bottom-up) or
+ * the number of entries: level_variant = BFS_V_PULL_B (bottom-up),
+ * BFS_MS_SPLIT (bottom-up split at options.hub_split's T) or
  * BFS_V_PUSH_Q_THREAD (top-down); level_frontier / level_frontier_edges =
  * vertices in some lane's frontier and their out-edges; level_unvisited =
  * vertices missing some lane when the step started (bottom-up steps only,

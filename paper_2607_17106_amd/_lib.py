@@ -31,6 +31,7 @@ PUSH_P3 = 8
 PUSH_Q_FILTER = 9
 PUSH_B_FILTER = 10
 NUM_VARIANTS = 11
+MS_SPLIT = 200  # bfs_multi level_variant: a split bottom-up level
 AUTO_HEURISTIC = 100
 AUTO_LEARNED = 101
 SCHEDULE = 102
@@ -65,7 +66,7 @@ class BfsOptions(ctypes.Structure):
     _fields_ = [("variant", c_int32), ("flags", c_int32), ("schedule_host", POINTER(c_int32)),
                 ("schedule_len", c_int32), ("max_levels", c_int32), ("heuristic_push", c_int32),
                 ("heuristic_pull", c_int32), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
-                ("graph_ld", c_int64), ("graph_ld2", c_int64), ("vertex_map", c_void_p)]
+                ("graph_ld", c_int64), ("graph_ld2", c_int64), ("vertex_map", c_void_p), ("hub_split", c_int32)]
 
 
 class BfsStats(ctypes.Structure):
@@ -78,7 +79,8 @@ class BfsStats(ctypes.Structure):
                 ("level_frontier_ld2", POINTER(c_int64)), ("graph_ld", c_int64), ("graph_ld2", c_int64),
                 ("level_scanned", POINTER(c_int64)), ("level_next", POINTER(c_int64)),
                 ("level_ms", POINTER(c_float)), ("level_ms_main", POINTER(c_float)),
-                ("level_scanned_aux", POINTER(c_int64)), ("level_hits_aux", POINTER(c_int64))]
+                ("level_scanned_aux", POINTER(c_int64)), ("level_hits_aux", POINTER(c_int64)),
+                ("level_scanned_push", POINTER(c_int64)), ("level_push_sources", POINTER(c_int64))]
 
 
 class BfsGraphBatch(ctypes.Structure):

@@ -158,9 +158,11 @@ class _StatsBuf:
         self.ms_main = np.zeros(cap, np.float32)
         self.scan_aux = np.zeros(cap, np.int64)
         self.hits_aux = np.zeros(cap, np.int64)
+        self.scan_push = np.zeros(cap, np.int64)
+        self.push_src = np.zeros(cap, np.int64)
         self._arrays = (self.variant, self.frontier, self.frontier_edges, self.unvisited, self.unvisited_edges,
                         self.fallback, self.fld, self.fld2, self.scanned, self.nxt, self.ms, self.ms_main,
-                        self.scan_aux, self.hits_aux)
+                        self.scan_aux, self.hits_aux, self.scan_push, self.push_src)
         self._dirty = 0
         P32, P64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
         self.s = L.BfsStats()
@@ -179,6 +181,8 @@ class _StatsBuf:
         self.s.level_ms_main = self.ms_main.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         self.s.level_scanned_aux = self.scan_aux.ctypes.data_as(P64)
         self.s.level_hits_aux = self.hits_aux.ctypes.data_as(P64)
+        self.s.level_scanned_push = self.scan_push.ctypes.data_as(P64)
+        self.s.level_push_sources = self.push_src.ctypes.data_as(P64)
 
     def as_dict(self, per_level: bool):
         s = self.s
@@ -194,7 +198,8 @@ class _StatsBuf:
                      frontier_ld=self.fld[:k].copy(), frontier_ld2=self.fld2[:k].copy(),
                      scanned=self.scanned[:k].copy(), next=self.nxt[:k].copy(), ms=self.ms[:k].copy(),
                      ms_main=self.ms_main[:k].copy(), scanned_aux=self.scan_aux[:k].copy(),
-                     hits_aux=self.hits_aux[:k].copy())
+                     hits_aux=self.hits_aux[:k].copy(), scanned_push=self.scan_push[:k].copy(),
+                     push_sources=self.push_src[:k].copy())
         return d
 
 
@@ -266,10 +271,12 @@ def bfs_parents(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, fl
 
 def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: int = 0, workspace=None,
               levels=None, stream=None, level_stats: bool = False, stats_capacity: int = 1 << 14,
-              vertex_map=None):
+              vertex_map=None, hub_split: int = 0):
     """Depths [k][n] from k sources in 64-lane bit-packed groups.  vertex_map:
     the new_of_old of reorder_degree when g is the renumbered graph (sources
-    and depth columns then use the original ids)."""
+    and depth columns then use the original ids).  hub_split: the split id of
+    split bottom-up levels (0 automatic, > 0 that id on every bottom-up level,
+    < 0 never; bfs_options.hub_split)."""
     lib = L.load()
     src = np.ascontiguousarray(sources, dtype=np.int32)
     k = int(src.size)
@@ -287,6 +294,7 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
         if vertex_map.dtype != torch.int32 or vertex_map.numel() != g.n or not vertex_map.is_contiguous():
             raise ValueError("vertex_map must be a contiguous int32 tensor of n entries")
         opt.vertex_map = vertex_map.data_ptr()
+    opt.hub_split = int(hub_split)
     rc = lib.bfs_multi(g.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k, _ptr(levels),
                        ctypes.byref(opt), ctypes.byref(sb.s), _stream(stream))
     L.check(rc, "bfs_multi")

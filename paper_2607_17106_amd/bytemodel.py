@@ -81,7 +81,8 @@ def ms_rel(k: int) -> int:
     return k % ((1 << MS_PLANES) - 1) + 1
 
 
-def ms_step_bytes(pull: bool, n: int, k: int, nf: int, unvis: int, scan: int, hits: int, found: int) -> float:
+def ms_step_bytes(pull: bool, n: int, k: int, nf: int, unvis: int, scan: int, hits: int, found: int,
+                  pscan: int = 0, pact: int = 0) -> float:
     """One level k of the 64-lane multi-source search (u64 words per vertex).
 
     Both directions clear the dead frontier buffer (8n) and record each found
@@ -94,38 +95,51 @@ def ms_step_bytes(pull: bool, n: int, k: int, nf: int, unvis: int, scan: int, hi
                  pair) + 12 per scanned edge (target id, its visited word)
                  + 8 per found vertex (its next word) + update pass: 8n next
                  words + n/8 next bitmap + 8 per found (visited read)
+      split bottom-up (pact > 0 or pscan > 0): the bottom-up terms over the
+                 pulled in-edges (scan - pscan), plus 8 per unvis (the pushed
+                 next word read as the start of the OR) and the push: n/8
+                 frontier bitmap + 16 per pushing vertex (word, row_ptr pair)
+                 + 12 per pushed edge (target id, its visited word)
     nf = frontier vertices, unvis = vertices missing some lane (bottom-up),
     hits = in-edges whose source is in the frontier, found = vertices with a
-    new lane."""
+    new lane, pscan / pact = edges and vertices of a split level's push."""
     disc = found * (8.0 + 16.0 * bin(ms_rel(k)).count("1"))
     if pull:
-        return 8.0 * n + 8.0 * n + 8.0 * n + n / 8.0 + 8.0 * unvis + 4.125 * scan + 8.0 * hits + disc
+        split = 8.0 * unvis + n / 8.0 + 16.0 * pact + 12.0 * pscan if (pscan or pact) else 0.0
+        return (8.0 * n + 8.0 * n + 8.0 * n + n / 8.0 + 8.0 * unvis + 4.125 * (scan - pscan) + 8.0 * hits + disc
+                + split)
     return 8.0 * n + n / 8.0 + 16.0 * nf + 12.0 * scan + 8.0 * found + 8.0 * n + n / 8.0 + 8.0 * found + disc
 
 
-def ms_tile_bytes(n: int, k: int, unvis: int, scan_light: int, hits_light: int, found: int) -> float:
+def ms_tile_bytes(n: int, k: int, unvis: int, scan_light: int, hits_light: int, found: int,
+                  split: bool = False) -> float:
     """The bottom-up tile kernel alone: the dense per-vertex part (8n visited
     read, 8n next written, 8n dead buffer cleared, n/8 next bitmap, 8 per
     unvis for the csc_ptr pair), the light vertices' in-edges (4 per column id
     + 1/8 per bitmap probe), their gathered frontier words (8 each) and the
     discoveries (visited write + plane updates).  The heavy kernel's edges and
     gathers are excluded (scan_light = scanned - scanned_aux, hits_light =
-    hits - hits_aux)."""
+    hits - hits_aux); on a split level so are the push's edges (scan_light
+    also less scanned_push), and each unvis vertex reads its pushed next word
+    (8 more)."""
     disc = found * (8.0 + 16.0 * bin(ms_rel(k)).count("1"))
-    return 24.0 * n + n / 8.0 + 8.0 * unvis + 4.125 * scan_light + 8.0 * hits_light + disc
+    return (24.0 * n + n / 8.0 + (16.0 if split else 8.0) * unvis + 4.125 * scan_light + 8.0 * hits_light
+            + disc)
 
 
 def ms_tile_level_bytes(stats: dict, n: int):
-    """ms_tile_bytes for every bottom-up level of a bfs_multi run (None for
-    top-down levels)."""
+    """ms_tile_bytes for every bottom-up level (split or not) of a bfs_multi
+    run (None for top-down levels)."""
     out = []
     k = 0
     for i in range(int(stats["num_levels"])):
-        if int(stats["variant"][i]) == L.PULL_B:
+        var = int(stats["variant"][i])
+        if var in (L.PULL_B, L.MS_SPLIT):
+            push = int(stats["scanned_push"][i]) if "scanned_push" in stats else 0
             out.append(ms_tile_bytes(n, k, int(stats["unvisited"][i]),
-                                     int(stats["scanned"][i]) - int(stats["scanned_aux"][i]),
+                                     int(stats["scanned"][i]) - int(stats["scanned_aux"][i]) - push,
                                      int(stats["frontier_ld2"][i]) - int(stats["hits_aux"][i]),
-                                     int(stats["frontier_ld"][i])))
+                                     int(stats["frontier_ld"][i]), split=var == L.MS_SPLIT))
         else:
             out.append(None)
         k = 0 if int(stats["next"][i]) == 0 else k + 1
@@ -138,10 +152,13 @@ def ms_level_bytes(stats: dict, n: int):
     out = []
     k = 0
     for i in range(int(stats["num_levels"])):
-        pull = int(stats["variant"][i]) == L.PULL_B
+        pull = int(stats["variant"][i]) in (L.PULL_B, L.MS_SPLIT)
+        split = int(stats["variant"][i]) == L.MS_SPLIT
         out.append(ms_step_bytes(pull, n, k, int(stats["frontier"][i]), int(stats["unvisited"][i]),
                                  int(stats["scanned"][i]), int(stats["frontier_ld2"][i]),
-                                 int(stats["frontier_ld"][i])))
+                                 int(stats["frontier_ld"][i]),
+                                 int(stats["scanned_push"][i]) if split else 0,
+                                 int(stats["push_sources"][i]) if split else 0))
         k = 0 if int(stats["next"][i]) == 0 else k + 1
     return out
 

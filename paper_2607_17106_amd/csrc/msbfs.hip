@@ -55,6 +55,12 @@ constexpr int MS_SUM_GRID = 1024;  // persistent workgroups of the summary-filte
 // [t, t + 1) * MS_TWEIGHT: BLOCK vertices where in-degrees are low, fewer
 // where they are high (a graph ordered by degree puts those together), so no
 // tile walks many more in-edges than MS_TWEIGHT + 64 * MS_HEAVY.
+// Split levels' push (k_ms_push_split): hub targets ORed in LDS (64 KB), workgroups
+// of 1024 threads, MS_PQ_GRID of them, staging rows merged MS_PQ_ROWS per thread.
+constexpr int MS_PQ_HUB = 8192;   // 64 KB of LDS
+constexpr int MS_PQ_BLOCK = 1024;
+constexpr int MS_PQ_GRID = 256;
+constexpr int MS_PQ_ROWS = 32;    // staging rows merged per k_ms_hub_or thread
 constexpr int MS_TALPHA = 64;
 constexpr long long MS_TWEIGHT = (long long)BLOCK * MS_TALPHA;
 // tiles for n vertices and any int32 edge count (a chunk weighs at most
@@ -74,7 +80,10 @@ struct MsCtr {  // two 64-byte lines per shard
   u64 hscanned;    // the part of `scanned` examined by the heavy-vertex kernel
   u64 hhits;       // the part of `hits` gathered by it
   u64 hpend;       // bottom-up: heavy vertices still missing some lane after the step
-  u64 pad[4];
+  u64 lout;        // out-edges of the found vertices at or above the split id (hub_t)
+  u64 pscan;       // split level: edges examined by the light-source push (part of `scanned`)
+  u64 pact;        // split level: frontier vertices that push expanded
+  u64 pad[1];
   u64 seq;         // totals only: sequence number written last (host polling)
 };
 static_assert(sizeof(MsCtr) == 128, "MsCtr is two lines");
@@ -104,6 +113,20 @@ struct MsArgs {
   const int *vmap;      // or null: column v of `levels` is vertex vmap[v] of the (renumbered) graph
   u32 *hsrc;            // top-down: set by k_ms_push when the frontier holds a heavy source, cleared by
                         // k_ms_push_update; k_ms_push_heavy does nothing while it is 0
+  // Split bottom-up level at split_t: in-edges from vertices below split_t
+  // are pulled (an in-edge list is read only up to its first entry >=
+  // split_t: lists are ascending), and the frontier vertices at or above
+  // split_t push their out-edges into `next` first (push_lo =
+  // split_t, k_ms_push_split and k_ms_hub_or).  The two
+  // halves cover every edge, so any split id gives the same result; on a graph
+  // numbered by decreasing degree, the heavy out-degree count turns a sparse
+  // hub frontier's full in-edge scan into the hubs' in-edges plus a few light
+  // out-edges.
+  int hub_t;            // split id of this call (0: none); discoveries at or above it count their
+                        // out-edges in lout
+  int split_t;          // this level's split id (0: not a split level)
+  int push_lo;          // k_ms_push: first vertex to expand (split level: split_t; else 0)
+  u64 *hubst;           // split level: staging rows of k_ms_push_split (MS_PQ_GRID x MS_PQ_HUB words)
   int base, np, nflush; // output passes: window base, planes in use, flushes so far
   int cap0;             // bottom-up: in-edges per pending vertex in the first merged round
   u64 *zplane;          // plane for the step kernels to zero for the next level, or null
@@ -119,6 +142,7 @@ struct MsCarve {
   u64 *fr[3], *vis, *flushed, *accb, *planes, *fb[2];
   u32 *fsum;
   int *hv, *hpre, *ov, *opre, *bcnt, *bchk, *tstart;
+  u64 *hubst;
   long long *bwt;       // per heavy-list block: tile weight of its chunks, then their exclusive prefix
   MsCtr *sh, *tot;
   int *src;             // [64] sources of the group, [64] their degrees, [192..196] heavy and tile
@@ -147,6 +171,8 @@ static MsCarve ms_carve(uintptr_t p, int n) {
   off += ib;
   c.opre = reinterpret_cast<int *>(p + off);
   off += ib;
+  c.hubst = reinterpret_cast<u64 *>(p + off);
+  off += (size_t)MS_PQ_GRID * MS_PQ_HUB * 8;
   c.bcnt = reinterpret_cast<int *>(p + off);
   off += nb;
   c.bchk = reinterpret_cast<int *>(p + off);
@@ -214,24 +240,25 @@ __global__ __launch_bounds__(BLOCK) void k_ms_summary(const u64 *fb, int nwords,
   sum[i] = out;
 }
 
+enum { C_NEW, C_COMP, C_ACTIVE, C_ACTOUT, C_DONEIN, C_SCAN, C_UNVIS, C_HITS, C_HSCAN, C_HHITS, C_HPEND, C_LOUT,
+       C_PSCAN, C_PACT };
+
+// Per-thread counters.  Within one launch every vertex is found, and every
+// edge examined, at most once, so each count but C_COMP stays below the edge
+// count (< 2^31) per thread and is kept in 32 bits (registers: the tile kernel
+// keeps ten of them live); C_COMP (lanes x out-degree) is kept in 64.
 struct MsStats {
-  u64 c[MS_NCTR] = {};
-  __device__ __forceinline__ void flush(MsCtr *sh) {
-    u64 *f = reinterpret_cast<u64 *>(sh + (blockIdx.x % NSH));
-#pragma unroll
-    for (int j = 0; j < MS_NCTR; ++j) {
-      const u64 r = wave_sum_u64(c[j]);
-      if (lane() == 0 && r) atomicAdd(f + j, r);
-    }
-  }
+  u32 c[MS_NCTR] = {};
+  u64 comp = 0;
+  __device__ __forceinline__ u64 get(int j) const { return j == C_COMP ? comp : (u64)c[j]; }
 };
-enum { C_NEW, C_COMP, C_ACTIVE, C_ACTOUT, C_DONEIN, C_SCAN, C_UNVIS, C_HITS, C_HSCAN, C_HHITS, C_HPEND };
 
 // Counters a kernel may touch, as a bit mask of their indices: the flush
 // reduces only those (a 64-lane reduction of a u64 costs some 24 VALU
 // instructions per counter and wave).
 constexpr unsigned ms_bit(int c) { return 1u << c; }
-constexpr unsigned MS_M_FOUND = ms_bit(C_NEW) | ms_bit(C_COMP) | ms_bit(C_ACTIVE) | ms_bit(C_ACTOUT) | ms_bit(C_DONEIN);
+constexpr unsigned MS_M_FOUND =
+    ms_bit(C_NEW) | ms_bit(C_COMP) | ms_bit(C_ACTIVE) | ms_bit(C_ACTOUT) | ms_bit(C_DONEIN) | ms_bit(C_LOUT);
 constexpr unsigned MS_M_ALL = (1u << MS_NCTR) - 1;
 
 // Workgroup-level flush: one atomic per counter and workgroup.  Every thread
@@ -242,7 +269,7 @@ __device__ __forceinline__ void ms_flush_block(MsStats &st, MsCtr *sh) {
 #pragma unroll
   for (int j = 0; j < MS_NCTR; ++j) {
     if (!((MASK >> j) & 1u)) continue;
-    const u64 r = wave_sum_u64(st.c[j]);
+    const u64 r = wave_sum_u64(st.get(j));
     if (lane() == 0) s_red[threadIdx.x / WAVE][j] = r;
   }
   __syncthreads();
@@ -256,8 +283,10 @@ __device__ __forceinline__ void ms_flush_block(MsStats &st, MsCtr *sh) {
 
 // Clears the dead frontier buffer and, when the host asks for it, the depth
 // plane the next level will use for the first time (zeroed here, one level
-// ahead, instead of by a launch on the host's critical path).
+// ahead, instead of by a launch on the host's critical path).  dead = null:
+// another kernel of the level does it.
 __device__ __forceinline__ void ms_clear_dead(const MsArgs &a) {
+  if (!a.dead) return;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nthr = gridDim.x * blockDim.x;
   for (int i = tid; i < a.n; i += nthr) {
@@ -275,11 +304,12 @@ __device__ __forceinline__ void ms_discover(const MsArgs &a, int v, u64 vis_old,
     if (r & 1) a.planes[(size_t)b * a.n + v] |= nw;
   const int c = __popcll(nw);
   const int od = a.rp[v + 1] - a.rp[v];
-  st.c[C_NEW] += (u64)c;
-  st.c[C_COMP] += (u64)c * (u64)od;
+  st.c[C_NEW] += (u32)c;
+  st.comp += (u64)c * (u64)od;
   st.c[C_ACTIVE] += 1;
-  st.c[C_ACTOUT] += (u64)od;
-  if ((vnew & a.full) == a.full) st.c[C_DONEIN] += (u64)(a.cp[v + 1] - a.cp[v]);
+  st.c[C_ACTOUT] += (u32)od;
+  if (v >= a.hub_t) st.c[C_LOUT] += (u32)od;
+  if ((vnew & a.full) == a.full) st.c[C_DONEIN] += (u32)(a.cp[v + 1] - a.cp[v]);
 }
 
 // Writes the depth of every lane of v not in `skip`: a.base + r for visited
@@ -378,6 +408,33 @@ __global__ void k_ms_seed(MsArgs a, MsSources src, u64 *f0, u64 *b0, const int *
 
 __global__ __launch_bounds__(BLOCK) void k_ms_fill(u64 *p, int n) {
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) p[i] = 0ull;
+}
+
+// First position in [lo, hi) of an ascending int array holding a value >= t
+// (hi if none): one thread.
+__device__ __forceinline__ int ms_lower_bound(const int *x, int lo, int hi, int t) {
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if (x[mid] < t) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// The same for a whole wave (same arguments in every lane, same result): each
+// round the lanes test 64 evenly spaced entries at once and a ballot narrows
+// the range 64-fold, so 4096 entries take two rounds of one load each.
+__device__ __forceinline__ int ms_wave_lower_bound(const int *x, int lo, int hi, int t) {
+  while (lo < hi) {  // the answer lies in [lo, hi]
+    const int step = (hi - lo + WAVE - 1) / WAVE;
+    const int p = lo + lane() * step;
+    const u64 below = __ballot(p < hi && x[p] < t);  // a prefix of the lanes (x ascending)
+    const int k = __popcll(below);
+    if (k == 0) return lo;
+    const int pk = lo + k * step;  // first tested position not below t, if any
+    lo = lo + (k - 1) * step + 1;
+    hi = min(hi, pk);
+  }
+  return lo;
 }
 
 // ------------------------------------------------------------ heavy list
@@ -573,9 +630,16 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
     const int v = a.hv[i];
     const u64 need = a.full & ~a.vis[v];
     if (!need) continue;
-    u64 known = a.accb[v];  // other chunks' results so far (possibly stale: only less early exit)
+    const int sb = a.cp[v] + (q - a.hpre[i]) * MS_HCHUNK;
+    int se = min(a.cp[v + 1], sb + MS_HCHUNK);
+    if (a.split_t) {  // split level: only the in-edges from vertices below split_t (a prefix)
+      se = ms_wave_lower_bound(a.cx, sb, se, a.split_t);
+      if (se == sb) continue;
+    }
+    // other chunks' results so far (possibly stale: only less early exit), and
+    // on a split level what the light sources pushed
+    u64 known = a.accb[v] | (a.split_t ? a.next[v] : 0ull);
     if ((known & need) == need) continue;
-    const int sb = a.cp[v] + (q - a.hpre[i]) * MS_HCHUNK, se = min(a.cp[v + 1], sb + MS_HCHUNK);
     u64 mine = 0ull, posted = 0ull;
     int round = 0;
     for (int base = sb; base < se; base += MS_HU * WAVE) {  // MS_HU rounds of 64 in-edges, loads in flight together
@@ -600,8 +664,8 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
       for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
       mine |= f & need;
       if (lane() == 0) {
-        st.c[C_SCAN] += (u64)min(MS_HU * WAVE, se - base);
-        st.c[C_HSCAN] += (u64)min(MS_HU * WAVE, se - base);
+        st.c[C_SCAN] += (u32)min(MS_HU * WAVE, se - base);
+        st.c[C_HSCAN] += (u32)min(MS_HU * WAVE, se - base);
       }
       if (((known | mine) & need) == need) break;
       if (++round % MS_POST == 0 && (mine & ~posted)) {
@@ -665,8 +729,8 @@ __device__ __forceinline__ void ms_multi_scan(const int (&x)[VPT], int (&off)[VP
 // edge i * BLOCK + t per position, each with its own owner search and
 // done-check, one segmented scan per position.  Heavy vertices take the heavy pass's result from accb.  Also
 // writes next, the next bitmap and the discoveries, and clears the dead
-// frontier buffer.
-template <int VPT, bool SUM, bool CONSEC>
+// frontier buffer.  SPLIT: a split level (MsArgs::split_t).
+template <int VPT, bool SUM, bool CONSEC, bool SPLIT = false>
 __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
   constexpr int TV = VPT * BLOCK;
   extern __shared__ u32 s_sum[];
@@ -706,18 +770,21 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
         st.c[C_UNVIS] += 1;
         b[j] = a.cp[v];
         d[j] = a.cp[v + 1] - b[j];
+        heavy[j] = d[j] > MS_HEAVY;
+        if (SPLIT) acc[j] = a.next[v];  // what the light sources pushed
       }
     }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       if (!need[j]) continue;
       const int v = vb + j * BLOCK + t;
-      if (d[j] > MS_HEAVY) {
-        heavy[j] = true;
-        acc[j] = a.accb[v];
-        if (acc[j]) a.accb[v] = 0ull;  // ready for the next bottom-up level
+      if (heavy[j]) {
+        const u64 h = a.accb[v];
+        acc[j] |= h;
+        if (h) a.accb[v] = 0ull;  // ready for the next bottom-up level
         continue;
       }
+      if (SPLIT && (acc[j] & need[j]) == need[j]) continue;  // covered by the push
       int u[MS_HEAD];
       if (d[j] >= MS_HEAD) {  // a whole head inside the list: 16-byte loads
         const I4u *p = reinterpret_cast<const I4u *>(a.cx + b[j]);
@@ -733,6 +800,13 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
 #pragma unroll
         for (int i = 0; i < MS_HEAD; ++i) u[i] = i < d[j] ? a.cx[b[j] + i] : -1;
       }
+      bool more = d[j] > MS_HEAD;  // the list goes on past the head
+      if (SPLIT) {  // read up to the first in-neighbour >= split_t (pushed instead)
+        if (more && u[MS_HEAD - 1] >= a.split_t) more = false;
+#pragma unroll
+        for (int i = 0; i < MS_HEAD; ++i)
+          if (u[i] >= a.split_t) u[i] = -1;
+      }
       bool hit[MS_HEAD];
 #pragma unroll
       for (int i = 0; i < MS_HEAD; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
@@ -742,9 +816,10 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
           acc[j] |= a.front[u[i]];
           st.c[C_HITS] += 1;
         }
-      st.c[C_SCAN] += (u64)min(d[j], MS_HEAD);
-      if (d[j] > MS_HEAD && (acc[j] & need[j]) != need[j]) {
-        len[j] = d[j] - MS_HEAD;
+      st.c[C_SCAN] += (u32)min(d[j], MS_HEAD);
+      if (more && (acc[j] & need[j]) != need[j]) {
+        const int e = SPLIT ? ms_lower_bound(a.cx, b[j] + MS_HEAD, b[j] + d[j], a.split_t) : b[j] + d[j];
+        len[j] = e - b[j] - MS_HEAD;
         b[j] += MS_HEAD;
       }
     }
@@ -966,7 +1041,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
           const u64 m = fu & ~a.vis[v];
           if (m) atomicOr(a.next + v, m);
         }
-      st.c[C_SCAN] += (u64)min(d, MS_T);
+      st.c[C_SCAN] += (u32)min(d, MS_T);
       pending = d > MS_T;
       b += MS_T;
     }
@@ -981,11 +1056,102 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
         const u64 m = lf & ~a.vis[v];
         if (m) atomicOr(a.next + v, m);
       }
-      if (lane() == l) st.c[C_SCAN] += (u64)(ve - vb);
+      if (lane() == l) st.c[C_SCAN] += (u32)(ve - vb);
     }
   }
   ms_flush_block<ms_bit(C_SCAN)>(st, a.sh);
 }
+
+// Split level, push half: the out-lists of the frontier vertices at or above
+// push_lo, one wave per list, MS_HU rounds of 64 edges with their loads in
+// flight together.  MS_PQ_GRID workgroups; workgroup b takes the bitmap words
+// push_lo/64 + b + k * MS_PQ_GRID (interleaved: on a graph numbered by degree
+// the busy words sit just above push_lo), 64 words per round, and its waves
+// share the round's frontier vertices through an LDS queue.  Light vertices'
+// lists start with the same few hubs (ascending lists, hubs first), so edges
+// into targets below MS_PQ_HUB are ORed into an LDS copy of those targets'
+// `next` words, which each workgroup writes to its row of the staging array
+// `hubst` at the end (k_ms_hub_or merges the rows); other targets take one
+// global atomic per edge that brings lanes they miss.
+
+__global__ __launch_bounds__(MS_PQ_BLOCK) void k_ms_push_split(MsArgs a) {
+  __shared__ u64 s_hub[MS_PQ_HUB];
+  __shared__ int s_q[WAVE * WAVE];  // one round: up to 64 words of 64 vertices
+  __shared__ int s_qn;
+  const int nh = min(a.push_lo, MS_PQ_HUB);
+  for (int i = threadIdx.x; i < nh; i += MS_PQ_BLOCK) s_hub[i] = 0ull;
+  MsStats st;
+  constexpr int WPB = MS_PQ_BLOCK / WAVE;
+  const int wv = threadIdx.x / WAVE;
+  const int nwords = (a.n + WAVE - 1) / WAVE, w0 = a.push_lo / WAVE;
+  for (long long k0 = 0; w0 + blockIdx.x + k0 * MS_PQ_GRID < nwords; k0 += WAVE) {  // uniform
+    if (threadIdx.x == 0) s_qn = 0;
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+      const long long w = w0 + blockIdx.x + (k0 + threadIdx.x) * MS_PQ_GRID;
+      u64 wb = w < nwords ? a.fbits[w] : 0ull;
+      if (w == w0) wb &= ~0ull << (a.push_lo % WAVE);  // vertices below push_lo are pulled
+      if (wb) {
+        int pos = atomicAdd(&s_qn, __popcll(wb));
+        for (; wb; wb &= wb - 1ull) s_q[pos++] = (int)w * WAVE + (__ffsll((long long)wb) - 1);
+      }
+    }
+    __syncthreads();
+    const int qn = s_qn;
+    for (int q = wv; q < qn; q += WPB) {
+      const int u = s_q[q];
+      const u64 fu = a.front[u];
+      const int sb = a.rp[u], se = a.rp[u + 1];
+      for (int base = sb; base < se; base += MS_HU * WAVE) {
+        int v[MS_HU];
+#pragma unroll
+        for (int r = 0; r < MS_HU; ++r) {
+          const int j = base + r * WAVE + lane();
+          v[r] = j < se ? a.ci[j] : -1;
+        }
+        u64 m[MS_HU];
+#pragma unroll
+        for (int r = 0; r < MS_HU; ++r) m[r] = v[r] >= nh ? fu & ~a.vis[v[r]] : 0ull;
+#pragma unroll
+        for (int r = 0; r < MS_HU; ++r) {
+          if (v[r] >= 0 && v[r] < nh) atomicOr(&s_hub[v[r]], fu);
+          else if (m[r]) atomicOr(a.next + v[r], m[r]);
+        }
+      }
+      if (lane() == 0) {
+        st.c[C_SCAN] += (u32)(se - sb);
+        st.c[C_PSCAN] += (u32)(se - sb);
+        st.c[C_PACT] += 1;
+      }
+    }
+    __syncthreads();  // the queue is refilled next round
+  }
+  u64 *row = a.hubst + (size_t)blockIdx.x * MS_PQ_HUB;
+  for (int i = threadIdx.x; i < nh; i += MS_PQ_BLOCK) row[i] = s_hub[i];
+  // counters: one atomic per wave and counter (these workgroups are not BLOCK wide)
+  u64 *f = reinterpret_cast<u64 *>(a.sh + (blockIdx.x % NSH));
+  const u64 r0 = wave_sum_u64(st.get(C_SCAN)), r1 = wave_sum_u64(st.get(C_PACT));
+  if (lane() == 0 && r0) {
+    atomicAdd(f + C_SCAN, r0);
+    atomicAdd(f + C_PSCAN, r0);
+  }
+  if (lane() == 0 && r1) atomicAdd(f + C_PACT, r1);
+}
+
+// Merges the MS_PQ_GRID staging rows of k_ms_push_split into `next` for the
+// targets below min(push_lo, MS_PQ_HUB): thread (i, g) ORs rows
+// g * MS_PQ_ROWS .. + MS_PQ_ROWS - 1 of column i.
+__global__ __launch_bounds__(BLOCK) void k_ms_hub_or(MsArgs a) {
+  const int nh = min(a.push_lo, MS_PQ_HUB);
+  const int i = blockIdx.x * BLOCK + threadIdx.x, g = blockIdx.y;
+  if (i >= nh) return;
+  const u64 *col = a.hubst + (size_t)g * MS_PQ_ROWS * MS_PQ_HUB + i;
+  u64 x = 0ull;
+#pragma unroll 8
+  for (int r = 0; r < MS_PQ_ROWS; ++r) x |= col[(size_t)r * MS_PQ_HUB];
+  if (x) atomicOr(a.next + i, x);  // the pull masks these words with the lanes v misses
+}
+static_assert(MS_PQ_GRID % MS_PQ_ROWS == 0, "staging rows split evenly");
 
 // Top-down, heavy part: one wave per chunk of MS_HCHUNK out-edges of a
 // heavy source (out-degree > MS_HEAVY) that is in the frontier, so a hub's
@@ -1015,8 +1181,8 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
         if (m[r]) atomicOr(a.next + v[r], m[r]);
     }
     if (lane() == 0) {
-      st.c[C_SCAN] += (u64)(se - sb);
-      st.c[C_HSCAN] += (u64)(se - sb);
+      st.c[C_SCAN] += (u32)(se - sb);
+      st.c[C_HSCAN] += (u32)(se - sb);
     }
   }
   ms_flush_block<ms_bit(C_SCAN) | ms_bit(C_HSCAN)>(st, a.sh);
@@ -1195,6 +1361,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.levels = levels + (size_t)g0 * n;
     a.vmap = opt ? opt->vertex_map : nullptr;
     a.hsrc = reinterpret_cast<u32 *>(src_dev + 200);
+    a.hubst = W.hubst;
     a.sh = sh;
     a.base = 0;
     a.np = 1;  // plane 0 is cleared by k_ms_init
@@ -1227,6 +1394,14 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       a.ocount = a.hcount;
       a.ochunks = a.hchunks;
     }
+    // split id: vertices below it are pulled on a split bottom-up level, the
+    // frontier vertices at or above it push (options.hub_split > 0: that id on
+    // every bottom-up level; 0: on a graph numbered by decreasing degree, its
+    // heavy out-degree vertices, where the cost rule below picks it; < 0: never)
+    const int hub_req = opt ? opt->hub_split : 0;
+    a.hub_t = hub_req > 0 ? std::min(hub_req, n) : (hub_req == 0 && (flags & BFS_F_HUB_ORDER)) ? a.ocount : 0;
+    a.push_lo = 0;
+    a.split_t = 0;
     long long nf = 0, ef = 0, src_comp = 0;
     {
       std::vector<std::pair<int, int>> sd;
@@ -1242,6 +1417,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         }
     }
     long long eu = g->nnz;  // in-edges of vertices still missing some lane
+    long long lout = ef;    // out-edges of the frontier vertices at or above hub_t (level 0: an upper bound)
     reached += L;
     int msdir = 0;
     long long prev_nf = -1;
@@ -1298,10 +1474,26 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       // enqueued, off the path between levels
       hipEvent_t *E = hc.lev_ev + 4 * (tslot % 16);
       if (timing) BFS_HIP(hipEventRecord(E[0], s));
+      // Split bottom-up level (see MsArgs::split_t): where the frontier is sparse
+      // (no early exits expected, so the plain step reads every in-edge of the
+      // vertices missing a lane) and the light frontier vertices' out-edges,
+      // one atomic each, cost less than the in-edges skipped.
+      const bool split = dir == 1 && a.hub_t > 0 && (hub_req > 0 || (ef * 4 <= eu && lout * 16 < eu));
       if (dir == 1) {
         // early exits pay for extra rounds only when the frontier carries a
         // large share of the remaining in-edges
         a.cap0 = ef * 4 > eu ? MS_CAP0 : (1 << 30);
+        if (split) {
+          // the light sources push first; the tile kernel clears the dead buffer
+          MsArgs ap = a;
+          ap.dead = nullptr;
+          ap.zplane = nullptr;
+          ap.push_lo = a.hub_t;
+          hipLaunchKernelGGL(k_ms_push_split, dim3(MS_PQ_GRID), dim3(MS_PQ_BLOCK), 0, s, ap);
+          hipLaunchKernelGGL(k_ms_hub_or, dim3((std::min(a.hub_t, MS_PQ_HUB) + BLOCK - 1) / BLOCK,
+                                               MS_PQ_GRID / MS_PQ_ROWS), dim3(BLOCK), 0, s, ap);
+          a.split_t = a.hub_t;
+        }
         // a sparse frontier is tested against its LDS summary first: most
         // in-neighbours are rejected without touching the bitmap
         // (the heavy pass, which exits early per chunk, gains from it only
@@ -1309,7 +1501,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         // renumbered by degree: there most in-edges come from the first few
         // hundred KB of bitmap, which stay in cache, and the 32 KB of LDS per
         // workgroup would cost more in occupancy than the filter saves.
-        const bool filt = !(flags & BFS_F_HUB_ORDER);
+        const bool filt = !(flags & BFS_F_HUB_ORDER) && !split;
         const bool sum = filt && (nf << a.sshift) * 8 < (long long)n;
         const bool hsum = filt && (nf << a.sshift) * 64 < (long long)n;
         if (sum)
@@ -1335,6 +1527,15 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
             hipLaunchKernelGGL((k_ms_pull_tile<1, true, true>), gt, dim3(BLOCK), lds, s, a);
           else
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, true, true>), gt, dim3(BLOCK), lds, s, a);
+        } else if (split) {
+          if (wide && rounds)
+            hipLaunchKernelGGL((k_ms_pull_tile<1, false, false, true>), gt, dim3(BLOCK), 0, s, a);
+          else if (wide)
+            hipLaunchKernelGGL((k_ms_pull_tile<1, false, true, true>), gt, dim3(BLOCK), 0, s, a);
+          else if (rounds)
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false, true>), gt, dim3(BLOCK), 0, s, a);
+          else
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true, true>), gt, dim3(BLOCK), 0, s, a);
         } else if (wide) {
           if (rounds)
             hipLaunchKernelGGL((k_ms_pull_tile<1, false, false>), gt, dim3(BLOCK), 0, s, a);
@@ -1347,6 +1548,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true>), gt, dim3(BLOCK), 0, s, a);
         }
         if (timing) BFS_HIP(hipEventRecord(E[2], s));
+        a.split_t = 0;
       } else {
         if (timing) BFS_HIP(hipEventRecord(E[1], s));
         hipLaunchKernelGGL(k_ms_push, dim3(grid_w), dim3(BLOCK), 0, s, a);
@@ -1370,7 +1572,8 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       if (rec && recorded < st->level_capacity) {
         // entry: one level of one group; variant 6 = bottom-up, 0 = top-down
         const int r = recorded++;
-        if (st->level_variant) st->level_variant[r] = dir == 1 ? BFS_V_PULL_B : BFS_V_PUSH_Q_THREAD;
+        if (st->level_variant)
+          st->level_variant[r] = split ? BFS_MS_SPLIT : dir == 1 ? BFS_V_PULL_B : BFS_V_PUSH_Q_THREAD;
         if (st->level_frontier) st->level_frontier[r] = nf;
         if (st->level_frontier_edges) st->level_frontier_edges[r] = ef;
         if (st->level_unvisited) st->level_unvisited[r] = (long long)c.unvis;
@@ -1381,6 +1584,8 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         if (st->level_frontier_ld2) st->level_frontier_ld2[r] = (long long)c.hits;
         if (st->level_scanned_aux) st->level_scanned_aux[r] = (long long)c.hscanned;
         if (st->level_hits_aux) st->level_hits_aux[r] = (long long)c.hhits;
+        if (st->level_scanned_push) st->level_scanned_push[r] = (long long)c.pscan;
+        if (st->level_push_sources) st->level_push_sources[r] = (long long)c.pact;
         if (st->level_ms_main) st->level_ms_main[r] = 0.f;
         if (st->level_ms) st->level_ms[r] = 0.f;
         if (timing) pend_r = r, pend_slot = tslot;
@@ -1393,6 +1598,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       comp += (long long)c.comp_edges;
       nf = (long long)c.active;
       ef = (long long)c.active_out;
+      lout = (long long)c.lout;
       eu -= (long long)c.done_in;
       if (lev > n + 1) {
         set_error("bfs_multi: level loop did not converge");

@@ -165,3 +165,67 @@ def test_level_timing_fills_ms():
         assert np.all(st["ms"][:k] > 0) and np.all(st["ms_main"][:k] > 0)
         assert np.all(st["ms_main"][:k] <= st["ms"][:k] + 1e-3)
         assert float(st["ms"][:k].sum()) <= st["elapsed_ms"] + 1e-3
+
+
+def _split_graphs():
+    yield "rmat12", gg.rmat(12, seed=77), None
+    yield "rmat14", gg.workload("rmat14"), None
+    yield "directed", gg.directed_random(3000, 15000, seed=4, self_loops=True, duplicates=True), \
+        np.arange(0, 3000, 47)[:64]
+    yield "lattice", gg.lattice(90, seed=3), None
+    yield "isolated", gg.from_edge_list(5, [(1, 2)], True), np.array([0, 1, 4])
+    rng = np.random.default_rng(11)
+    n = 9000
+    src = np.concatenate([rng.integers(0, n, 30000), np.full(3000, 7), rng.integers(0, n, 2600)])
+    dst = np.concatenate([rng.integers(0, n, 30000), rng.integers(0, n, 3000), np.full(2600, 4242)])
+    yield "directed_hubs", gg.from_edge_list(n, np.stack([src, dst], 1), False), np.array([7, 4242, 1, 2, 3, 100])
+
+
+@pytest.mark.parametrize("variant", [B.AUTO_HEURISTIC, B.PULL_B])
+def test_forced_split_any_id(variant):
+    """Split bottom-up levels (options.hub_split = T: in-edges from vertices
+    below T pulled, frontier vertices at or above T pushed) give the oracle's
+    depths for every T, and every bottom-up level is split.  On a split level
+    the push expands exactly the frontier vertices >= T and examines all
+    their out-edges (counts from the oracle's depths)."""
+    for name, g, srcs in _split_graphs():
+        g.with_csc()
+        for v in range(g.n):  # the split needs ascending in-edge lists
+            assert np.all(np.diff(g.csc_idx[g.csc_ptr[v]:g.csc_ptr[v + 1]]) >= 0)
+        if srcs is None:
+            srcs = gg.pick_sources(g, 64, 5)
+        ref = oracle.multi(g.row_ptr, g.col_idx, srcs)
+        deg = np.diff(g.row_ptr.astype(np.int64))
+        dg = B.DeviceGraph.from_graph(g)
+        for t in sorted({1, 63, 64, 65, g.n // 3, max(g.n - 1, 1), g.n, g.n + 7}):
+            lv, st = B.bfs_multi(dg, srcs, variant=variant, level_stats=True, hub_split=t)
+            np.testing.assert_array_equal(lv.cpu().numpy(), ref, err_msg=f"{name} T={t} mode {variant}")
+            k = st["num_levels"]
+            assert k == int(ref.max()) + 1
+            var = st["variant"][:k]
+            assert not np.any(var == B.PULL_B), (name, t)
+            if variant == B.PULL_B:
+                assert np.all(var == B.MS_SPLIT), (name, t)
+            tt = min(t, g.n)
+            for lev in range(k):
+                if var[lev] == B.MS_SPLIT:
+                    front = (ref == lev).any(axis=0)
+                    front[:tt] = False
+                    assert int(st["push_sources"][lev]) == int(front.sum()), (name, t, lev)
+                    assert int(st["scanned_push"][lev]) == int(deg[front].sum()), (name, t, lev)
+                    assert int(st["scanned_push"][lev]) <= int(st["scanned"][lev])
+                else:
+                    assert int(st["scanned_push"][lev]) == 0 and int(st["push_sources"][lev]) == 0
+
+
+def test_split_never_and_default_unsplit():
+    """hub_split < 0 never splits; the default splits only graphs marked as
+    numbered by degree (the input order here is not)."""
+    g = gg.workload("rmat14")
+    srcs = gg.pick_sources(g, 64, 5)
+    ref = oracle.multi(g.row_ptr, g.col_idx, srcs)
+    dg = B.DeviceGraph.from_graph(g)
+    for hs in (-1, 0):
+        lv, st = B.bfs_multi(dg, srcs, variant=B.PULL_B, level_stats=True, hub_split=hs)
+        np.testing.assert_array_equal(lv.cpu().numpy(), ref)
+        assert np.all(st["variant"][:st["num_levels"]] == B.PULL_B)

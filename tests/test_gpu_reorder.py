@@ -53,10 +53,10 @@ def test_reorder_matches_oracle(name, g):
         assert rg.csc_ptr.data_ptr() == rg.row_ptr.data_ptr()
 
 
-def _check_mapped(g, srcs, variant):
+def _check_mapped(g, srcs, variant, hub_split=0):
     dg = B.DeviceGraph.from_graph(g)
     rg, new_of_old, _ = B.reorder_degree(dg)
-    lv, st = B.bfs_multi(rg, srcs, variant=variant, vertex_map=new_of_old)
+    lv, st = B.bfs_multi(rg, srcs, variant=variant, vertex_map=new_of_old, hub_split=hub_split)
     lv = lv.cpu().numpy()
     ref = oracle.multi(g.row_ptr, g.col_idx, srcs)
     for i in range(len(srcs)):
@@ -77,6 +77,18 @@ def test_mapped_multi_matches_oracle(variant):
     _check_mapped(g, np.arange(0, 3000, 47)[:64], variant)
     g = gg.from_edge_list(5, [(1, 2)], True)
     _check_mapped(g, np.array([0, 1, 4]), variant)
+
+
+@pytest.mark.parametrize("variant", [B.AUTO_HEURISTIC, B.PULL_B])
+def test_mapped_split_levels(variant):
+    """Renumbered graphs with vertex_map and split bottom-up levels at ids
+    around the hub block (every bottom-up level split)."""
+    g = gg.workload("rmat14")
+    srcs = gg.pick_sources(g, 64, 5)
+    for t in (1, 16, 100, 1000, 5000):
+        _check_mapped(g, srcs, variant, hub_split=t)
+    g = gg.directed_random(3000, 15000, seed=4, self_loops=True, duplicates=True)
+    _check_mapped(g, np.arange(0, 3000, 47)[:64], variant, hub_split=40)
 
 
 @pytest.mark.parametrize("variant", MODES)
@@ -126,7 +138,9 @@ def test_rmat22_64_sources_renumbered_sampled_rows():
     dg = B.DeviceGraph.from_graph(g)
     rg, new_of_old, _ = B.reorder_degree(dg)
     del dg
-    lv, st = B.bfs_multi(rg, srcs, vertex_map=new_of_old)
+    lv, st = B.bfs_multi(rg, srcs, vertex_map=new_of_old, level_stats=True)
+    # the sparse hub frontier after the first level takes a split level
+    assert np.any(st["variant"][:st["num_levels"]] == B.MS_SPLIT)
     lv = lv.cpu().numpy()
     for i in (0, 21, 63):
         np.testing.assert_array_equal(lv[i], oracle.bfs(g.row_ptr, g.col_idx, int(srcs[i]), want_parents=False)[0],
