@@ -511,35 +511,45 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, 
 
 // In place: bcnt/bchk (and bwt) become exclusive offsets; tot = {heavy
 // vertices, chunks}, *tiles = bottom-up tiles (total weight / MS_TWEIGHT + 1).
+// One workgroup: each thread sums a contiguous segment of the nb entries, one
+// block scan per array gives the segments' offsets, and each thread then
+// rewrites its own segment.
 __global__ __launch_bounds__(BLOCK) void k_ms_heavy_scan(int nb, int *bcnt, int *bchk, int *tot, long long *bwt,
                                                          int *tiles) {
   __shared__ int s_w[BLOCK / WAVE];
   __shared__ long long s_wl[BLOCK / WAVE];
-  int rc = 0, rk = 0;
-  long long rw = 0;
-  for (int base = 0; base < nb; base += BLOCK) {
-    const int i = base + threadIdx.x;
-    const int c = i < nb ? bcnt[i] : 0, k = i < nb ? bchk[i] : 0;
-    int tc, tk;
-    const int oc = block_excl_scan(c, &tc, s_w);
-    const int ok = block_excl_scan(k, &tk, s_w);
-    if (i < nb) {
-      bcnt[i] = rc + oc;
-      bchk[i] = rk + ok;
-    }
-    rc += tc;
-    rk += tk;
-    if (bwt) {  // uniform
-      long long tw;
-      const long long ow = block_excl_scan_ll(i < nb ? bwt[i] : 0, &tw, s_wl);
-      if (i < nb) bwt[i] = rw + ow;
-      rw += tw;
+  const int seg = (nb + BLOCK - 1) / BLOCK;
+  const int i0 = min(nb, (int)threadIdx.x * seg), i1 = min(nb, i0 + seg);
+  int c = 0, k = 0;
+  long long w = 0;
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
+    c += bcnt[i];
+    k += bchk[i];
+    if (bwt) w += bwt[i];
+  }
+  int tc, tk;
+  long long tw = 0;
+  int oc = block_excl_scan(c, &tc, s_w);
+  int ok = block_excl_scan(k, &tk, s_w);
+  long long ow = bwt ? block_excl_scan_ll(w, &tw, s_wl) : 0;  // bwt is the same in every thread
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
+    const int xc = bcnt[i], xk = bchk[i];
+    bcnt[i] = oc;
+    bchk[i] = ok;
+    oc += xc;
+    ok += xk;
+    if (bwt) {
+      const long long xw = bwt[i];
+      bwt[i] = ow;
+      ow += xw;
     }
   }
   if (threadIdx.x == 0) {
-    tot[0] = rc;
-    tot[1] = rk;
-    if (bwt) *tiles = (int)(rw / MS_TWEIGHT) + 1;
+    tot[0] = tc;
+    tot[1] = tk;
+    if (bwt) *tiles = (int)(tw / MS_TWEIGHT) + 1;
   }
 }
 
