@@ -206,6 +206,15 @@ __device__ __forceinline__ bool in_front_s(const MsArgs &a, const u32 *s_sum, in
   return in_front(a.fbits, u);
 }
 
+// Frontier test of in-neighbour u (-1: none) before its word is gathered: the
+// summary and bitmap (PROBE), or none on dense frontiers, where nearly every
+// examined in-neighbour is in the frontier and its word, zero off the frontier,
+// is the test itself.
+template <bool SUM, bool PROBE>
+__device__ __forceinline__ bool ms_probe(const MsArgs &a, const u32 *s_sum, int u) {
+  return u >= 0 && (!PROBE || in_front_s<SUM>(a, s_sum, u));
+}
+
 template <bool SUM>
 __device__ __forceinline__ void ms_stage_summary(const MsArgs &a, u32 *s_sum) {
   if (SUM) {
@@ -629,7 +638,7 @@ __device__ __forceinline__ int ms_heavy_of_chunk(const int *hpre, int hcount, in
 constexpr int MS_HU = 4;    // 64-edge rounds per heavy-pass iteration
 constexpr int MS_POST = 1;  // iterations between posts
 
-template <bool SUM>
+template <bool SUM, bool PROBE = true>
 __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
   extern __shared__ u32 s_sum[];
   ms_stage_summary<SUM>(a, s_sum);
@@ -661,14 +670,17 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
       }
       bool hit[MS_HU];
 #pragma unroll
-      for (int r = 0; r < MS_HU; ++r) hit[r] = u[r] >= 0 && in_front_s<SUM>(a, s_sum, u[r]);
+      for (int r = 0; r < MS_HU; ++r) hit[r] = ms_probe<SUM, PROBE>(a, s_sum, u[r]);
       u64 f = 0ull;
 #pragma unroll
       for (int r = 0; r < MS_HU; ++r)
         if (hit[r]) {
-          f |= a.front[u[r]];
-          st.c[C_HITS] += 1;
-          st.c[C_HHITS] += 1;
+          const u64 w = a.front[u[r]];
+          f |= w;
+          if (PROBE || w) {
+            st.c[C_HITS] += 1;
+            st.c[C_HHITS] += 1;
+          }
         }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
@@ -740,7 +752,7 @@ __device__ __forceinline__ void ms_multi_scan(const int (&x)[VPT], int (&off)[VP
 // done-check, one segmented scan per position.  Heavy vertices take the heavy pass's result from accb.  Also
 // writes next, the next bitmap and the discoveries, and clears the dead
 // frontier buffer.  SPLIT: a split level (MsArgs::split_t).
-template <int VPT, bool SUM, bool CONSEC, bool SPLIT = false>
+template <int VPT, bool SUM, bool CONSEC, bool SPLIT = false, bool PROBE = true>
 __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
   constexpr int TV = VPT * BLOCK;
   extern __shared__ u32 s_sum[];
@@ -819,12 +831,13 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       }
       bool hit[MS_HEAD];
 #pragma unroll
-      for (int i = 0; i < MS_HEAD; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
+      for (int i = 0; i < MS_HEAD; ++i) hit[i] = ms_probe<SUM, PROBE>(a, s_sum, u[i]);
 #pragma unroll
       for (int i = 0; i < MS_HEAD; ++i)
         if (hit[i]) {
-          acc[j] |= a.front[u[i]];
-          st.c[C_HITS] += 1;
+          const u64 w = a.front[u[i]];
+          acc[j] |= w;
+          st.c[C_HITS] += (PROBE || w) ? 1 : 0;
         }
       st.c[C_SCAN] += (u32)min(d[j], MS_HEAD);
       if (more && (acc[j] & need[j]) != need[j]) {
@@ -919,7 +932,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
           }
           bool hit[MS_EPT];
   #pragma unroll
-          for (int i = 0; i < MS_EPT; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
+          for (int i = 0; i < MS_EPT; ++i) hit[i] = ms_probe<SUM, PROBE>(a, s_sum, u[i]);
           // OR per owner inside the thread; a segment that ends inside the thread
           // is posted directly, the thread's last segment goes through one
           // segmented scan over the wave (equal owners in neighbouring lanes merge)
@@ -928,7 +941,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
   #pragma unroll
           for (int i = 0; i < MS_EPT; ++i) {
             const u64 f = hit[i] ? a.front[u[i]] : 0ull;
-            st.c[C_HITS] += hit[i] ? 1 : 0;
+            st.c[C_HITS] += (PROBE ? hit[i] : f != 0ull) ? 1 : 0;
             if (own[i] != ro) {
               if (run) atomicOr(&s_acc[ro], run);
               run = 0ull;
@@ -974,11 +987,11 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
           }
           bool hit[MS_EPT];
   #pragma unroll
-          for (int i = 0; i < MS_EPT; ++i) hit[i] = u[i] >= 0 && in_front_s<SUM>(a, s_sum, u[i]);
+          for (int i = 0; i < MS_EPT; ++i) hit[i] = ms_probe<SUM, PROBE>(a, s_sum, u[i]);
   #pragma unroll
           for (int i = 0; i < MS_EPT; ++i) {
             u64 f = hit[i] ? a.front[u[i]] : 0ull;
-            st.c[C_HITS] += hit[i] ? 1 : 0;
+            st.c[C_HITS] += (PROBE ? hit[i] : f != 0ull) ? 1 : 0;
             if (__ballot(f != 0ull)) {
               const int oi = own[i];
   #pragma unroll
@@ -1522,6 +1535,8 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           const int gh = std::min(hsum ? MS_SUM_GRID : 4096, (a.hchunks + 3) / 4);
           if (hsum)
             hipLaunchKernelGGL(k_ms_pull_heavy<true>, dim3(gh), dim3(BLOCK), lds, s, a);
+          else if (ef * 4 > eu)  // dense frontier (see `rounds`): gathers without the bitmap probe
+            hipLaunchKernelGGL((k_ms_pull_heavy<false, false>), dim3(gh), dim3(BLOCK), 0, s, a);
           else
             hipLaunchKernelGGL(k_ms_pull_heavy<false>, dim3(gh), dim3(BLOCK), 0, s, a);
         }
@@ -1539,21 +1554,21 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, true, true>), gt, dim3(BLOCK), lds, s, a);
         } else if (split) {
           if (wide && rounds)
-            hipLaunchKernelGGL((k_ms_pull_tile<1, false, false, true>), gt, dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_ms_pull_tile<1, false, false, true, false>), gt, dim3(BLOCK), 0, s, a);
           else if (wide)
             hipLaunchKernelGGL((k_ms_pull_tile<1, false, true, true>), gt, dim3(BLOCK), 0, s, a);
           else if (rounds)
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false, true>), gt, dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false, true, false>), gt, dim3(BLOCK), 0, s, a);
           else
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true, true>), gt, dim3(BLOCK), 0, s, a);
         } else if (wide) {
-          if (rounds)
-            hipLaunchKernelGGL((k_ms_pull_tile<1, false, false>), gt, dim3(BLOCK), 0, s, a);
+          if (rounds)  // dense frontier: gathers without the bitmap probe
+            hipLaunchKernelGGL((k_ms_pull_tile<1, false, false, false, false>), gt, dim3(BLOCK), 0, s, a);
           else
             hipLaunchKernelGGL((k_ms_pull_tile<1, false, true>), gt, dim3(BLOCK), 0, s, a);
         } else {
           if (rounds)
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false>), gt, dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false, false, false>), gt, dim3(BLOCK), 0, s, a);
           else
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true>), gt, dim3(BLOCK), 0, s, a);
         }
