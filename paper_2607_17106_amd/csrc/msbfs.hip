@@ -1535,7 +1535,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           const int gh = std::min(hsum ? MS_SUM_GRID : 4096, (a.hchunks + 3) / 4);
           if (hsum)
             hipLaunchKernelGGL(k_ms_pull_heavy<true>, dim3(gh), dim3(BLOCK), lds, s, a);
-          else if (ef * 4 > eu)  // dense frontier (see `rounds`): gathers without the bitmap probe
+          else if (ef * 4 > eu || split)  // dense frontier (see `rounds`) or split: gathers without the probe
             hipLaunchKernelGGL((k_ms_pull_heavy<false, false>), dim3(gh), dim3(BLOCK), 0, s, a);
           else
             hipLaunchKernelGGL(k_ms_pull_heavy<false>, dim3(gh), dim3(BLOCK), 0, s, a);
@@ -1556,11 +1556,11 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           if (wide && rounds)
             hipLaunchKernelGGL((k_ms_pull_tile<1, false, false, true, false>), gt, dim3(BLOCK), 0, s, a);
           else if (wide)
-            hipLaunchKernelGGL((k_ms_pull_tile<1, false, true, true>), gt, dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_ms_pull_tile<1, false, true, true, false>), gt, dim3(BLOCK), 0, s, a);
           else if (rounds)
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false, true, false>), gt, dim3(BLOCK), 0, s, a);
           else
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true, true>), gt, dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true, true, false>), gt, dim3(BLOCK), 0, s, a);
         } else if (wide) {
           if (rounds)  // dense frontier: gathers without the bitmap probe
             hipLaunchKernelGGL((k_ms_pull_tile<1, false, false, false, false>), gt, dim3(BLOCK), 0, s, a);
