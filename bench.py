@@ -236,29 +236,34 @@ def main():
     log(f"[bench] renumbered by out-degree in {reorder_s * 1e3:.1f} ms")
 
     # ---------------------------------------------------------- timed step
+    # timing: 0 none, 1 the main kernel of each level (HIP events around it:
+    # the tile kernel's duration for the roofline), 2 every level's step too
     def step(timing, graph=rg, vmap=new_of_old):
-        return B.bfs_multi(graph, sources, flags=B.F_LEVEL_TIMING if timing else 0, workspace=ws_multi,
-                           levels=lv_multi, vertex_map=vmap)[1]
+        flags = (0, B.F_MAIN_TIMING, B.F_LEVEL_TIMING)[timing]
+        return B.bfs_multi(graph, sources, flags=flags, workspace=ws_multi, levels=lv_multi, vertex_map=vmap)[1]
 
     for _ in range(args.warmup):
-        step(False)
+        step(0)
     torch.cuda.synchronize()
     stats = []
     t_start = time.perf_counter()
     for i in range(args.steps):
-        stats.append(step(True))
+        stats.append(step(1))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     log(f"[bench] {args.steps} timed steps done in {elapsed * 1e3:.2f} ms")
     gteps = sum(st["component_edges"] for st in stats) / 2 / elapsed / 1e9
+    # per-level step times for the diagnostics below, from the same steps run
+    # again after the timed region
+    stats_lev = [step(2) for _ in range(args.steps)]
 
     # the same search on the graph as generated (no renumbering), for comparison
     input_order = rcm_order = None
     if not args.no_input_order:
-        step(False, dg, None)
+        step(0, dg, None)
         torch.cuda.synchronize()
         t_in = time.perf_counter()
-        st_in = [step(False, dg, None) for _ in range(args.steps)]
+        st_in = [step(0, dg, None) for _ in range(args.steps)]
         torch.cuda.synchronize()
         el_in = time.perf_counter() - t_in
         input_order = {"gteps": round(sum(st["component_edges"] for st in st_in) / 2 / el_in / 1e9, 3),
@@ -266,10 +271,10 @@ def main():
         log(f"[bench] input order: {input_order}")
         # and on the graph renumbered by reverse Cuthill-McKee
         (cg, cmap, _), rcm_s = timed(lambda: B.reorder_rcm(dg))
-        step(False, cg, cmap)
+        step(0, cg, cmap)
         torch.cuda.synchronize()
         t_c = time.perf_counter()
-        st_c = [step(False, cg, cmap) for _ in range(args.steps)]
+        st_c = [step(0, cg, cmap) for _ in range(args.steps)]
         torch.cuda.synchronize()
         el_c = time.perf_counter() - t_c
         rcm_order = {"gteps": round(sum(st["component_edges"] for st in st_c) / 2 / el_c / 1e9, 3),
@@ -285,31 +290,36 @@ def main():
     per_t, per_b = {}, {}
     for st in stats:
         tb = bytemodel.ms_tile_level_bytes(st, g.n)
+        for k in range(st["num_levels"]):
+            if tb[k] is not None:
+                t_tile += float(st["ms_main"][k])
+                b_tile += tb[k]
+                n_tile += 1
+    tile_lev = 0.0
+    for st in stats_lev:
         lb = bytemodel.ms_level_bytes(st, g.n)
         for k in range(st["num_levels"]):
             v = {B.PULL_B: "bottom_up_step", B.MS_SPLIT: "split_step"}.get(int(st["variant"][k]), "top_down_step")
             per_t[v] = per_t.get(v, 0.0) + float(st["ms"][k])
             per_b[v] = per_b.get(v, 0.0) + lb[k]
-            if tb[k] is not None:
-                t_tile += float(st["ms_main"][k])
-                b_tile += tb[k]
-                n_tile += 1
+            if int(st["variant"][k]) in (B.PULL_B, B.MS_SPLIT):
+                tile_lev += float(st["ms_main"][k])
     achieved = b_tile / (t_tile * 1e-3) / 1e9
-    step_level_ms = sum(per_t.values()) / len(stats)
+    step_level_ms = sum(per_t.values()) / len(stats_lev)
     traffic = tile_traffic_bytes() if args.workload == "rmat22" and len(sources) == 64 else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None, "kernel": "k_ms_pull_tile",
             "launches": n_tile, "avg_launch_us": round(t_tile * 1e3 / max(n_tile, 1), 2),
             "bytes_per_launch": round(b_tile / max(n_tile, 1)),
-            "time_share_of_level_steps": round(t_tile / len(stats) / step_level_ms, 3),
+            "time_share_of_level_steps": round(tile_lev / len(stats_lev) / step_level_ms, 3),
             "level_steps_gbs": {k: round(per_b[k] / (per_t[k] * 1e-3) / 1e9, 1) for k in per_t}}
     copy_gbs = copy_rate_gbs(torch)
     roof["copy_gbs"] = round(copy_gbs, 1)
     roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if traffic is not None:
         roof["traffic_over_algorithmic"] = round(traffic / (b_tile / max(n_tile, 1)), 2)
-    st0 = stats[0]
+    st0 = stats_lev[0]
     for k in range(st0["num_levels"]):
         log(f"[bench] ms level {k}: {({B.PULL_B: 'pull', B.MS_SPLIT: 'split'}).get(int(st0['variant'][k]), 'push')} "
             f"active={st0['frontier'][k]} ef={st0['frontier_edges'][k]} eu={st0['unvisited_edges'][k]} "

@@ -129,6 +129,9 @@ int bfs_version(void);
                                     stay in cache and they skip the LDS frontier summary,
                                     and sparse bottom-up levels may be split at the heavy
                                     vertices (options.hub_split = 0) */
+#define BFS_F_MAIN_TIMING 128    /* bfs_multi: time only each level's main kernel (fills
+                                    level_ms_main, not level_ms; implies BFS_F_LEVEL_STATS):
+                                    two HIP events per level instead of four */
 
 /* ----------------------------------------------------------------- types */
 typedef struct bfs_graph {

@@ -51,6 +51,7 @@ F_DEVICE_LOOP = 8
 F_LEVEL_TIMING = 16
 F_GRAPH_SUMS = 32
 F_HUB_ORDER = 64
+F_MAIN_TIMING = 128
 
 MLP_NPARAM = 5252
 MLP_NFEAT = 12

@@ -282,7 +282,7 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
     k = int(src.size)
     if levels is None:
         levels = torch.empty((max(k, 1), g.n), dtype=torch.int32, device=g.row_ptr.device)
-    if flags & L.F_LEVEL_TIMING:
+    if flags & (L.F_LEVEL_TIMING | L.F_MAIN_TIMING):
         level_stats = True
     if level_stats:
         flags |= L.F_LEVEL_STATS

@@ -1339,8 +1339,10 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   long long reached = 0, comp = 0;
   int max_levels = 0, syncs = 0;
   const int flags = opt ? opt->flags : 0;
-  const bool rec = st && (flags & (BFS_F_LEVEL_STATS | BFS_F_LEVEL_TIMING)) && st->level_capacity > 0;
-  const bool timing = rec && (flags & BFS_F_LEVEL_TIMING);
+  const bool rec =
+      st && (flags & (BFS_F_LEVEL_STATS | BFS_F_LEVEL_TIMING | BFS_F_MAIN_TIMING)) && st->level_capacity > 0;
+  const bool timing = rec && (flags & BFS_F_LEVEL_TIMING);             // all four events per level
+  const bool mtiming = rec && (flags & (BFS_F_LEVEL_TIMING | BFS_F_MAIN_TIMING));  // main kernel's two
   int recorded = 0;
   // level timing: the entry whose events are still to be read (-1: none)
   int tslot = 0, pend_r = -1, pend_slot = 0;
@@ -1352,7 +1354,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       BFS_HIP(hipEventElapsedTime(&ms, P[1], P[2]));
       st->level_ms_main[pend_r] = ms;
     }
-    if (st->level_ms) {
+    if (st->level_ms && timing) {
       BFS_HIP(hipEventElapsedTime(&ms, P[0], P[3]));
       st->level_ms[pend_r] = ms;
     }
@@ -1542,7 +1544,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         }
         // one vertex per thread while many in-edges remain to be scanned (more
         // workgroups in flight); four when few do (fixed costs amortised)
-        if (timing) BFS_HIP(hipEventRecord(E[1], s));
+        if (mtiming) BFS_HIP(hipEventRecord(E[1], s));
         const bool rounds = a.cap0 < (1 << 30);  // dense frontier: per-position walk
         const bool wide = eu > 2 * (long long)n;
         const dim3 gt(wide ? (sum ? std::min(grid_t1, MS_SUM_GRID) : grid_t1)
@@ -1572,12 +1574,12 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           else
             hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true>), gt, dim3(BLOCK), 0, s, a);
         }
-        if (timing) BFS_HIP(hipEventRecord(E[2], s));
+        if (mtiming) BFS_HIP(hipEventRecord(E[2], s));
         a.split_t = 0;
       } else {
-        if (timing) BFS_HIP(hipEventRecord(E[1], s));
+        if (mtiming) BFS_HIP(hipEventRecord(E[1], s));
         hipLaunchKernelGGL(k_ms_push, dim3(grid_w), dim3(BLOCK), 0, s, a);
-        if (timing) BFS_HIP(hipEventRecord(E[2], s));
+        if (mtiming) BFS_HIP(hipEventRecord(E[2], s));
         if (a.ochunks > 0)
           hipLaunchKernelGGL(k_ms_push_heavy, dim3(std::min(4096, (a.ochunks + 3) / 4)), dim3(BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
@@ -1613,7 +1615,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         if (st->level_push_sources) st->level_push_sources[r] = (long long)c.pact;
         if (st->level_ms_main) st->level_ms_main[r] = 0.f;
         if (st->level_ms) st->level_ms[r] = 0.f;
-        if (timing) pend_r = r, pend_slot = tslot;
+        if (mtiming) pend_r = r, pend_slot = tslot;
       }
       ++tslot;
       if (dir == 1 && c.hpend == 0) heavy_done = true;  // visited words only grow

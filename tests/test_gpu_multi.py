@@ -229,3 +229,17 @@ def test_split_never_and_default_unsplit():
         lv, st = B.bfs_multi(dg, srcs, variant=B.PULL_B, level_stats=True, hub_split=hs)
         np.testing.assert_array_equal(lv.cpu().numpy(), ref)
         assert np.all(st["variant"][:st["num_levels"]] == B.PULL_B)
+
+
+def test_main_timing_only():
+    """BFS_F_MAIN_TIMING: each level's main kernel is timed (level_ms_main),
+    the level's whole step is not (level_ms stays 0); depths unchanged."""
+    g = gg.workload("rmat14")
+    srcs = gg.pick_sources(g, 64, 5)
+    dg = B.DeviceGraph.from_graph(g)
+    lv, st = B.bfs_multi(dg, srcs, flags=B.F_MAIN_TIMING)
+    k = st["num_levels"]
+    assert k > 0
+    assert np.all(st["ms_main"][:k] > 0) and np.all(st["ms"][:k] == 0)
+    assert float(st["ms_main"][:k].sum()) <= st["elapsed_ms"] + 1e-3
+    np.testing.assert_array_equal(lv.cpu().numpy(), oracle.multi(g.row_ptr, g.col_idx, srcs))
