@@ -450,18 +450,42 @@ __device__ __forceinline__ int ms_wave_lower_bound(const int *x, int lo, int hi,
 // Vertices with in-degree (CSC) or out-degree (CSR) > MS_HEAVY, in increasing
 // order, and the prefix of their chunk counts: a count pass per MS_HB vertices, a one-workgroup scan of
 // the per-workgroup totals, and a write pass.  Built once per call.
-__device__ __forceinline__ int ms_heavy_chunks(const int *cp, int v) {
-  const int d = cp[v + 1] - cp[v];
-  return d > MS_HEAVY ? (d + MS_HCHUNK - 1) / MS_HCHUNK : 0;
+// Each thread takes 4 consecutive vertices of its workgroup's MS_HB (one pass,
+// one scan per array); 16 neighbouring lanes hold one 64-vertex tile chunk.
+static_assert(MS_HB == 4 * BLOCK, "four vertices per thread in the heavy-list build");
+
+// Vertices v .. v+3 (those below v1 <= n): h[i] = chunks of v+i if heavy
+// (else 0); *light = the sum of the light ones' degrees.
+__device__ __forceinline__ void ms_quad(const int *cp, int v, int v1, int (&h)[4], u64 *light) {
+  int c[5];
+  if (v + 4 <= v1) {  // all four: one 16-byte load (4-byte aligned) and one more
+    const I4u q = *reinterpret_cast<const I4u *>(cp + v);
+    c[0] = q.x;
+    c[1] = q.y;
+    c[2] = q.z;
+    c[3] = q.w;
+    c[4] = cp[v + 4];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) c[i] = v + i <= v1 ? cp[v + i] : 0;
+  }
+  u64 l = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int d = v + i < v1 ? c[i + 1] - c[i] : 0;
+    h[i] = d > MS_HEAVY ? (d + MS_HCHUNK - 1) / MS_HCHUNK : 0;
+    l += d <= MS_HEAVY ? (u64)d : 0ull;
+  }
+  *light = l;
 }
 
-// Tile weight of the 64-vertex chunk this wave covers (vertices v0 .. v0 + 63,
-// those below n; see MS_TALPHA), the same value in every lane.
-__device__ __forceinline__ long long ms_chunk_weight(const int *cp, int v0, int n) {
-  const int v = v0 + lane();
-  const int d = v < n ? cp[v + 1] - cp[v] : 0;
-  const u64 light = wave_sum_u64(d <= MS_HEAVY ? (u64)d : 0ull);
-  const long long floor_w = (long long)min(n - v0, WAVE) * MS_TALPHA;
+// Tile weight of the 64-vertex chunk starting at cw (see MS_TALPHA) from the
+// 16 lanes holding it: every lane of the group passes its `light`; the
+// result is valid in all 16.
+__device__ __forceinline__ long long ms_chunk_weight16(u64 light, int cw, int n) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) light += __shfl_xor(light, o);
+  const long long floor_w = (long long)min(n - cw, WAVE) * MS_TALPHA;
   return max(floor_w, (long long)light);
 }
 
@@ -493,18 +517,21 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, 
   __shared__ int s_w[BLOCK / WAVE];
   __shared__ long long s_wl[BLOCK / WAVE];
   const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
+  const int v = v0 + 4 * (int)threadIdx.x;
+  int h[4] = {0, 0, 0, 0};
+  u64 light = 0;
+  if (v < v1) ms_quad(cp, v, v1, h, &light);
   int c = 0, k = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    c += h[i] ? 1 : 0;
+    k += h[i];
+  }
   long long wt = 0;
-  for (int vb = v0; vb < v1; vb += BLOCK) {  // uniform per workgroup; wave w covers one chunk
-    const int v = vb + threadIdx.x;
-    const int h = v < v1 ? ms_heavy_chunks(cp, v) : 0;
-    c += h ? 1 : 0;
-    k += h;
-    const int cw = vb + (threadIdx.x & ~(WAVE - 1));
-    if (bwt && cw < v1) {  // uniform per wave
-      const long long w = ms_chunk_weight(cp, cw, n);
-      if (lane() == 0) wt += w;
-    }
+  if (bwt) {  // uniform
+    const int cw = v0 + WAVE * (int)(threadIdx.x / 16);
+    const long long w = ms_chunk_weight16(light, cw, n);
+    if ((threadIdx.x & 15) == 0 && cw < v1) wt = w;
   }
   int tc, tk;
   long long tw;
@@ -520,47 +547,89 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, 
 
 // In place: bcnt/bchk (and bwt) become exclusive offsets; tot = {heavy
 // vertices, chunks}, *tiles = bottom-up tiles (total weight / MS_TWEIGHT + 1).
-// One workgroup: each thread sums a contiguous segment of the nb entries, one
-// block scan per array gives the segments' offsets, and each thread then
-// rewrites its own segment.
+// One workgroup, MS_SCAN_CH entries at a time staged in LDS (coalesced loads
+// and stores): each thread sums a contiguous segment, one block scan per array
+// gives the segments' offsets, each thread rewrites its segment.
+constexpr int MS_SCAN_CH = 4096;
 __global__ __launch_bounds__(BLOCK) void k_ms_heavy_scan(int nb, int *bcnt, int *bchk, int *tot, long long *bwt,
                                                          int *tiles) {
+  __shared__ int s_c[MS_SCAN_CH], s_k[MS_SCAN_CH];
+  __shared__ long long s_x[MS_SCAN_CH];
   __shared__ int s_w[BLOCK / WAVE];
   __shared__ long long s_wl[BLOCK / WAVE];
-  const int seg = (nb + BLOCK - 1) / BLOCK;
-  const int i0 = min(nb, (int)threadIdx.x * seg), i1 = min(nb, i0 + seg);
-  int c = 0, k = 0;
-  long long w = 0;
-#pragma unroll 4
-  for (int i = i0; i < i1; ++i) {
-    c += bcnt[i];
-    k += bchk[i];
-    if (bwt) w += bwt[i];
-  }
-  int tc, tk;
-  long long tw = 0;
-  int oc = block_excl_scan(c, &tc, s_w);
-  int ok = block_excl_scan(k, &tk, s_w);
-  long long ow = bwt ? block_excl_scan_ll(w, &tw, s_wl) : 0;  // bwt is the same in every thread
-#pragma unroll 4
-  for (int i = i0; i < i1; ++i) {
-    const int xc = bcnt[i], xk = bchk[i];
-    bcnt[i] = oc;
-    bchk[i] = ok;
-    oc += xc;
-    ok += xk;
-    if (bwt) {
-      const long long xw = bwt[i];
-      bwt[i] = ow;
-      ow += xw;
+  constexpr int SEG = MS_SCAN_CH / BLOCK;
+  int rc = 0, rk = 0;
+  long long rw = 0;
+  for (int base = 0; base < nb; base += MS_SCAN_CH) {  // uniform
+    const int m = min(MS_SCAN_CH, nb - base);
+    {  // all loads in flight before the first LDS store: registers first, from
+       // in-range addresses (clamped, so no branch around a load)
+      int xc[SEG], xk[SEG];
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) {
+        const int i = base + min((int)threadIdx.x + j * BLOCK, m - 1);
+        xc[j] = bcnt[i];
+        xk[j] = bchk[i];
+      }
+      if (bwt) {  // uniform
+        long long xw[SEG];
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) xw[j] = bwt[base + min((int)threadIdx.x + j * BLOCK, m - 1)];
+#pragma unroll
+        for (int j = 0; j < SEG; ++j)
+          if ((int)threadIdx.x + j * BLOCK < m) s_x[threadIdx.x + j * BLOCK] = xw[j];
+      }
+#pragma unroll
+      for (int j = 0; j < SEG; ++j)
+        if ((int)threadIdx.x + j * BLOCK < m) {
+          s_c[threadIdx.x + j * BLOCK] = xc[j];
+          s_k[threadIdx.x + j * BLOCK] = xk[j];
+        }
     }
+    __syncthreads();
+    const int i0 = threadIdx.x * SEG, i1 = min(m, i0 + SEG);
+    int c = 0, k = 0;
+    long long w = 0;
+    for (int i = i0; i < i1; ++i) {
+      c += s_c[i];
+      k += s_k[i];
+      if (bwt) w += s_x[i];
+    }
+    int tc, tk;
+    long long tw = 0;
+    int oc = rc + block_excl_scan(c, &tc, s_w);
+    int ok = rk + block_excl_scan(k, &tk, s_w);
+    long long ow = bwt ? rw + block_excl_scan_ll(w, &tw, s_wl) : 0;  // bwt is the same in every thread
+    for (int i = i0; i < i1; ++i) {
+      const int xc = s_c[i], xk = s_k[i];
+      s_c[i] = oc;
+      s_k[i] = ok;
+      oc += xc;
+      ok += xk;
+      if (bwt) {
+        const long long xw = s_x[i];
+        s_x[i] = ow;
+        ow += xw;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += BLOCK) {
+      bcnt[base + i] = s_c[i];
+      bchk[base + i] = s_k[i];
+      if (bwt) bwt[base + i] = s_x[i];
+    }
+    rc += tc;
+    rk += tk;
+    rw += tw;
+    __syncthreads();  // the next chunk reuses the LDS arrays
   }
   if (threadIdx.x == 0) {
-    tot[0] = tc;
-    tot[1] = tk;
-    if (bwt) *tiles = (int)(tw / MS_TWEIGHT) + 1;
+    tot[0] = rc;
+    tot[1] = rk;
+    if (bwt) *tiles = (int)(rw / MS_TWEIGHT) + 1;
   }
 }
+static_assert(MS_SCAN_CH % BLOCK == 0, "whole segments");
 
 // Also clears accb of every heavy vertex (the only entries the pull uses)
 // when accb is given.
@@ -573,32 +642,37 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, 
   __shared__ int s_w[BLOCK / WAVE];
   __shared__ long long s_wl[BLOCK / WAVE];
   const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
-  int rc = bcnt[blockIdx.x], rk = bchk[blockIdx.x];
-  long long rw = bwt ? bwt[blockIdx.x] : 0;
-  for (int vb = v0; vb < v1; vb += BLOCK) {  // uniform per workgroup
-    const int v = vb + threadIdx.x;
-    const int h = v < v1 ? ms_heavy_chunks(cp, v) : 0;
-    int tc, tk;
-    const int oc = block_excl_scan(h ? 1 : 0, &tc, s_w);
-    const int ok = block_excl_scan(h, &tk, s_w);
-    if (h) {
-      hv[rc + oc] = v;
-      hpre[rc + oc] = rk + ok;
-      if (accb) accb[v] = 0ull;
+  const int v = v0 + 4 * (int)threadIdx.x;
+  int h[4] = {0, 0, 0, 0};
+  u64 light = 0;
+  if (v < v1) ms_quad(cp, v, v1, h, &light);
+  int c = 0, k = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    c += h[i] ? 1 : 0;
+    k += h[i];
+  }
+  int tc, tk;
+  int pos = bcnt[blockIdx.x] + block_excl_scan(c, &tc, s_w);
+  int chk = bchk[blockIdx.x] + block_excl_scan(k, &tk, s_w);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (h[i]) {
+      hv[pos] = v + i;
+      hpre[pos] = chk;
+      if (accb) accb[v + i] = 0ull;
+      ++pos;
+      chk += h[i];
     }
-    rc += tc;
-    rk += tk;
-    if (bwt) {  // uniform
-      const int cw = vb + (threadIdx.x & ~(WAVE - 1));
-      const long long w = cw < v1 ? ms_chunk_weight(cp, cw, n) : 0;  // cw < v1 uniform per wave
-      long long tw;
-      const long long ow = block_excl_scan_ll(lane() == 0 ? w : 0, &tw, s_wl);
-      if (lane() == 0 && cw < v1) {
-        const long long key = rw + ow;
-        const int e = min(cw + WAVE, n), last = *tiles - 1;
-        for (long long t = key / MS_TWEIGHT + 1; t <= (key + w) / MS_TWEIGHT && t <= last; ++t) tstart[t] = e;
-      }
-      rw += tw;
+  if (bwt) {  // uniform
+    const int cw = v0 + WAVE * (int)(threadIdx.x / 16);
+    const long long w = ms_chunk_weight16(light, cw, n);
+    const bool lead = (threadIdx.x & 15) == 0 && cw < v1;
+    long long tw;
+    const long long key = bwt[blockIdx.x] + block_excl_scan_ll(lead ? w : 0, &tw, s_wl);
+    if (lead) {
+      const int e = min(cw + WAVE, n), last = *tiles - 1;
+      for (long long t = key / MS_TWEIGHT + 1; t <= (key + w) / MS_TWEIGHT && t <= last; ++t) tstart[t] = e;
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1251,11 +1325,16 @@ __global__ __launch_bounds__(NSH) void k_ms_finish(MsCtr *sh, MsCtr *tot, u64 se
   __shared__ u64 s_red[MS_NCTR][NSH / WAVE];
   const int t = threadIdx.x;
   u64 *f = reinterpret_cast<u64 *>(sh + t);
+  u64 x[MS_NCTR];  // all of the shard's loads in flight before the first reduction
+#pragma unroll
+  for (int j = 0; j < MS_NCTR; ++j) x[j] = f[j];
+#pragma unroll
+  for (int j = 0; j < MS_NCTR; ++j) f[j] = 0ull;
+#pragma unroll
   for (int j = 0; j < MS_NCTR; ++j) {
-    u64 r = wave_sum_u64(f[j]);
+    const u64 r = wave_sum_u64(x[j]);
     if (lane() == 0) s_red[j][t / WAVE] = r;
   }
-  for (int j = 0; j < MS_NCTR; ++j) f[j] = 0ull;
   __syncthreads();
   if (t == 0) {
     u64 *o = reinterpret_cast<u64 *>(tot);
