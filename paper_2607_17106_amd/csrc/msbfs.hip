@@ -108,7 +108,8 @@ struct MsArgs {
   int hcount, hchunks;
   const int *ov;        // the same for out-degree (CSR): heavy sources of the top-down step
   const int *opre;
-  int ocount, ochunks;
+  int ocount, ochunks;  // -1: not read back yet; k_ms_push_heavy takes them from otot
+  const int *otot;      // device {ocount, ochunks}
   int *levels;          // row l at levels + l * n
   const int *vmap;      // or null: column v of `levels` is vertex vmap[v] of the (renumbered) graph
   u32 *hsrc;            // top-down: set by k_ms_push when the frontier holds a heavy source, cleared by
@@ -123,7 +124,8 @@ struct MsArgs {
   // hub frontier's full in-edge scan into the hubs' in-edges plus a few light
   // out-edges.
   int hub_t;            // split id of this call (0: none); discoveries at or above it count their
-                        // out-edges in lout
+                        // out-edges in lout (-1 before the host has read it: k_ms_push_update
+                        // takes otot[0], the heavy out-degree count)
   int split_t;          // this level's split id (0: not a split level)
   int push_lo;          // k_ms_push: first vertex to expand (split level: split_t; else 0)
   u64 *hubst;           // split level: staging rows of k_ms_push_split (MS_PQ_GRID x MS_PQ_HUB words)
@@ -1255,6 +1257,10 @@ static_assert(MS_PQ_GRID % MS_PQ_ROWS == 0, "staging rows split evenly");
 // list is spread over many waves.
 __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
   if (__hip_atomic_load(a.hsrc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;  // uniform
+  if (a.ochunks < 0) {  // the first level, enqueued before the host read the heavy-list totals
+    a.ocount = a.otot[0];
+    a.ochunks = a.otot[1];
+  }
   MsStats st;
   const int wv = threadIdx.x / WAVE;
   for (int q = blockIdx.x * (BLOCK / WAVE) + wv; q < a.ochunks; q += gridDim.x * (BLOCK / WAVE)) {
@@ -1288,6 +1294,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
 // Owner-computes update after a push: F_{k+1}[v] = next[v] (already masked).
 __global__ __launch_bounds__(BLOCK) void k_ms_push_update(MsArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.hsrc = 0u;  // k_ms_push_heavy has finished
+  if (a.hub_t < 0) a.hub_t = a.otot[0];  // the first level (see MsArgs::hub_t)
   MsStats st;
   for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {  // uniform per wave
     const int v = base + threadIdx.x;
@@ -1480,34 +1487,31 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, a, sv, fr[0], W.fb[0], (const int *)htot_dev, post_host,
                        post_seq, seed_seq);
     BFS_HIP(hipGetLastError());
-    rc = wait_posted(post_seq, seed_seq, s);
-    if (rc) return rc;
-    a.hcount = htot_host[0];
-    a.hchunks = htot_host[1];
-    a.ntiles = htot_host[4];
-    const int grid_t1 = std::min(65536, a.ntiles);
-    const int grid_t4 = std::min(65536, (a.ntiles + MS_VPT_SPARSE - 1) / MS_VPT_SPARSE);
-    if (g->row_ptr != g->csc_ptr) {
-      a.ov = W.ov;
-      a.opre = W.opre;
-      a.ocount = htot_host[2];
-      a.ochunks = htot_host[3];
-    } else {
-      a.ov = W.hv;
-      a.opre = W.hpre;
-      a.ocount = a.hcount;
-      a.ochunks = a.hchunks;
-    }
     // split id: vertices below it are pulled on a split bottom-up level, the
     // frontier vertices at or above it push (options.hub_split > 0: that id on
     // every bottom-up level; 0: on a graph numbered by decreasing degree, its
     // heavy out-degree vertices, where the cost rule below picks it; < 0: never)
     const int hub_req = opt ? opt->hub_split : 0;
-    a.hub_t = hub_req > 0 ? std::min(hub_req, n) : (hub_req == 0 && (flags & BFS_F_HUB_ORDER)) ? a.ocount : 0;
+    const bool hub_auto = hub_req == 0 && (flags & BFS_F_HUB_ORDER);
     a.push_lo = 0;
     a.split_t = 0;
+    const bool sym = g->row_ptr == g->csc_ptr;
+    a.ov = sym ? W.hv : W.ov;
+    a.opre = sym ? W.hpre : W.opre;
+    a.otot = sym ? htot_dev : htot_dev + 2;
+    int grid_t1 = 0, grid_t4 = 0;
     long long nf = 0, ef = 0, src_comp = 0;
-    {
+    // What the seed kernel posted: the heavy-list and tile totals, and the
+    // count and out-edges of F_0 for the direction rule.
+    auto take_seed = [&]() {
+      a.hcount = htot_host[0];
+      a.hchunks = htot_host[1];
+      a.ntiles = htot_host[4];
+      grid_t1 = std::min(65536, a.ntiles);
+      grid_t4 = std::min(65536, (a.ntiles + MS_VPT_SPARSE - 1) / MS_VPT_SPARSE);
+      a.ocount = sym ? a.hcount : htot_host[2];
+      a.ochunks = sym ? a.hchunks : htot_host[3];
+      a.hub_t = hub_req > 0 ? std::min(hub_req, n) : hub_auto ? a.ocount : 0;
       std::vector<std::pair<int, int>> sd;
       for (int i = 0; i < L; ++i) {
         sd.push_back({sources[g0 + i], deg_host[i]});
@@ -1519,6 +1523,19 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           ++nf;
           ef += sd[i].second;
         }
+    };
+    // Except when every level is bottom-up, the first level (a frontier of at
+    // most 64 sources) is top-down: it is enqueued at once, without waiting
+    // for the seed's post, which the host reads with that level's counters.
+    bool seed_read = mode == BFS_V_PULL_B;
+    if (seed_read) {
+      rc = wait_posted(post_seq, seed_seq, s);
+      if (rc) return rc;
+      take_seed();
+    } else {
+      a.hcount = a.hchunks = a.ntiles = 0;  // not used by a top-down level
+      a.ocount = a.ochunks = -1;
+      a.hub_t = hub_req > 0 ? std::min(hub_req, n) : hub_auto ? -1 : 0;
     }
     long long eu = g->nnz;  // in-edges of vertices still missing some lane
     long long lout = ef;    // out-edges of the frontier vertices at or above hub_t (level 0: an upper bound)
@@ -1529,7 +1546,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     int lev = 0;
     for (;;) {
       int dir;
-      if (mode == BFS_V_PUSH_Q_THREAD || mode == BFS_V_PUSH_Q_BLOCK || mode == BFS_V_PUSH_Q_MERGE)
+      if (mode == BFS_V_PUSH_Q_THREAD || mode == BFS_V_PUSH_Q_BLOCK || mode == BFS_V_PUSH_Q_MERGE || !seed_read)
         dir = 0;
       else if (mode == BFS_V_PULL_B)
         dir = 1;
@@ -1659,8 +1676,12 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         if (mtiming) BFS_HIP(hipEventRecord(E[1], s));
         hipLaunchKernelGGL(k_ms_push, dim3(grid_w), dim3(BLOCK), 0, s, a);
         if (mtiming) BFS_HIP(hipEventRecord(E[2], s));
-        if (a.ochunks > 0)
-          hipLaunchKernelGGL(k_ms_push_heavy, dim3(std::min(4096, (a.ochunks + 3) / 4)), dim3(BLOCK), 0, s, a);
+        // chunk count not read back yet (first level): a grid for any graph; the kernel
+        // reads the count, and returns at once unless a heavy source is in the frontier
+        const long long och = a.ochunks >= 0 ? a.ochunks : 2 * (long long)g->nnz / MS_HCHUNK + 1;
+        if (och > 0)
+          hipLaunchKernelGGL(k_ms_push_heavy, dim3((int)std::min<long long>(4096, (och + 3) / 4)), dim3(BLOCK), 0,
+                             s, a);
         hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
       }
       if (timing) BFS_HIP(hipEventRecord(E[3], s));
@@ -1675,6 +1696,11 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       ++syncs;
       MsCtr c;
       memcpy(&c, hc.pinned, sizeof(c));
+      if (!seed_read) {  // the seed kernel's post is complete: it ran before this level
+        take_seed();
+        prev_nf = nf;  // the direction rule's state after a first level it did not choose
+        seed_read = true;
+      }
       if (rec && recorded < st->level_capacity) {
         // entry: one level of one group; variant 6 = bottom-up, 0 = top-down
         const int r = recorded++;
