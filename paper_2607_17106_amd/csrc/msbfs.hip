@@ -66,6 +66,9 @@ constexpr long long MS_TWEIGHT = (long long)BLOCK * MS_TALPHA;
 // tiles for n vertices and any int32 edge count (a chunk weighs at most
 // 64 * MS_TALPHA plus its in-edges)
 constexpr long long ms_tile_cap(long long n) { return n / BLOCK + (1ll << 31) / MS_TWEIGHT + 4; }
+// Chunk-to-owner tables of the heavy lists: entries for chunks below this
+// many; later chunks (graphs with far more edges than vertices) search hpre.
+constexpr long long ms_hq_cap(long long n) { return n * 2 + 1024 < (1ll << 22) ? n * 2 + 1024 : (1ll << 22); }
 static_assert(MS_HCHUNK <= MS_HEAVY, "a heavy list is longer than one chunk");
 
 struct MsCtr {  // two 64-byte lines per shard
@@ -106,6 +109,8 @@ struct MsArgs {
   const int *hv;        // heavy vertices in increasing order
   const int *hpre;      // hpre[i]: first chunk of hv[i]; hpre[hcount] = hchunks
   int hcount, hchunks;
+  const int *hq, *oq;   // chunk q's index in hv (ov) for q < hqcap
+  int hqcap;
   const int *ov;        // the same for out-degree (CSR): heavy sources of the top-down step
   const int *opre;
   int ocount, ochunks;  // -1: not read back yet; k_ms_push_heavy takes them from otot
@@ -143,7 +148,7 @@ struct MsArgs {
 struct MsCarve {
   u64 *fr[3], *vis, *flushed, *accb, *planes, *fb[2];
   u32 *fsum;
-  int *hv, *hpre, *ov, *opre, *bcnt, *bchk, *tstart;
+  int *hv, *hpre, *ov, *opre, *bcnt, *bchk, *tstart, *hq, *oq;
   u64 *hubst;
   long long *bwt;       // per heavy-list block: tile weight of its chunks, then their exclusive prefix
   MsCtr *sh, *tot;
@@ -179,6 +184,10 @@ static MsCarve ms_carve(uintptr_t p, int n) {
   off += nb;
   c.bchk = reinterpret_cast<int *>(p + off);
   off += nb;
+  c.hq = reinterpret_cast<int *>(p + off);
+  off += al((size_t)ms_hq_cap(n) * 4);
+  c.oq = reinterpret_cast<int *>(p + off);
+  off += al((size_t)ms_hq_cap(n) * 4);
   c.tstart = reinterpret_cast<int *>(p + off);
   off += al((size_t)ms_tile_cap(n) * 4);
   c.bwt = reinterpret_cast<long long *>(p + off);
@@ -639,8 +648,9 @@ static_assert(MS_SCAN_CH % BLOCK == 0, "whole segments");
 // for each tile t whose first weight t * MS_TWEIGHT lies in (key, key + w_c]
 // (tiles inside one chunk's span are empty); tstart[0] = 0, tstart[tiles] = n.
 __global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, const int *bcnt, const int *bchk,
-                                                          int *hv, int *hpre, u64 *accb, const int *tot,
-                                                          const long long *bwt, int *tstart, const int *tiles) {
+                                                          int *hv, int *hpre, int *hq, int hqcap, u64 *accb,
+                                                          const int *tot, const long long *bwt, int *tstart,
+                                                          const int *tiles) {
   __shared__ int s_w[BLOCK / WAVE];
   __shared__ long long s_wl[BLOCK / WAVE];
   const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
@@ -662,6 +672,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, 
     if (h[i]) {
       hv[pos] = v + i;
       hpre[pos] = chk;
+      for (int q = chk; q < chk + h[i] && q < hqcap; ++q) hq[q] = pos;
       if (accb) accb[v + i] = 0ull;
       ++pos;
       chk += h[i];
@@ -691,6 +702,13 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, 
 // (hpre[hcount] = hchunks > q).  Wave-uniform 64-ary search: each round the
 // 64 lanes test 64 evenly spaced entries of the current interval and a ballot
 // narrows it 64-fold, so 12K heavy vertices take 3 rounds of one load each.
+__device__ __forceinline__ int ms_heavy_of_chunk(const int *hpre, int hcount, int q);
+
+// The same from the chunk-to-owner table where it has the entry.
+__device__ __forceinline__ int ms_chunk_owner(const int *hq, int hqcap, const int *hpre, int hcount, int q) {
+  return q < hqcap ? hq[q] : ms_heavy_of_chunk(hpre, hcount, q);
+}
+
 __device__ __forceinline__ int ms_heavy_of_chunk(const int *hpre, int hcount, int q) {
   int lo = 0, hi = hcount;  // hpre[lo] <= q < hpre[hi]
   while (hi - lo > 1) {
@@ -721,7 +739,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
   MsStats st;
   const int wv = threadIdx.x / WAVE;
   for (int q = blockIdx.x * (BLOCK / WAVE) + wv; q < a.hchunks; q += gridDim.x * (BLOCK / WAVE)) {
-    const int i = ms_heavy_of_chunk(a.hpre, a.hcount, q);
+    const int i = ms_chunk_owner(a.hq, a.hqcap, a.hpre, a.hcount, q);
     const int v = a.hv[i];
     const u64 need = a.full & ~a.vis[v];
     if (!need) continue;
@@ -1150,10 +1168,19 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
       pm &= pm - 1;
       const int vb = __shfl(b, l), ve = __shfl(e, l);
       const u64 lf = __shfl(fu, l);
-      for (int j = vb + lane(); j < ve; j += WAVE) {
-        const int v = a.ci[j];
-        const u64 m = lf & ~a.vis[v];
-        if (m) atomicOr(a.next + v, m);
+      for (int base = vb; base < ve; base += MS_HU * WAVE) {  // MS_HU rounds of 64 edges, loads in flight together
+        int v[MS_HU];
+#pragma unroll
+        for (int r = 0; r < MS_HU; ++r) {
+          const int j = base + r * WAVE + lane();
+          v[r] = j < ve ? a.ci[j] : -1;
+        }
+        u64 m[MS_HU];
+#pragma unroll
+        for (int r = 0; r < MS_HU; ++r) m[r] = v[r] >= 0 ? lf & ~a.vis[v[r]] : 0ull;
+#pragma unroll
+        for (int r = 0; r < MS_HU; ++r)
+          if (m[r]) atomicOr(a.next + v[r], m[r]);
       }
       if (lane() == l) st.c[C_SCAN] += (u32)(ve - vb);
     }
@@ -1264,7 +1291,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
   MsStats st;
   const int wv = threadIdx.x / WAVE;
   for (int q = blockIdx.x * (BLOCK / WAVE) + wv; q < a.ochunks; q += gridDim.x * (BLOCK / WAVE)) {
-    const int i = ms_heavy_of_chunk(a.opre, a.ocount, q);
+    const int i = ms_chunk_owner(a.oq, a.hqcap, a.opre, a.ocount, q);
     const int u = a.ov[i];
     if (!in_front(a.fbits, u)) continue;
     const u64 fu = a.front[u];
@@ -1409,8 +1436,9 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.bwt);
   hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev, W.bwt,
                      htot_dev + 4);
+  const int hqcap = (int)ms_hq_cap(n);
   hipLaunchKernelGGL(k_ms_heavy_write, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.hv, W.hpre,
-                     W.accb, htot_dev, (const long long *)W.bwt, W.tstart, (const int *)(htot_dev + 4));
+                     W.hq, hqcap, W.accb, htot_dev, (const long long *)W.bwt, W.tstart, (const int *)(htot_dev + 4));
   // the same over out-degrees for the top-down step (a symmetric graph passes one array twice)
   if (g->row_ptr != g->csc_ptr) {
     hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk,
@@ -1418,7 +1446,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev + 2,
                        (long long *)nullptr, (int *)nullptr);
     hipLaunchKernelGGL(k_ms_heavy_write, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk, W.ov, W.opre,
-                       (u64 *)nullptr, htot_dev + 2, (const long long *)nullptr, (int *)nullptr,
+                       W.oq, hqcap, (u64 *)nullptr, htot_dev + 2, (const long long *)nullptr, (int *)nullptr,
                        (const int *)nullptr);
   }
   BFS_HIP(hipGetLastError());
@@ -1498,6 +1526,9 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     const bool sym = g->row_ptr == g->csc_ptr;
     a.ov = sym ? W.hv : W.ov;
     a.opre = sym ? W.hpre : W.opre;
+    a.hq = W.hq;
+    a.oq = sym ? W.hq : W.oq;
+    a.hqcap = hqcap;
     a.otot = sym ? htot_dev : htot_dev + 2;
     int grid_t1 = 0, grid_t4 = 0;
     long long nf = 0, ef = 0, src_comp = 0;
