@@ -24,8 +24,12 @@ namespace bfs {
 __global__ __launch_bounds__(64) void k_select(SelDevice sd, RingSlot *ring, int k, int n, int nnz, int init,
                                                int use_net, LevelLog *log) {
   __shared__ __align__(16) char smem[SM_SELECT];
-  __shared__ int4 s_wt[SEL_W16];
-  body_select(sd, ring, k, n, nnz, init, use_net, log, smem, s_wt);
+  __shared__ SelLds s_sel;
+  if (use_net) {
+    stage_selector<64>(sd, &s_sel);
+    __syncthreads();
+  }
+  body_select(sd, ring, k, n, nnz, init, use_net, log, smem, use_net ? &s_sel : nullptr);
 }
 
 // The per-level counter reduction (body_finish) followed, in the same
@@ -37,11 +41,14 @@ __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap,
                                                        SelDevice sd, RingSlot *ring, int n, int nnz, int select,
                                                        int use_net, LevelCtr *host, u64 *host_seq, u64 seq) {
   __shared__ __align__(16) char smem[SM_FINISH + SM_SELECT];
-  __shared__ int4 s_wt[SEL_W16];
+  __shared__ SelLds s_sel;
+  const bool net = select && use_net;
+  if (net) stage_selector<NSH>(sd, &s_sel);  // its loads overlap the reduction's
   body_finish(slot, qcap, k, log, ctl, smem);
   __syncthreads();
   __threadfence_block();
-  if (select && threadIdx.x < WAVE) body_select(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH, s_wt);
+  if (select && threadIdx.x < WAVE)
+    body_select(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH, net ? &s_sel : nullptr);
   if (threadIdx.x == 0 && host) {  // lane 0 wrote the decision above
     *host = slot->tot;
     __threadfence_system();

@@ -72,6 +72,80 @@ __device__ inline float forward_row(const W &wt, const float *p, const float *x,
   return out;
 }
 
+// Selector parameters staged in LDS as fp32 for the per-level kernels: each
+// weight matrix transposed (input k of every output adjacent, at [k][out]),
+// so the forward pass's lanes read consecutive words.  Read in place, a lane's
+// own row lies 128 bytes from the next lane's and all 64 lanes hit one LDS
+// bank on every product.
+struct SelLds {
+  float w1t[NF * NH], w2t[NH * NH], w3t[NH * NC], b1[NH], b2[NH], b3[NC];
+};
+
+// Stages the parameters with the NT threads of the workgroup, every global
+// load issued before the first LDS store; a __syncthreads() must follow.
+template <int NT>
+__device__ inline void stage_selector(const SelDevice &sd, SelLds *L) {
+  static_assert(NF * NH % NT == 0 && NH * NH % NT == 0 && NH * NC % NT == 0 && NT >= NH, "whole rounds");
+  constexpr int N1 = NF * NH / NT, N2 = NH * NH / NT, N3 = NH * NC / NT;
+  const int t = threadIdx.x;
+  float v1[N1], v2[N2], v3[N3], b1 = 0.f, b2 = 0.f, b3 = 0.f;
+#pragma unroll
+  for (int j = 0; j < N1; ++j) {  // w1t[k][l] = W1[l][k]
+    const int i = t + j * NT;
+    v1[j] = bf2f(sd.w[OFF_W1 + (i % NH) * NF + i / NH]);
+  }
+#pragma unroll
+  for (int j = 0; j < N2; ++j) {
+    const int i = t + j * NT;
+    v2[j] = bf2f(sd.w[OFF_W2 + (i % NH) * NH + i / NH]);
+  }
+#pragma unroll
+  for (int j = 0; j < N3; ++j) {
+    const int i = t + j * NT;
+    v3[j] = bf2f(sd.w[OFF_W3 + (i % NC) * NH + i / NC]);
+  }
+  if (t < NH) {
+    b1 = sd.p[OFF_B1 + t];
+    b2 = sd.p[OFF_B2 + t];
+  }
+  if (t < NC) b3 = sd.p[OFF_B3 + t];
+#pragma unroll
+  for (int j = 0; j < N1; ++j) L->w1t[t + j * NT] = v1[j];
+#pragma unroll
+  for (int j = 0; j < N2; ++j) L->w2t[t + j * NT] = v2[j];
+#pragma unroll
+  for (int j = 0; j < N3; ++j) L->w3t[t + j * NT] = v3[j];
+  if (t < NH) {
+    L->b1[t] = b1;
+    L->b2[t] = b2;
+  }
+  if (t < NC) L->b3[t] = b3;
+}
+
+// forward_row from the staged parameters: the same values, the same order of
+// accumulation, so the same logits.
+__device__ inline float forward_row_lds(const SelLds &L, const float *x, float *h0, float *h1, float *h2) {
+  const int l = lane();
+  if (l < NF) h0[l] = bfr(x[l]);
+  __builtin_amdgcn_wave_barrier();
+  float acc = L.b1[l];
+  for (int k = 0; k < NF; ++k) acc = acc + h0[k] * L.w1t[k * NH + l];
+  h1[l] = bfr(fmaxf(acc, 0.f));
+  __builtin_amdgcn_wave_barrier();
+  acc = L.b2[l];
+#pragma unroll 8
+  for (int k = 0; k < NH; ++k) acc = acc + h1[k] * L.w2t[k * NH + l];
+  h2[l] = bfr(fmaxf(acc, 0.f));
+  __builtin_amdgcn_wave_barrier();
+  float out = 0.f;
+  if (l < NC) {
+    acc = L.b3[l];
+    for (int k = 0; k < NH; ++k) acc = acc + h2[k] * L.w3t[k * NC + l];
+    out = acc;
+  }
+  return out;
+}
+
 // Argmax over lanes 0..3 (ties to the lowest index) and the top softmax
 // probability, 1 / sum_j exp(l_j - l_max).
 __device__ inline void argmax_conf(float logit, int *cls, float *conf) {
@@ -90,13 +164,10 @@ __device__ inline void argmax_conf(float logit, int *cls, float *conf) {
 // Runs after the step that produced F_k: updates the running unvisited
 // totals, advances the direction rule, evaluates the network on F_k's
 // features and stores the choice in ring[k % RING].decision.
-// Run by one whole wave.  smem: SM_SELECT bytes.
-// bf16 weights staged in LDS before the forward pass (16-byte copies, all in
-// flight at once), instead of one dependent 2-byte global load per product.
-constexpr int SEL_W16 = (NPARAM * 2 + 15) / 16;  // 16-byte units; the source buffer extends past them
-
+// Run by one whole wave.  smem: SM_SELECT bytes.  lds: the parameters staged
+// by stage_selector (else read from global memory).
 __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, int init,
-                                            int use_net, LevelLog *log, char *smem, int4 *s_wt = nullptr) {
+                                            int use_net, LevelLog *log, char *smem, const SelLds *lds = nullptr) {
   float *s_x = reinterpret_cast<float *>(smem), *h0 = s_x + NF, *h1 = h0 + NH, *h2 = h1 + NH;
   int &s_hv = *reinterpret_cast<int *>(h2 + NH);
   LevelCtr *c = &ring[k % RING].tot;
@@ -152,15 +223,13 @@ __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring,
   __builtin_amdgcn_wave_barrier();
   if (lane() < NF) s_x[lane()] = xn;
   __builtin_amdgcn_wave_barrier();
-  const u16 *w = sd.w;
-  if (s_wt) {
-    const int4 *src = reinterpret_cast<const int4 *>(sd.w);
-    for (int i = lane(); i < SEL_W16; i += WAVE) s_wt[i] = src[i];
-    __builtin_amdgcn_wave_barrier();
-    w = reinterpret_cast<const u16 *>(s_wt);
+  float logit;
+  if (lds) {
+    logit = forward_row_lds(*lds, s_x, h0, h1, h2);
+  } else {
+    float z1, z2;
+    logit = forward_row(WBf16{sd.w}, sd.p, s_x, h0, h1, h2, z1, z2);
   }
-  float z1, z2;
-  float logit = forward_row(WBf16{w}, sd.p, s_x, h0, h1, h2, z1, z2);
   int cls;
   float conf;
   argmax_conf(logit, &cls, &conf);
