@@ -732,18 +732,32 @@ __device__ __forceinline__ int ms_heavy_of_chunk(const int *hpre, int hcount, in
 constexpr int MS_HU = 4;    // 64-edge rounds per heavy-pass iteration
 constexpr int MS_POST = 1;  // iterations between posts
 
+// phase 0: every chunk; 1: the first chunk of each heavy vertex; 2: the other
+// chunks.  On dense frontiers a vertex's first chunk usually finds every lane
+// it misses, so running the first chunks on their own lets the others see that
+// in accb before reading any edge (all chunks at once each read a round).
 template <bool SUM, bool PROBE = true>
-__global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a, int phase) {
   extern __shared__ u32 s_sum[];
   ms_stage_summary<SUM>(a, s_sum);
   MsStats st;
   const int wv = threadIdx.x / WAVE;
-  for (int q = blockIdx.x * (BLOCK / WAVE) + wv; q < a.hchunks; q += gridDim.x * (BLOCK / WAVE)) {
-    const int i = ms_chunk_owner(a.hq, a.hqcap, a.hpre, a.hcount, q);
+  const int items = phase == 1 ? a.hcount : a.hchunks;
+  for (int it = blockIdx.x * (BLOCK / WAVE) + wv; it < items; it += gridDim.x * (BLOCK / WAVE)) {
+    int i, q;
+    if (phase == 1) {
+      i = it;
+      q = a.hpre[i];
+    } else {
+      q = it;
+      i = ms_chunk_owner(a.hq, a.hqcap, a.hpre, a.hcount, q);
+    }
+    const int q0 = a.hpre[i];  // the vertex's first chunk
+    if (phase == 2 && q == q0) continue;
     const int v = a.hv[i];
     const u64 need = a.full & ~a.vis[v];
     if (!need) continue;
-    const int sb = a.cp[v] + (q - a.hpre[i]) * MS_HCHUNK;
+    const int sb = a.cp[v] + (q - q0) * MS_HCHUNK;
     int se = min(a.cp[v + 1], sb + MS_HCHUNK);
     if (a.split_t) {  // split level: only the in-edges from vertices below split_t (a prefix)
       se = ms_wave_lower_bound(a.cx, sb, se, a.split_t);
@@ -1662,12 +1676,17 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         const size_t lds = sum ? MS_SUM_WORDS * sizeof(u32) : 0;
         if (a.hchunks > 0 && !heavy_done) {
           const int gh = std::min(hsum ? MS_SUM_GRID : 4096, (a.hchunks + 3) / 4);
-          if (hsum)
-            hipLaunchKernelGGL(k_ms_pull_heavy<true>, dim3(gh), dim3(BLOCK), lds, s, a);
-          else if (ef * 4 > eu || split)  // dense frontier (see `rounds`) or split: gathers without the probe
-            hipLaunchKernelGGL((k_ms_pull_heavy<false, false>), dim3(gh), dim3(BLOCK), 0, s, a);
-          else
-            hipLaunchKernelGGL(k_ms_pull_heavy<false>, dim3(gh), dim3(BLOCK), 0, s, a);
+          if (hsum) {
+            hipLaunchKernelGGL(k_ms_pull_heavy<true>, dim3(gh), dim3(BLOCK), lds, s, a, 0);
+          } else if (ef * 4 > eu) {  // dense frontier (see `rounds`): first chunks first, no bitmap probe
+            const int g1 = std::min(4096, (a.hcount + 3) / 4);
+            hipLaunchKernelGGL((k_ms_pull_heavy<false, false>), dim3(g1), dim3(BLOCK), 0, s, a, 1);
+            hipLaunchKernelGGL((k_ms_pull_heavy<false, false>), dim3(gh), dim3(BLOCK), 0, s, a, 2);
+          } else if (split) {  // gathers of hub words without the probe
+            hipLaunchKernelGGL((k_ms_pull_heavy<false, false>), dim3(gh), dim3(BLOCK), 0, s, a, 0);
+          } else {
+            hipLaunchKernelGGL(k_ms_pull_heavy<false>, dim3(gh), dim3(BLOCK), 0, s, a, 0);
+          }
         }
         // one vertex per thread while many in-edges remain to be scanned (more
         // workgroups in flight); four when few do (fixed costs amortised)
