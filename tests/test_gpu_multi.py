@@ -243,3 +243,26 @@ def test_main_timing_only():
     assert np.all(st["ms_main"][:k] > 0) and np.all(st["ms"][:k] == 0)
     assert float(st["ms_main"][:k].sum()) <= st["elapsed_ms"] + 1e-3
     np.testing.assert_array_equal(lv.cpu().numpy(), oracle.multi(g.row_ptr, g.col_idx, srcs))
+
+
+@pytest.mark.parametrize("variant", MODES)
+def test_heavy_chunks_beyond_owner_table(variant):
+    """More 1024-edge chunks of heavy vertices than the chunk-to-owner table
+    holds (2n + 1024 entries): the later chunks find their vertex by search.
+    A 48-vertex directed graph with duplicate edges (about 43K in- and
+    out-edges on each of 40 vertices, about 1700 chunks per direction), and a
+    path through the other 8."""
+    rng = np.random.default_rng(21)
+    n = 48
+    m = 2_500_000
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    # vertices 40..47 only on a path 39 -> 40 -> ... -> 47, so depths grow past 2
+    keep = (src < 40) & (dst < 40)
+    src, dst = src[keep], dst[keep]
+    path = np.array([[i, i + 1] for i in range(39, 47)])
+    e = np.concatenate([np.stack([src, dst], 1), path])
+    g = gg.from_edge_list(n, e, False)
+    hchunks = int(np.sum(np.where(np.diff(g.csc_ptr) > 1024, (np.diff(g.csc_ptr) + 1023) // 1024, 0)))
+    assert hchunks > 2 * n + 1024
+    _check(g, np.array([0, 5, 39, 40, 47, 3, 3]), variant, level_stats=True)
