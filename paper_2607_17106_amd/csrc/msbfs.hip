@@ -7,16 +7,21 @@
 //   vis[v]  = vis[v] OR next[v]                                (update)
 // and depth k+1 is recorded for every lane bit newly set at v.
 //
-// Pull (bottom-up, CSC): one wave per 64 consecutive vertices; a lane ORs the
-// frontier words of its first MS_T in-neighbours, then vertices still needing
-// lanes are scanned by the whole wave, 64 in-edges per iteration with an OR
-// reduction, stopping once every lane the vertex lacks has been found.  An
-// in-neighbour's frontier word is gathered only when its bit is set in the
-// any-lane frontier bitmap (n/8 bytes, cache resident), so edges from
-// vertices outside the frontier cost a column id and one bit.
+// Pull (bottom-up, CSC): vertices with more than MS_HEAVY in-edges are split
+// into 1024-edge chunks, one wave each (k_ms_pull_heavy); the others go by
+// tiles of consecutive vertices cut to similar in-edge counts, a workgroup per
+// tile (k_ms_pull_tile): each vertex's thread reads its first MS_HEAD
+// in-edges, then the remaining lists of the vertices still missing lanes are
+// laid end to end and walked by the whole workgroup.  A vertex stops once
+// every lane it lacks is found.  On sparse frontiers an in-neighbour's word is
+// gathered only when its bit is set in the any-lane frontier bitmap (n/8
+// bytes, cache resident); on dense ones it is gathered directly.
 // Push (top-down, CSR): frontier vertices OR their frontier word, masked by
 // the target's (read-only) visited word, into the target's next word with
 // atomicOr; an owner-computes pass then applies the update.
+// Split (bottom-up at a vertex id, see MsArgs::split_t): in-edges from the
+// hubs below it are pulled, the out-edges of the frontier vertices above it
+// pushed.
 //
 // Depths are not written during the levels.  Each discovery ORs the new lane
 // bits into bit planes of the relative depth r = k + 1 - base (bit l of plane
@@ -33,7 +38,7 @@
 
 namespace bfs {
 
-constexpr int MS_T = 4;   // in-edges per lane before the wave-cooperative scan (push)
+constexpr int MS_T = 4;   // out-edges per lane before the wave-cooperative walk (push)
 constexpr int MS_HEAD = 8; // in-edges a light vertex's own thread reads before the merged walk (pull)
 static_assert(MS_HEAD % 4 == 0, "the head is read in 16-byte pieces");
 constexpr long long MS_ALPHA = 7;  // bottom-up when frontier out-edges exceed 1/7 of eu (and n/8)
