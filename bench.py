@@ -341,10 +341,10 @@ def main():
         ws = torch.empty(B.workspace_size(g.n), dtype=torch.uint8, device="cuda")
         lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
 
-        def run_single(var, srcs, flags=0):
+        def run_single(var, srcs, graph=dg, vmap=None):
             edges = 0
             for s in srcs:
-                _, st = B.bfs_levels(dg, int(s), variant=var, flags=flags, workspace=ws, levels=lv)
+                _, st = B.bfs_levels(graph, int(s), variant=var, workspace=ws, levels=lv, vertex_map=vmap)
                 edges += st["component_edges"] // 2
             return edges
 
@@ -356,14 +356,25 @@ def main():
         modes += [(B.VARIANT_NAMES[v], v, sources[: args.sweep_sources]) for v in range(B.NUM_VARIANTS)]
         for name, var, srcs in modes:
             run_single(var, srcs[:2])  # warm-up
-            # best of 3 passes over the sources: a pass is a few ms of host-driven
-            # launches, and one host stall of tens of ms would halve its rate
-            best = None
-            for _ in range(3):
-                edges, dt = timed(lambda: run_single(var, srcs))
-                best = dt if best is None else min(best, dt)
-            single[name] = round(edges / best / 1e9, 3)
+        # best of 3 passes over the sources, the modes taking turns within each
+        # pass: a pass is a few ms of host-driven launches, and one host stall
+        # of tens of ms would halve its rate
+        best, edges_of = {}, {}
+        for _ in range(3):
+            for name, var, srcs in modes:
+                edges_of[name], dt = timed(lambda: run_single(var, srcs))
+                best[name] = min(best.get(name, dt), dt)
+        for name, _, _ in modes:
+            single[name] = round(edges_of[name] / best[name] / 1e9, 3)
             log(f"[bench] single-source {name}: {single[name]} GTEPS")
+        # the direction heuristic on the degree-renumbered graph (vertex_map)
+        run_single(B.AUTO_HEURISTIC, sources[:2], rg, new_of_old)
+        ren_t = None
+        for _ in range(3):
+            ren_e, dt = timed(lambda: run_single(B.AUTO_HEURISTIC, sources, rg, new_of_old))
+            ren_t = dt if ren_t is None else min(ren_t, dt)
+        out["single_source_renumbered_heuristic_gteps"] = round(ren_e / ren_t / 1e9, 3)
+        log(f"[bench] single-source heuristic, renumbered graph: {out['single_source_renumbered_heuristic_gteps']} GTEPS")
         fixed = {k: v for k, v in single.items() if k not in ("learned", "heuristic")}
         best_fixed = max(fixed, key=fixed.get)
         out["single_source_gteps"] = single

@@ -158,9 +158,10 @@ typedef struct bfs_options {
   int64_t graph_ld, graph_ld2;   /* with BFS_F_GRAPH_SUMS: the values bfs_graph_sums returned */
   const int32_t *vertex_map;     /* device [n] or NULL.  Set: the graph is a renumbered copy
                                     (bfs_reorder_degree, bfs_reorder_rcm) and vertex_map[v] is the new id of
-                                    original vertex v (its new_of_old); sources and depths are
-                                    then in the original numbering.  bfs_multi only: the other
-                                    calls return BFS_ENOTSUP when it is set */
+                                    original vertex v (its new_of_old, a permutation of 0 .. n-1);
+                                    sources, depths and parents are then in the original
+                                    numbering.  bfs_multi, bfs_levels and bfs_parents; bfs_step_time
+                                    returns BFS_ENOTSUP when it is set */
   int32_t hub_split;             /* bfs_multi only (the other calls ignore it): the split id T of
                                     split bottom-up levels.  On such a level the in-edges from
                                     vertices < T are pulled, reading each in-edge list only up to

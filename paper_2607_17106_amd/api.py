@@ -222,8 +222,14 @@ def _options(variant, flags, schedule, workspace, max_levels, heuristic_push):
     return opt, keep
 
 
+def _check_vmap(g, vertex_map):
+    if vertex_map.dtype != torch.int32 or vertex_map.numel() != g.n or not vertex_map.is_contiguous():
+        raise ValueError("vertex_map must be a contiguous int32 tensor of n entries")
+    return vertex_map.data_ptr()
+
+
 def _run_single(fn_name, g: DeviceGraph, source, want_parents, variant, flags, schedule, level_stats,
-                workspace, levels, parents, max_levels, heuristic_push, stream, stats_capacity):
+                workspace, levels, parents, max_levels, heuristic_push, stream, stats_capacity, vertex_map=None):
     lib = L.load()
     dev = g.row_ptr.device
     if levels is None:
@@ -239,6 +245,8 @@ def _run_single(fn_name, g: DeviceGraph, source, want_parents, variant, flags, s
     if variant == L.AUTO_LEARNED or level_stats:
         opt.graph_ld, opt.graph_ld2 = g.graph_sums(stream)
         opt.flags |= L.F_GRAPH_SUMS
+    if vertex_map is not None:
+        opt.vertex_map = _check_vmap(g, vertex_map)
     if want_parents:
         rc = lib.bfs_parents(g.c, int(source), _ptr(levels), _ptr(parents), ctypes.byref(opt),
                              ctypes.byref(sb.s), _stream(stream))
@@ -253,20 +261,23 @@ def _run_single(fn_name, g: DeviceGraph, source, want_parents, variant, flags, s
 def bfs_levels(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, flags: int = 0,
                schedule: Optional[Sequence[int]] = None, level_stats: bool = False, workspace=None,
                levels=None, max_levels: int = 0, heuristic_push=None, stream=None,
-               stats_capacity: int = 1 << 16):
-    """Depths from `source`; returns (levels int32 tensor, stats dict)."""
+               stats_capacity: int = 1 << 16, vertex_map=None):
+    """Depths from `source`; returns (levels int32 tensor, stats dict).
+    vertex_map: the new_of_old of a renumbering when g is the renumbered graph
+    (source and depths then use the original ids)."""
     lv, _, st = _run_single("bfs_levels", g, source, False, variant, flags, schedule, level_stats, workspace,
-                            levels, None, max_levels, heuristic_push, stream, stats_capacity)
+                            levels, None, max_levels, heuristic_push, stream, stats_capacity, vertex_map)
     return lv, st
 
 
 def bfs_parents(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, flags: int = 0,
                 schedule: Optional[Sequence[int]] = None, level_stats: bool = False, workspace=None,
                 levels=None, parents=None, max_levels: int = 0, heuristic_push=None, stream=None,
-                stats_capacity: int = 1 << 16):
-    """Depths and a valid BFS parent per vertex; returns (levels, parents, stats)."""
+                stats_capacity: int = 1 << 16, vertex_map=None):
+    """Depths and a valid BFS parent per vertex; returns (levels, parents, stats).
+    vertex_map as for bfs_levels (parents are then original ids too)."""
     return _run_single("bfs_parents", g, source, True, variant, flags, schedule, level_stats, workspace,
-                       levels, parents, max_levels, heuristic_push, stream, stats_capacity)
+                       levels, parents, max_levels, heuristic_push, stream, stats_capacity, vertex_map)
 
 
 def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: int = 0, workspace=None,
@@ -291,9 +302,7 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
         flags |= L.F_HUB_ORDER
     opt, keep = _options(variant, flags, None, workspace, 0, None)
     if vertex_map is not None:
-        if vertex_map.dtype != torch.int32 or vertex_map.numel() != g.n or not vertex_map.is_contiguous():
-            raise ValueError("vertex_map must be a contiguous int32 tensor of n entries")
-        opt.vertex_map = vertex_map.data_ptr()
+        opt.vertex_map = _check_vmap(g, vertex_map)
     opt.hub_split = int(hub_split)
     rc = lib.bfs_multi(g.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k, _ptr(levels),
                        ctypes.byref(opt), ctypes.byref(sb.s), _stream(stream))

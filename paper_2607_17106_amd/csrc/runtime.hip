@@ -37,7 +37,7 @@ static inline int words_of(int n) { return (n + 63) / 64; }
 
 constexpr int GSUM_WORDS = 1280;  // graph sums, selector state, flag, 64 partial lines
 
-size_t workspace_bytes_single(int n) {
+static size_t single_core_bytes(int n) {
   const size_t W = (size_t)words_of(n);
   size_t b = 0;
   b += align256(W * 8);                              // vis
@@ -56,6 +56,38 @@ size_t workspace_bytes_single(int n) {
   b += align256(sizeof(int));                        // p3_level
   b += 2 * align256((size_t)tmp_entries(n) * 4);     // tmp_v, tmp_u
   return b;
+}
+
+// After the layout carve_single cuts: with options.vertex_map, the depths and
+// parents in the graph's numbering and the inverse map (n ints each).
+size_t workspace_bytes_single(int n) { return single_core_bytes(n) + 3 * align256((size_t)n * 4); }
+
+struct MapBufs {
+  int *lv, *par, *inv;
+};
+static MapBufs map_bufs(void *base, int n) {
+  char *p = static_cast<char *>(base) + single_core_bytes(n);
+  const size_t b = align256((size_t)n * 4);
+  return MapBufs{reinterpret_cast<int *>(p), reinterpret_cast<int *>(p + b), reinterpret_cast<int *>(p + 2 * b)};
+}
+
+// inv[map[v]] = v (map: a permutation of 0 .. n-1).
+__global__ __launch_bounds__(BLOCK) void k_invert_map(const int *map, int *inv, int n) {
+  for (int v = blockIdx.x * BLOCK + threadIdx.x; v < n; v += gridDim.x * BLOCK) inv[map[v]] = v;
+}
+
+// Depths (and parents) of the renumbered graph's search at the original ids:
+// lv[v] = lv_new[map[v]], par[v] = inv[par_new[map[v]]] (or -1).
+__global__ __launch_bounds__(BLOCK) void k_unmap(const int *map, const int *inv, const int *lv_new,
+                                                 const int *par_new, int *lv, int *par, int n) {
+  for (int v = blockIdx.x * BLOCK + threadIdx.x; v < n; v += gridDim.x * BLOCK) {
+    const int m = map[v];
+    lv[v] = lv_new[m];
+    if (par) {
+      const int p = par_new[m];
+      par[v] = p >= 0 ? inv[p] : -1;
+    }
+  }
 }
 
 Workspace carve_single(void *base, int n) {
@@ -267,10 +299,6 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     set_error("source %d out of range [0, %d)", src, g->n);
     return BFS_EINVAL;
   }
-  if (opt_in && opt_in->vertex_map) {
-    set_error("options.vertex_map is honoured by bfs_multi only");
-    return BFS_ENOTSUP;
-  }
   bfs_options dflt;
   memset(&dflt, 0, sizeof(dflt));
   dflt.variant = selector_loaded() ? BFS_AUTO_LEARNED : BFS_AUTO_HEURISTIC;
@@ -340,6 +368,23 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   if (opt->flags & BFS_F_VALIDATE) {
     rc = validate_graph(g, w.gsum + 8, s);
     if (rc) return rc;
+  }
+  // vertex_map (a renumbered graph): the search runs in the graph's numbering
+  // from the source's new id, into workspace buffers, and a last pass writes
+  // depths (and parents) at the original ids
+  const int *vmap = opt->vertex_map;
+  int *levels_out = levels, *parents_out = parents;
+  const MapBufs mb = map_bufs(wsp, g->n);
+  if (vmap) {
+    BFS_HIP(hipMemcpyAsync(hc.pinned_u64 + 24, vmap + src, sizeof(int), hipMemcpyDeviceToHost, s));
+    BFS_HIP(hipStreamSynchronize(s));
+    src = reinterpret_cast<const int *>(hc.pinned_u64 + 24)[0];
+    if (src < 0 || src >= g->n) {
+      set_error("vertex_map maps the source to %d, outside [0, %d)", src, g->n);
+      return BFS_EINVAL;
+    }
+    levels = mb.lv;
+    parents = parents ? mb.par : nullptr;
   }
   const long long maxlev = opt->max_levels > 0 ? opt->max_levels : (long long)g->n + 1;
   const bool want_levels =
@@ -516,6 +561,13 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
       }
     }
   }
+  if (vmap) {
+    const int grid = std::min(4096, (g->n + BLOCK - 1) / BLOCK);
+    if (parents_out) hipLaunchKernelGGL(k_invert_map, dim3(grid), dim3(BLOCK), 0, s, vmap, mb.inv, g->n);
+    hipLaunchKernelGGL(k_unmap, dim3(grid), dim3(BLOCK), 0, s, vmap, (const int *)mb.inv, (const int *)mb.lv,
+                       (const int *)(parents_out ? mb.par : nullptr), levels_out, parents_out, g->n);
+    BFS_HIP(hipGetLastError());
+  }
   BFS_HIP(hipEventRecord(hc.ev[1], s));
   BFS_HIP(hipMemcpyAsync(hc.pinned_u64, w.ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
   BFS_HIP(hipEventSynchronize(hc.ev[1]));
@@ -599,7 +651,7 @@ static int step_time(const bfs_graph *g, const int *depths, int k, int variant, 
     return BFS_EINVAL;
   }
   if (opt && opt->vertex_map) {
-    set_error("options.vertex_map is honoured by bfs_multi only");
+    set_error("options.vertex_map is not honoured by bfs_step_time");
     return BFS_ENOTSUP;
   }
   if (is_pull(variant) && !g->csc_ptr) {

@@ -99,22 +99,42 @@ def test_mapped_long_paths(variant):
         _check_mapped(g, np.array([0, n - 1, 350, 100, 0, 3]), variant)
 
 
-def test_vertex_map_rejected_elsewhere():
-    import ctypes
+@pytest.mark.parametrize("variant", [B.AUTO_HEURISTIC, B.PUSH_Q_BLOCK, B.PULL_B, B.PUSH_B_NOATOMIC])
+def test_single_source_vertex_map(variant):
+    """bfs_levels / bfs_parents on the renumbered graph with vertex_map: the
+    oracle's depths on the original graph from the original source, and
+    parents (original ids) that pass the validity checks there."""
+    from oracle import checks
+    graphs = [gg.workload("rmat14"), gg.directed_random(3000, 15000, seed=4, self_loops=True, duplicates=True),
+              gg.from_edge_list(701, [(i, i + 1) for i in range(700)], True), gg.from_edge_list(5, [(1, 2)], True)]
+    for g in graphs:
+        dg = B.DeviceGraph.from_graph(g)
+        for reorder in (B.reorder_degree, B.reorder_rcm):
+            rg, new_of_old, _ = reorder(dg)
+            for s in (0, g.n - 1, g.n // 2):
+                ref = oracle.bfs(g.row_ptr, g.col_idx, s, want_parents=False)[0]
+                lv, _ = B.bfs_levels(rg, s, variant=variant, vertex_map=new_of_old)
+                np.testing.assert_array_equal(lv.cpu().numpy(), ref, err_msg=f"{reorder.__name__} source {s}")
+                lv, par, _ = B.bfs_parents(rg, s, variant=variant, vertex_map=new_of_old)
+                np.testing.assert_array_equal(lv.cpu().numpy(), ref)
+                assert checks.check_parents(g.row_ptr, g.col_idx, s, ref, par.cpu().numpy()) is None
+
+
+def test_vertex_map_rejected_by_step_time():
     g = gg.rmat(10, seed=3)
     dg = B.DeviceGraph.from_graph(g)
     rg, new_of_old, _ = B.reorder_degree(dg)
+    depths = torch.from_numpy(oracle.bfs(rg.row_ptr.cpu().numpy(), rg.col_idx.cpu().numpy(), 0,
+                                         want_parents=False)[0]).cuda()
     lib = B.load()
     opt = B._lib.BfsOptions()
-    opt.variant = B.AUTO_HEURISTIC
-    opt.heuristic_push = opt.heuristic_pull = -1
     opt.vertex_map = new_of_old.data_ptr()
-    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    rc = lib.bfs_levels(rg.c, 0, ctypes.c_void_p(lv.data_ptr()), ctypes.byref(opt), None, stream)
-    assert rc == -7
-    rc = lib.bfs_parents(rg.c, 0, ctypes.c_void_p(lv.data_ptr()), ctypes.c_void_p(lv.data_ptr()),
-                         ctypes.byref(opt), None, stream)
+    import ctypes
+    ms = ctypes.c_float(0)
+    scratch = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    rc = lib.bfs_step_time(rg.c, ctypes.c_void_p(depths.data_ptr()), 0, B.PUSH_Q_BLOCK, 1,
+                           ctypes.c_void_p(scratch.data_ptr()), ctypes.byref(opt), ctypes.byref(ms),
+                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == -7
 
 
