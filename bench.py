@@ -45,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of k_ms_pull_tile on this workload: two rocprofv3 --pmc runs of
 # `bench.py --steps 3 --warmup 1 --no-sweep --no-batch --no-cpu --no-input-order` (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch averaged over the kernel's 16 dispatches),
+# then WRITE_SIZE, KiB per dispatch averaged over all the kernel's dispatches in the run),
 # each scaled by what the same counter reads for a plain copy of 1 GiB
 # (`bench.py --copy-calibration 1073741824`: FETCH_SIZE 524300 KiB -> x2.0,
 # WRITE_SIZE 1048576 KiB -> x1.0).  Reported only while the kernel code
