@@ -47,6 +47,7 @@ extern "C" {
 #define BFS_ENOSEL (-5)     /* learned mode with BFS_F_STRICT_SELECTOR and no weights */
 #define BFS_ELEVELCAP (-6)  /* the level loop hit options.max_levels */
 #define BFS_ENOTSUP (-7)    /* requested variant needs CSC arrays that were not given */
+#define BFS_EFILE (-8)      /* selector weights file missing, short or malformed */
 
 const char *bfs_strerror(int code);
 const char *bfs_last_error(void);
@@ -321,7 +322,7 @@ typedef struct bfs_batch_config {
   int32_t small_vertices;    /* instances with n <= this keep their visited and frontier
                                 bitmaps in LDS; larger ones in private scratch memory */
   int32_t chunk_vertices;    /* frontier vertices flattened per workgroup pass
-                                (a multiple of block_threads, <= 4 * block_threads) */
+                                (block_threads or 2 * block_threads) */
   int32_t blocks_per_cu;     /* resident workgroups per compute unit (1..4) */
 } bfs_batch_config;
 
@@ -358,6 +359,22 @@ int bfs_selector_set(const float *params_host, const float *feat_mean_host,
                      const float *feat_std_host, const float *feat_min_host,
                      const float *feat_max_host, float min_confidence,
                      const int32_t *class_variant_host /* [4] BFS_V_* */);
+/* Loads selector weights from a file (the persisted form of the trained
+ * network, so a C caller can use BFS_AUTO_LEARNED without Python).  Layout,
+ * little-endian, 21,244 bytes:
+ *   bytes 0..7     magic "BFSSEL01"
+ *   uint32 x 4     version (1), parameter count (5,252), features (12), classes (4)
+ *   float32 x 5252 parameters in the layout above
+ *   float32 x 12   feature mean      float32 x 12  feature std (> 0)
+ *   float32 x 12   training minimum  float32 x 12  training maximum
+ *   float32        min_confidence
+ *   int32 x 4      BFS_V_* variant of each class
+ * The file is read and checked in full before anything is loaded: a missing,
+ * short or long file, a wrong header, a non-finite value, a std <= 0 or a
+ * class outside the variant range returns BFS_EFILE and leaves the loaded
+ * selector (if any) unchanged.  Otherwise as bfs_selector_set (which
+ * allocates the device copy of the weights on first use per device). */
+int bfs_selector_load(const char *path);
 int bfs_selector_clear(void);
 int bfs_selector_loaded(void);
 

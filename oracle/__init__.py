@@ -20,6 +20,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -90,20 +91,42 @@ def level_profile(row_ptr, csc_ptr, csc_idx, levels):
     return {k: v[:nlev] for k, v in out.items()}
 
 
-def multi(row_ptr, col_idx, sources):
+def host_threads() -> int:
+    """Threads for the per-source loops: the host's cores, at most 16."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _map(fn, items, threads):
+    """fn over items, one oracle search per host thread (the C search runs
+    with the interpreter lock released); results in item order."""
+    items = list(items)
+    threads = host_threads() if threads is None else max(1, int(threads))
+    if threads == 1 or len(items) <= 1:
+        return [fn(x) for x in items]
+    with ThreadPoolExecutor(max_workers=min(threads, len(items))) as ex:
+        return list(ex.map(fn, items))
+
+
+def multi(row_ptr, col_idx, sources, threads=None):
     """Levels [k][n] of one oracle BFS per source (the multi-source BFS with
-    one lane per source computes exactly these)."""
+    one lane per source computes exactly these).  The searches are
+    independent; up to `threads` run at once."""
+    row_ptr = _i32(row_ptr)
+    col_idx = _i32(col_idx)
     n = len(row_ptr) - 1
     out = np.empty((len(sources), n), dtype=np.int32)
-    for i, s in enumerate(sources):
-        out[i] = bfs(row_ptr, col_idx, int(s), want_parents=False)[0]
+
+    def one(i):
+        out[i] = bfs(row_ptr, col_idx, int(sources[i]), want_parents=False)[0]
+
+    _map(one, range(len(sources)), threads)
     return out
 
 
-def batch(batch_graphs, sources):
+def batch(batch_graphs, sources, threads=None):
     """Per-instance levels (local ids), concatenated in instance order."""
-    parts = [bfs(g.row_ptr, g.col_idx, int(s), want_parents=False)[0]
-             for g, s in zip(batch_graphs, sources)]
+    pairs = list(zip(batch_graphs, sources))
+    parts = _map(lambda gs: bfs(gs[0].row_ptr, gs[0].col_idx, int(gs[1]), want_parents=False)[0], pairs, threads)
     return np.concatenate(parts) if parts else np.zeros(0, dtype=np.int32)
 
 

@@ -52,7 +52,18 @@ def check_levels(row_ptr, col_idx, source: int, levels) -> str | None:
     return None
 
 
-def check_parents(row_ptr, col_idx, source: int, levels, parents) -> str | None:
+def edge_keys(row_ptr, col_idx):
+    """Sorted keys u * n + v of every CSR edge (u, v), for check_parents on
+    many searches of one graph."""
+    n = len(row_ptr) - 1
+    s, d = _edges(row_ptr, col_idx)
+    k = s * n + d
+    k.sort()
+    return k
+
+
+def check_parents(row_ptr, col_idx, source: int, levels, parents, keys=None) -> str | None:
+    """keys: edge_keys(row_ptr, col_idx) when already at hand."""
     lv = np.asarray(levels, dtype=np.int64)
     pa = np.asarray(parents, dtype=np.int64)
     n = len(row_ptr) - 1
@@ -71,10 +82,7 @@ def check_parents(row_ptr, col_idx, source: int, levels, parents) -> str | None:
     if (lv[p] != lv[v] - 1).any():
         return "parent not one level up"
     # edge (p, v) must exist: look it up in p's CSR row (rows need not be sorted)
-    rp = np.asarray(row_ptr, dtype=np.int64)
-    col = np.asarray(col_idx, dtype=np.int64)
-    key_edges = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp)) * n + col
-    key_edges.sort()
+    key_edges = edge_keys(row_ptr, col_idx) if keys is None else keys
     key = p * n + v
     if key.size == 0:
         return None

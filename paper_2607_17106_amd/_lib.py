@@ -18,6 +18,7 @@ BFS_EHIP = -4
 BFS_ENOSEL = -5
 BFS_ELEVELCAP = -6
 BFS_ENOTSUP = -7
+BFS_EFILE = -8
 
 PUSH_Q_THREAD = 0
 PUSH_Q_BLOCK = 1
@@ -115,6 +116,7 @@ SIGNATURES = {
     "bfs_batch_autotune": (c_int32, [POINTER(BfsGraphBatch), POINTER(c_int32), c_void_p,
                                      POINTER(BfsBatchConfig), POINTER(c_float), c_void_p]),
     "bfs_selector_set": (c_int32, [POINTER(c_float)] * 5 + [c_float, POINTER(c_int32)]),
+    "bfs_selector_load": (c_int32, [ctypes.c_char_p]),
     "bfs_selector_clear": (c_int32, []),
     "bfs_selector_loaded": (c_int32, []),
     "bfs_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),

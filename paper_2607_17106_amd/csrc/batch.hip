@@ -106,7 +106,9 @@ __global__ __launch_bounds__(BT) void k_batch(BatchArgs A) {
   int *qa = reinterpret_cast<int *>(slot);
   int *qb = qa + A.max_n;
   const int max_words = (A.max_n + 63) / 64;
-  u64 *g_vis = reinterpret_cast<u64 *>(qb + A.max_n + ((A.max_n & 1) ? 1 : 0));
+  // the two queues take 8 max_n bytes, rounded up to 256 so that the bitmaps
+  // (64-bit atomics) start 256-byte aligned whatever max_n's parity
+  u64 *g_vis = reinterpret_cast<u64 *>(slot + (((size_t)A.max_n * 8 + 255) & ~(size_t)255));
   u64 *g_fr = g_vis + max_words;
   for (;;) {
     if (threadIdx.x == 0) s_inst = atomicAdd(A.ticket, 1);
@@ -338,7 +340,7 @@ static int batch_run(const bfs_graph_batch *b, const int32_t *sources, int32_t *
   const int grid = std::min(num, cfg.blocks_per_cu * cus);
   size_t ints = (size_t)(num + 1) + 2 * (size_t)num + 64;
   size_t head = ((ints * 4 + 255) & ~(size_t)255) + (((size_t)num * 16 + 255) & ~(size_t)255);
-  size_t slot = (size_t)max_n * 8 + 8 + 2 * (size_t)((max_n + 63) / 64) * 8;
+  size_t slot = (((size_t)max_n * 8 + 255) & ~(size_t)255) + 2 * (size_t)((max_n + 63) / 64) * 8;
   slot = (slot + 255) & ~(size_t)255;
   void *wsp = nullptr;
   int rc = cached_workspace(head + slot * (size_t)grid, &wsp);

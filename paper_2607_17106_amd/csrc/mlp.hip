@@ -10,7 +10,9 @@
 // values is exact in fp32, so a fused multiply-add gives the same result as a
 // separate multiply and add; the order is what makes the result reproducible.
 // Backward treats each bf16 rounding as the identity (straight-through).
+#include <stdio.h>
 #include <string.h>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -264,6 +266,54 @@ int bfs_selector_set(const float *params, const float *mean, const float *stdv, 
   for (int i = 0; i < NC; ++i) h.cls[i] = class_variant[i];
   h.loaded = true;
   return BFS_OK;
+}
+
+// Weights file (little-endian; layout in bfs_eeds.h): parsed and checked in
+// full on the host before anything reaches the device.
+int bfs_selector_load(const char *path) {
+  if (!path) {
+    set_error("bfs_selector_load: path is NULL");
+    return BFS_EINVAL;
+  }
+  FILE *f = fopen(path, "rb");
+  if (!f) {
+    set_error("bfs_selector_load: cannot open %s", path);
+    return BFS_EFILE;
+  }
+  constexpr size_t kFloats = NPARAM + 4 * NF + 1;
+  constexpr size_t kBytes = 24 + kFloats * 4 + NC * 4;
+  std::vector<unsigned char> buf(kBytes + 1);
+  const size_t got = fread(buf.data(), 1, buf.size(), f);
+  fclose(f);
+  if (got != kBytes) {
+    set_error("bfs_selector_load: %s holds %zu bytes, expected %zu", path, got, kBytes);
+    return BFS_EFILE;
+  }
+  auto rd32 = [&](size_t off) {
+    return (uint32_t)buf[off] | ((uint32_t)buf[off + 1] << 8) | ((uint32_t)buf[off + 2] << 16) |
+           ((uint32_t)buf[off + 3] << 24);
+  };
+  if (memcmp(buf.data(), "BFSSEL01", 8) != 0 || rd32(8) != 1u || rd32(12) != (uint32_t)NPARAM ||
+      rd32(16) != (uint32_t)NF || rd32(20) != (uint32_t)NC) {
+    set_error("bfs_selector_load: %s is not a version-1 selector file for a 12-64-64-4 network", path);
+    return BFS_EFILE;
+  }
+  std::vector<float> fl(kFloats);
+  for (size_t i = 0; i < kFloats; ++i) {
+    const uint32_t u = rd32(24 + 4 * i);
+    memcpy(&fl[i], &u, 4);
+  }
+  int32_t cls[NC];
+  for (int i = 0; i < NC; ++i) cls[i] = (int32_t)rd32(24 + 4 * kFloats + 4 * i);
+  for (size_t i = 0; i < kFloats; ++i)
+    if (!std::isfinite(fl[i])) {
+      set_error("bfs_selector_load: %s holds a non-finite value at float %zu", path, i);
+      return BFS_EFILE;
+    }
+  const float *p = fl.data(), *mean = p + NPARAM, *stdv = mean + NF, *fmin = stdv + NF, *fmax = fmin + NF;
+  const float min_conf = fmax[NF];
+  const int rc = bfs_selector_set(p, mean, stdv, fmin, fmax, min_conf, cls);
+  return rc == BFS_EINVAL ? BFS_EFILE : rc;
 }
 
 int bfs_selector_clear(void) {

@@ -706,6 +706,7 @@ const char *bfs_strerror(int code) {
     case BFS_ENOSEL: return "no selector weights loaded";
     case BFS_ELEVELCAP: return "level cap reached";
     case BFS_ENOTSUP: return "variant not supported for this graph";
+    case BFS_EFILE: return "selector weights file missing or malformed";
     default: return "unknown error";
   }
 }

@@ -71,3 +71,36 @@ def test_struct_layouts_match_header(cname, pyname):
     from paper_2607_17106_amd import _lib
     py = [f[0] for f in getattr(_lib, pyname)._fields_]
     assert py == _struct_fields(cname)
+
+
+def test_selector_file_checks_before_any_device_call(tmp_path):
+    """bfs_selector_load reads and checks the whole file on the host: a
+    missing, short, long or corrupted file returns BFS_EFILE (no GPU needed,
+    nothing is loaded).  The shipped .bin holds exactly the shipped .npz."""
+    import numpy as np
+    from paper_2607_17106_amd import _lib, selector
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    with np.load(selector.NPZ_PATH, allow_pickle=False) as z:
+        good = selector.to_bytes(z["params"], z["mean"], z["std"], z["fmin"], z["fmax"], float(z["min_conf"]),
+                                 z["classes"])
+    assert open(selector.DEFAULT_PATH, "rb").read() == good
+    assert len(good) == 21244
+    assert lib.bfs_selector_load(None) == _lib.BFS_EINVAL
+    assert lib.bfs_selector_load(os.fsencode(str(tmp_path / "absent.bin"))) == _lib.BFS_EFILE
+    nan = np.frombuffer(good, np.uint8).copy()
+    nan[24:28] = np.frombuffer(np.float32(np.nan).tobytes(), np.uint8)
+    bad_std = np.frombuffer(good, np.uint8).copy()
+    off = 24 + 4 * (5252 + 12)  # first feature std
+    bad_std[off:off + 4] = np.frombuffer(np.float32(0.0).tobytes(), np.uint8)
+    bad_cls = np.frombuffer(good, np.uint8).copy()
+    bad_cls[-4:] = np.frombuffer(np.int32(99).tobytes(), np.uint8)
+    cases = {"short": good[:-1], "long": good + b"\0", "magic": b"BFSSEL02" + good[8:],
+             "version": good[:8] + b"\2" + good[9:], "nan": nan.tobytes(), "std": bad_std.tobytes(),
+             "class": bad_cls.tobytes()}
+    for name, data in cases.items():
+        f = tmp_path / (name + ".bin")
+        f.write_bytes(data)
+        assert lib.bfs_selector_load(os.fsencode(str(f))) == _lib.BFS_EFILE, name
+        assert lib.bfs_selector_loaded() == 0, name

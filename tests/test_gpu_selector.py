@@ -1,5 +1,7 @@
-"""The trained selector (paper_2607_17106_amd/selector_weights.npz): levels
-stay exact under its choices, its device-side choices equal the reference's,
+"""The trained selector, loaded through the C ABI (bfs_selector_load of the
+shipped selector_weights.bin; the reference reads the same values from
+selector_weights.npz): levels stay exact under its choices, its device-side
+choices equal the reference's,
 and on freshly measured per-level step times of a held-out R-MAT graph it
 costs no more than the direction heuristic (the gain it was trained for)."""
 import os
@@ -24,8 +26,9 @@ W = selector.DEFAULT_PATH
 def weights():
     if not os.path.exists(W):
         pytest.skip("no trained selector weights committed")
-    z = np.load(W, allow_pickle=False)
+    z = np.load(selector.NPZ_PATH, allow_pickle=False)
     assert selector.load(W)
+    assert B.selector_loaded()
     yield z
     B.selector_clear()
 

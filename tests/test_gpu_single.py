@@ -70,6 +70,25 @@ def test_rmat14_every_variant(variant):
         np.testing.assert_array_equal(lv2.cpu().numpy(), lv)
 
 
+def test_rmat22_every_fixed_variant():
+    """The fixed-variant sweep's graph (R-MAT scale 22, 128M CSR entries):
+    each fixed variant (and the two automatic modes) from three of its 64
+    sources, depths equal to the oracle and parents valid -- the size where
+    hub splitting, chunked temporary lists and large offsets are exercised."""
+    g = gg.workload("rmat22")
+    nsrc, sseed = gg.WORKLOAD_SOURCES["rmat22"]
+    srcs = gg.pick_sources(g, nsrc, sseed)[[0, 31, 63]]
+    ref = oracle.multi(g.row_ptr, g.col_idx, srcs)
+    keys = checks.edge_keys(g.row_ptr, g.col_idx)
+    dg = B.DeviceGraph.from_graph(g)
+    for variant in VARIANTS + [B.AUTO_HEURISTIC, B.AUTO_LEARNED]:
+        for i, s in enumerate(srcs):
+            lv, par, _ = _run(dg, g, s, variant)
+            np.testing.assert_array_equal(lv, ref[i], err_msg=f"rmat22 s={s} v={variant}")
+            err = checks.check_parents(g.row_ptr, g.col_idx, int(s), lv, par, keys=keys)
+            assert err is None, f"rmat22 s={s} v={variant}: {err}"
+
+
 def test_level_stats_match_oracle_profile():
     g = gg.workload("rmat14").with_csc()
     dg = B.DeviceGraph.from_graph(g)

@@ -168,6 +168,23 @@ def test_profile_scan_brute_force():
         assert prof["eScan"][k] == tot
 
 
+def test_profile_hand_worked_example():
+    """Per-level counts of a 7-vertex directed graph worked out by hand
+    (tests/golden/level_profile_hand_example.json): a wrong scan convention
+    (the hit not counted, descending lists, stopping at a visited vertex),
+    out- for in-degrees in eU, or U_k taken to include F_k all fail it."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "level_profile_hand_example.json")) as f:
+        ex = json.load(f)
+    g = gg.from_edge_list(ex["n"], ex["edges"], False)
+    lv, _, nl = oracle.bfs(g.row_ptr, g.col_idx, ex["source"])
+    np.testing.assert_array_equal(lv, ex["depths"])
+    prof = oracle.level_profile(g.row_ptr, g.csc_ptr, g.csc_idx, lv)
+    for key in ("nF", "eF", "nU", "eU", "eScan"):
+        np.testing.assert_array_equal(prof[key], ex[key], err_msg=key)
+
+
 def test_directed_graph_invariants():
     g = gg.directed_random(5000, 20000, seed=3, self_loops=True, duplicates=True)
     for s in (0, 17, 4999):
