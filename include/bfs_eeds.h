@@ -300,11 +300,15 @@ int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_
  * Many independent graphs stored back to back (a disjoint union).  Instance b
  * owns global vertices [v_off[b], v_off[b+1]); row_ptr has total_n+1 GLOBAL
  * entry offsets; col_idx holds LOCAL vertex ids of the same instance.  All
- * instances are searched in one persistent launch: each workgroup takes the
- * next instance (largest first) from a queue and runs that whole search
- * itself, choosing bottom-up for a level when the in-edges it expects to read
- * (min(e_U, n_U (e_U + e_F) / e_F)) are fewer than the frontier's out-edges, so
- * no instance needs synchronisation across workgroups. */
+ * instances are searched in one persistent launch (each level is Cascade 1's
+ * step on that instance alone).  The instances are taken largest first from a
+ * queue of tasks: an instance with n <= small_vertices is one task, searched
+ * by one workgroup with its visited bitmap in LDS; a larger one is
+ * G = min(ceil(n / team_vertices), max_team) tasks (1 when team_vertices is
+ * 0), and the G workgroups that take them search it together, level by level,
+ * behind a per-instance arrive counter.  A level goes bottom-up when the
+ * in-edges it is expected to read (min(e_U, n_U (e_U + e_F) / e_F)) are fewer
+ * than the frontier's out-edges (symmetric instances only). */
 typedef struct bfs_graph_batch {
   int32_t num;               /* instances, > 0 */
   int32_t total_n;
@@ -319,22 +323,38 @@ typedef struct bfs_graph_batch {
 
 typedef struct bfs_batch_config {
   int32_t block_threads;     /* 256, 512 or 1024 threads per workgroup */
-  int32_t small_vertices;    /* instances with n <= this keep their visited and frontier
-                                bitmaps in LDS; larger ones in private scratch memory */
-  int32_t chunk_vertices;    /* frontier vertices flattened per workgroup pass
-                                (block_threads or 2 * block_threads) */
-  int32_t blocks_per_cu;     /* resident workgroups per compute unit (1..4) */
+  int32_t small_vertices;    /* instances with n <= this are searched by one workgroup with
+                                the visited bitmap in LDS (and the bottom-up frontier bitmap
+                                when both fit); at most 2^20 and what the device's LDS per
+                                workgroup holds (BFS_EINVAL otherwise) */
+  int32_t blocks_per_cu;     /* resident workgroups per compute unit (1..4; lowered to what
+                                the kernel's registers and LDS allow) */
+  int32_t team_vertices;     /* larger instances: vertices per team member (0: one member) */
+  int32_t max_team;          /* most workgroups per team (1..16) */
+  void *workspace;           /* device scratch of at least bfs_batch_workspace_size bytes,
+                                or NULL for a buffer the library allocates and keeps */
+  size_t workspace_bytes;
 } bfs_batch_config;
+
+/* Device scratch bytes bfs_batch needs for this batch and config (cfg NULL:
+ * the config bfs_batch would use).  Host-only; sources_host as for bfs_batch. */
+int bfs_batch_workspace_size(const bfs_graph_batch *b, const int32_t *sources_host,
+                             const bfs_batch_config *cfg, size_t *bytes);
 
 /* levels: device [total_n] int32, per instance in local depth terms.
  * sources_host: host [num] local ids.  cfg NULL => defaults (or the last
- * autotuned config for a batch of the same signature). */
+ * autotuned config for a batch of the same signature) with a library-kept
+ * workspace.  Returns BFS_EHIP if a team's wait for its members ran out (2 s;
+ * only when other work on the device keeps part of the grid from running). */
 int bfs_batch(const bfs_graph_batch *b, const int32_t *sources_host, int32_t *levels,
               const bfs_batch_config *cfg, bfs_stats *st, void *stream);
 
-/* Times candidate configs on this batch and returns the fastest in *best
- * (and caches it under the batch's size signature).  levels is device
- * scratch of total_n ints.  ms_best may be NULL. */
+/* Times candidate configs (threads per workgroup, small-instance threshold,
+ * team_vertices, max_team) on this batch and returns the fastest in *best
+ * (and caches it under the batch's size signature).  best->workspace /
+ * workspace_bytes, if set on entry, serve every candidate (candidates that
+ * need more are skipped).  levels is device scratch of total_n ints.
+ * ms_best may be NULL. */
 int bfs_batch_autotune(const bfs_graph_batch *b, const int32_t *sources_host, int32_t *levels,
                        bfs_batch_config *best, float *ms_best, void *stream);
 

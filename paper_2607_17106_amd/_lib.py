@@ -92,8 +92,9 @@ class BfsGraphBatch(ctypes.Structure):
 
 
 class BfsBatchConfig(ctypes.Structure):
-    _fields_ = [("block_threads", c_int32), ("small_vertices", c_int32), ("chunk_vertices", c_int32),
-                ("blocks_per_cu", c_int32)]
+    _fields_ = [("block_threads", c_int32), ("small_vertices", c_int32),
+                ("blocks_per_cu", c_int32), ("team_vertices", c_int32), ("max_team", c_int32),
+                ("workspace", c_void_p), ("workspace_bytes", c_size_t)]
 
 
 # name -> (restype, argtypes)
@@ -115,6 +116,8 @@ SIGNATURES = {
                             POINTER(BfsStats), c_void_p]),
     "bfs_batch_autotune": (c_int32, [POINTER(BfsGraphBatch), POINTER(c_int32), c_void_p,
                                      POINTER(BfsBatchConfig), POINTER(c_float), c_void_p]),
+    "bfs_batch_workspace_size": (c_int32, [POINTER(BfsGraphBatch), POINTER(c_int32), POINTER(BfsBatchConfig),
+                                           POINTER(c_size_t)]),
     "bfs_selector_set": (c_int32, [POINTER(c_float)] * 5 + [c_float, POINTER(c_int32)]),
     "bfs_selector_load": (c_int32, [ctypes.c_char_p]),
     "bfs_selector_clear": (c_int32, []),

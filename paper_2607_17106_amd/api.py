@@ -312,17 +312,23 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
 
 @dataclass
 class BatchConfig:
-    block_threads: int = 512
-    small_vertices: int = 65536
-    chunk_vertices: int = 512
+    block_threads: int = 1024
+    small_vertices: int = 1 << 20
     blocks_per_cu: int = 2
+    team_vertices: int = 131072
+    max_team: int = 8
 
-    def c(self):
-        return L.BfsBatchConfig(self.block_threads, self.small_vertices, self.chunk_vertices, self.blocks_per_cu)
+    def c(self, workspace=None):
+        c = L.BfsBatchConfig(self.block_threads, self.small_vertices, self.blocks_per_cu,
+                             self.team_vertices, self.max_team, None, 0)
+        if workspace is not None:
+            c.workspace = workspace.data_ptr()
+            c.workspace_bytes = workspace.numel() * workspace.element_size()
+        return c
 
     @classmethod
     def from_c(cls, c):
-        return cls(c.block_threads, c.small_vertices, c.chunk_vertices, c.blocks_per_cu)
+        return cls(c.block_threads, c.small_vertices, c.blocks_per_cu, c.team_vertices, c.max_team)
 
 
 class DeviceBatch:
@@ -348,25 +354,47 @@ class DeviceBatch:
         return ctypes.byref(self._c)
 
 
-def bfs_batch(b: DeviceBatch, sources=None, config: Optional[BatchConfig] = None, levels=None, stream=None):
+def batch_workspace_size(b: DeviceBatch, config: Optional[BatchConfig] = None, sources=None) -> int:
+    src = np.ascontiguousarray(b.sources if sources is None else sources, dtype=np.int32)
+    cfg = config.c() if config is not None else None
+    nb = ctypes.c_size_t(0)
+    L.check(L.load().bfs_batch_workspace_size(b.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                              ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(nb)),
+            "bfs_batch_workspace_size")
+    return int(nb.value)
+
+
+def bfs_batch(b: DeviceBatch, sources=None, config: Optional[BatchConfig] = None, levels=None, stream=None,
+              workspace=None):
+    """With a config, the scratch is a caller tensor (`workspace`, else one
+    allocated here of bfs_batch_workspace_size bytes); without one the library
+    uses the default or autotuned config and a buffer it keeps."""
     lib = L.load()
     src = np.ascontiguousarray(b.sources if sources is None else sources, dtype=np.int32)
     if levels is None:
         levels = torch.empty(b.total_n, dtype=torch.int32, device=b.row_ptr.device)
     sb = _StatsBuf.get(0)
-    cfg = config.c() if config is not None else None
+    cfg = None
+    if config is not None:
+        if workspace is None:
+            workspace = torch.empty(batch_workspace_size(b, config, src), dtype=torch.uint8,
+                                    device=b.row_ptr.device)
+        cfg = config.c(workspace)
     rc = lib.bfs_batch(b.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(levels),
                        ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(sb.s), _stream(stream))
     L.check(rc, "bfs_batch")
     return levels, sb.as_dict(False)
 
 
-def bfs_batch_autotune(b: DeviceBatch, sources=None, levels=None, stream=None):
+def bfs_batch_autotune(b: DeviceBatch, sources=None, levels=None, stream=None, workspace=None):
     lib = L.load()
     src = np.ascontiguousarray(b.sources if sources is None else sources, dtype=np.int32)
     if levels is None:
         levels = torch.empty(b.total_n, dtype=torch.int32, device=b.row_ptr.device)
     best = L.BfsBatchConfig()
+    if workspace is not None:
+        best.workspace = workspace.data_ptr()
+        best.workspace_bytes = workspace.numel() * workspace.element_size()
     ms = ctypes.c_float(0)
     rc = lib.bfs_batch_autotune(b.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(levels),
                                 ctypes.byref(best), ctypes.byref(ms), _stream(stream))

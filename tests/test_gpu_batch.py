@@ -46,12 +46,19 @@ def _check(b, lv):
     return ref
 
 
-CONFIGS = [B.api.BatchConfig(256, 0, 256, 1), B.api.BatchConfig(256, 4096, 512, 2),
-           B.api.BatchConfig(512, 65536, 512, 2), B.api.BatchConfig(1024, 131072, 2048, 1),
-           B.api.BatchConfig(1024, 0, 1024, 2)]
+# (threads, small_vertices, blocks/CU, team_vertices, max_team): single
+# workgroups with the visited bitmap in LDS, one-member teams, and teams of up
+# to 16 workgroups
+CONFIGS = [B.api.BatchConfig(256, 0, 1, 0, 1), B.api.BatchConfig(256, 4096, 2, 1024, 4),
+           B.api.BatchConfig(512, 65536, 2), B.api.BatchConfig(1024, 1 << 20, 1),
+           B.api.BatchConfig(1024, 0, 2, 512, 16), B.api.BatchConfig(512, 64, 4, 256, 8)]
 
 
-@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"t{c.block_threads}_s{c.small_vertices}_c{c.chunk_vertices}")
+def _cid(c):
+    return f"t{c.block_threads}_s{c.small_vertices}_tv{c.team_vertices}_g{c.max_team}"
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=_cid)
 def test_batch_matches_oracle(cfg):
     b = _small_batch()
     db = B.DeviceBatch(b)
@@ -70,7 +77,7 @@ def test_batch_odd_largest_instance_global_bitmaps():
     srcs = [int(gg.pick_sources(g, 1, 3)[0]) if g.n > 3 else 0 for g in graphs]
     b = gg.concat(graphs, srcs)
     assert max(g.n for g in graphs) % 2 == 1
-    for cfg in (B.api.BatchConfig(256, 0, 256, 1), B.api.BatchConfig(1024, 0, 2048, 2)):
+    for cfg in (B.api.BatchConfig(256, 0, 1, 0, 1), B.api.BatchConfig(1024, 0, 2, 0, 1), B.api.BatchConfig(1024, 8192, 2)):
         lv, _ = B.bfs_batch(B.DeviceBatch(b), config=cfg)
         _check(b, lv)
 
@@ -78,8 +85,52 @@ def test_batch_odd_largest_instance_global_bitmaps():
 def test_batch_directed_instances_push_only():
     graphs = [gg.directed_random(500 + 50 * i, 3000, seed=i, self_loops=True, duplicates=True) for i in range(8)]
     b = gg.concat(graphs, [i for i in range(8)])
-    lv, _ = B.bfs_batch(B.DeviceBatch(b))
+    db = B.DeviceBatch(b)
+    lv, _ = B.bfs_batch(db)
     _check(b, lv)
+    for cfg in (B.api.BatchConfig(256, 0, 1, 128, 6), B.api.BatchConfig(1024, 0, 2, 0, 1), B.api.BatchConfig(1024, 1 << 20, 1)):
+        lv, _ = B.bfs_batch(db, config=cfg)
+        _check(b, lv)
+
+
+@pytest.mark.parametrize("cfg", [B.api.BatchConfig(256, 0, 2, 2048, 16), B.api.BatchConfig(1024, 0, 1, 0, 1),
+                                 B.api.BatchConfig(512, 1000, 2, 4096, 3), B.api.BatchConfig(1024, 1 << 20, 2)],
+                         ids=_cid)
+def test_batch_team_giant_vertices(cfg):
+    """Vertices of out-degree above the team kernel's giant threshold (8192):
+    listed when found and expanded by every member in slices -- a hub found at
+    level 1, a hub that is the source, two hubs joined by a path, and a
+    directed hub with in-degree but no out-edges."""
+    graphs, srcs = [], []
+    graphs.append(gg.from_edge_list(20000, [(0, j) for j in range(1, 20000)] + [(7, 8)], True))
+    srcs.append(5)
+    graphs.append(gg.from_edge_list(20000, [(0, j) for j in range(1, 20000)], True))
+    srcs.append(0)
+    e = [(0, j) for j in range(1, 9500)] + [(9500, j) for j in range(9501, 19000)] + [(1, 2), (2, 9501)]
+    graphs.append(gg.from_edge_list(19100, e, True))
+    srcs.append(19000 - 1)
+    graphs.append(gg.lattice(70, seed=9))
+    srcs.append(0)
+    b = gg.concat(graphs, srcs)
+    lv, st = B.bfs_batch(B.DeviceBatch(b), config=cfg)
+    ref = _check(b, lv)
+    comp = sum(oracle.edges_in_component(g.row_ptr, ref[int(b.v_off[i]):int(b.v_off[i + 1])])
+               for i, g in enumerate(b.graphs))
+    assert st["component_edges"] == comp
+
+
+def test_batch_workspace_size_and_caller_workspace():
+    b = _small_batch(seed=8)
+    db = B.DeviceBatch(b)
+    cfg = B.api.BatchConfig(512, 1024, 2, 2048, 4)
+    need = B.api.batch_workspace_size(db, cfg)
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    lv, _ = B.bfs_batch(db, config=cfg, workspace=ws)
+    _check(b, lv)
+    with pytest.raises(B.BfsError) as e:
+        B.bfs_batch(db, config=cfg, workspace=ws[:need - 1])
+    assert e.value.code == -3
 
 
 def test_batch_autotune_then_run():
@@ -100,7 +151,7 @@ def test_batch_errors():
         B.bfs_batch(db, sources=bad)
     assert e.value.code == -1
     with pytest.raises(B.BfsError) as e:
-        B.bfs_batch(db, config=B.api.BatchConfig(300, 0, 300, 1))
+        B.bfs_batch(db, config=B.api.BatchConfig(300, 0, 1))
     assert e.value.code == -1
 
 
