@@ -268,6 +268,23 @@ def main():
         el_in = time.perf_counter() - t_in
         input_order = {"gteps": round(sum(st["component_edges"] for st in st_in) / 2 / el_in / 1e9, 3),
                        "ms_per_step": round(el_in * 1e3 / args.steps, 3)}
+        # the tile kernel's roofline on this graph, from steps run again with
+        # the main-kernel events (outside the timed loop above)
+        t_in = b_in = 0.0
+        n_in = 0
+        for st in [step(1, dg, None) for _ in range(args.steps)]:
+            tb = bytemodel.ms_tile_level_bytes(st, g.n)
+            for k in range(st["num_levels"]):
+                if tb[k] is not None:
+                    t_in += float(st["ms_main"][k])
+                    b_in += tb[k]
+                    n_in += 1
+        a_in = b_in / (t_in * 1e-3) / 1e9
+        input_order["roofline"] = {"bound": "hbm", "achieved": round(a_in, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(a_in / HBM_PEAK_GBS, 4), "traffic": None,
+                                   "kernel": "k_ms_pull_tile", "launches": n_in,
+                                   "avg_launch_us": round(t_in * 1e3 / max(n_in, 1), 2),
+                                   "bytes_per_launch": round(b_in / max(n_in, 1))}
         log(f"[bench] input order: {input_order}")
         # and on the graph renumbered by reverse Cuthill-McKee
         (cg, cmap, _), rcm_s = timed(lambda: B.reorder_rcm(dg))
@@ -417,9 +434,20 @@ def main():
             one_by_one()
             e, dt = timed(one_by_one)
             one[name] = round(e / dt / 1e9, 3)
+        # roofline of the batched kernel: its algorithmic bytes over the device
+        # time of the call (HIP events around the state-clearing and search
+        # kernels on the library's stream)
+        reached = int((lvb >= 0).sum().item())
+        bb_bytes = bytemodel.batch_bytes(bb.total_n, reached, int(stb["component_edges"]))
+        b_ach = bb_bytes / (stb["elapsed_ms"] * 1e-3) / 1e9
         out["batch512"] = {"gteps": round(batch_gteps, 3), "ms": round(dtb * 1e3, 2),
+                           "kernel_ms": round(stb["elapsed_ms"], 3),
+                           "roofline": {"bound": "hbm", "achieved": round(b_ach, 1), "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": round(b_ach / HBM_PEAK_GBS, 4), "traffic": None,
+                                        "kernel": "k_batch", "bytes_per_launch": round(bb_bytes)},
                            "config": {"block_threads": cfg.block_threads, "blocks_per_cu": cfg.blocks_per_cu,
-                                      "small_vertices": cfg.small_vertices, "chunk_vertices": cfg.chunk_vertices},
+                                      "small_vertices": cfg.small_vertices, "team_vertices": cfg.team_vertices,
+                                      "max_team": cfg.max_team},
                            "autotune_best_ms": round(tune_ms, 2),
                            "sample_64_instances": {"batched_gteps": round(sts["component_edges"] / 2 / dts / 1e9, 3),
                                                    "one_by_one_gteps": one}}
