@@ -268,6 +268,21 @@ int bfs_levels(const bfs_graph *g, int32_t source, int32_t *levels,
 int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *parents,
                 const bfs_options *opt, bfs_stats *st, void *stream);
 
+/* bfs_levels for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same search and
+ * depths, with its scratch in a 32 MiB array the library holds on each GPU
+ * for the life of the process instead of a workspace.  The call allocates no
+ * device or host memory; it reads the loop state back into host stack memory
+ * once per 16 levels.  Limits: n <= 724,928 (else BFS_EWORKSPACE);
+ * options.workspace is ignored; BFS_F_LEVEL_STATS, BFS_F_LEVEL_TIMING and
+ * BFS_F_DEVICE_LOOP return BFS_ENOTSUP (every level choice is made on the
+ * device); st receives num_levels, reached, component_edges, fell_back,
+ * host_syncs and elapsed_ms (host clock).  Every call on a GPU shares that
+ * GPU's scratch and overwrites it (each call starts by resetting what it
+ * reads): calls that overlap on one GPU, on any streams or threads, race. */
+int bfs_levels_noalloc(const bfs_graph *g, int32_t source, int32_t *levels, const bfs_options *opt,
+                       bfs_stats *st, void *stream);
+
 /* Multi-source BFS over k sources (Cascade 1 started from several source nodes: one extra
  * lane rank on F and P).  Sources are processed in groups of up to 64 lanes;
  * lane l of vertex v lives in bit l of one u64 word, so a level is

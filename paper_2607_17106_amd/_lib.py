@@ -110,6 +110,8 @@ SIGNATURES = {
                              c_void_p]),
     "bfs_parents": (c_int32, [POINTER(BfsGraph), c_int32, c_void_p, c_void_p, POINTER(BfsOptions),
                               POINTER(BfsStats), c_void_p]),
+    "bfs_levels_noalloc": (c_int32, [POINTER(BfsGraph), c_int32, c_void_p, POINTER(BfsOptions), POINTER(BfsStats),
+                                     c_void_p]),
     "bfs_multi": (c_int32, [POINTER(BfsGraph), POINTER(c_int32), c_int32, c_void_p, POINTER(BfsOptions),
                             POINTER(BfsStats), c_void_p]),
     "bfs_batch": (c_int32, [POINTER(BfsGraphBatch), POINTER(c_int32), c_void_p, POINTER(BfsBatchConfig),

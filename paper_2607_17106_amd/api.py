@@ -280,6 +280,25 @@ def bfs_parents(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, fl
                        levels, parents, max_levels, heuristic_push, stream, stats_capacity, vertex_map)
 
 
+def bfs_levels_noalloc(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURISTIC, flags: int = 0,
+                       schedule: Optional[Sequence[int]] = None, levels=None, max_levels: int = 0,
+                       heuristic_push=None, stream=None, vertex_map=None):
+    """bfs_levels_noalloc: depths from `source` with the library's static
+    scratch (no workspace, nothing allocated by the call); returns (levels,
+    stats dict without per-level arrays)."""
+    if levels is None:
+        levels = torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+    sb = _StatsBuf.get(0)
+    opt, keep = _options(variant, flags, schedule, None, max_levels, heuristic_push)
+    if vertex_map is not None:
+        opt.vertex_map = _check_vmap(g, vertex_map)
+    rc = L.load().bfs_levels_noalloc(g.c, int(source), _ptr(levels), ctypes.byref(opt), ctypes.byref(sb.s),
+                                     _stream(stream))
+    L.check(rc, "bfs_levels_noalloc")
+    del keep
+    return levels, sb.as_dict(False)
+
+
 def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: int = 0, workspace=None,
               levels=None, stream=None, level_stats: bool = False, stats_capacity: int = 1 << 14,
               vertex_map=None, hub_split: int = 0):

@@ -689,6 +689,255 @@ static int step_time(const bfs_graph *g, const int *depths, int k, int variant, 
   return BFS_OK;
 }
 
+// ------------------------------------------------- allocation-free search
+// bfs_levels_noalloc's scratch: a file-scope device array in place of a
+// workspace, for callers that cannot allocate (graph capture, serving loops).
+// Each GPU the library runs on holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, never the device memory:
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {nullptr};
+
+static int scratch_address(void **out) {
+  int dev = 0;
+  BFS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    set_error("device %d out of range", dev);
+    return BFS_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BFS_OK;
+}
+
+// Largest n whose single-source workspace fits in the scratch array.
+static int noalloc_max_n() {
+  int lo = 1, hi = 1 << 26;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    if (workspace_bytes_single(mid) <= NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Zero-fill of device words (a kernel, not a memset node, so a captured
+// stream replays it correctly).
+__global__ void k_fill0(u64 *p, int words) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+// Device-to-host copy of a few bytes into host stack memory, then a stream
+// synchronisation: no pinned staging buffer of the library's own.
+static int read_back(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  BFS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  BFS_HIP(hipStreamSynchronize(s));
+  return BFS_OK;
+}
+
+// The search of run_single on the scratch array, with every level choice
+// made on the device: the step kernels for the next levels are enqueued in
+// batches, each gated by the decision and frontier size of its level, and the
+// host reads the loop control once per batch.  Depths only; per-level
+// statistics and level timing are not offered here.
+static int run_single_noalloc(const bfs_graph *g, int src, int *levels, const bfs_options *opt_in, bfs_stats *st,
+                              hipStream_t s) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (!levels) {
+    set_error("levels is NULL");
+    return BFS_EINVAL;
+  }
+  if (src < 0 || src >= g->n) {
+    set_error("source %d out of range [0, %d)", src, g->n);
+    return BFS_EINVAL;
+  }
+  const int max_n = noalloc_max_n();
+  if (g->n > max_n) {
+    set_error("bfs_levels_noalloc: n = %d exceeds the %d vertices its %zu-byte scratch holds", g->n, max_n,
+              NOALLOC_SCRATCH_BYTES);
+    return BFS_EWORKSPACE;
+  }
+  bfs_options dflt;
+  memset(&dflt, 0, sizeof(dflt));
+  dflt.variant = selector_loaded() ? BFS_AUTO_LEARNED : BFS_AUTO_HEURISTIC;
+  dflt.heuristic_push = -1;
+  dflt.heuristic_pull = -1;
+  const bfs_options *opt = opt_in ? opt_in : &dflt;
+  if (opt->flags & (BFS_F_LEVEL_STATS | BFS_F_LEVEL_TIMING | BFS_F_DEVICE_LOOP)) {
+    set_error("bfs_levels_noalloc: per-level statistics, level timing and the persistent loop are not offered");
+    return BFS_ENOTSUP;
+  }
+  int mode = opt->variant;
+  const bool have_csc = g->csc_ptr != nullptr;
+  if (mode >= 0 && mode < BFS_NUM_VARIANTS) {
+    if (is_pull(mode) && !have_csc) {
+      set_error("pull variant needs CSC arrays");
+      return BFS_ENOTSUP;
+    }
+  } else if (mode == BFS_SCHEDULE) {
+    if (!opt->schedule_host || opt->schedule_len <= 0) {
+      set_error("BFS_SCHEDULE needs schedule_host and schedule_len > 0");
+      return BFS_EINVAL;
+    }
+    for (int i = 0; i < opt->schedule_len; ++i) {
+      const int v = opt->schedule_host[i];
+      if (v < 0 || v >= BFS_NUM_VARIANTS || (is_pull(v) && !have_csc)) {
+        set_error("schedule entry %d is not a usable variant", i);
+        return v < 0 || v >= BFS_NUM_VARIANTS ? BFS_EINVAL : BFS_ENOTSUP;
+      }
+    }
+  } else if (mode != BFS_AUTO_HEURISTIC && mode != BFS_AUTO_LEARNED) {
+    set_error("unknown variant/mode %d", mode);
+    return BFS_EINVAL;
+  }
+  bool learned = mode == BFS_AUTO_LEARNED;
+  int fell_back_all = 0;
+  if (learned && !selector_loaded()) {
+    if (opt->flags & BFS_F_STRICT_SELECTOR) {
+      set_error("learned mode requested but no selector weights are loaded");
+      return BFS_ENOSEL;
+    }
+    learned = false;
+    mode = BFS_AUTO_HEURISTIC;
+    fell_back_all = 1;
+  }
+  const bool device_decides = mode == BFS_AUTO_HEURISTIC || mode == BFS_AUTO_LEARNED;
+  const int push_v = (opt->heuristic_push >= 0 && opt->heuristic_push < BFS_NUM_VARIANTS &&
+                      !is_pull(opt->heuristic_push)) ? opt->heuristic_push : BFS_V_PUSH_Q_BLOCK;
+  const int pull_v = have_csc ? BFS_V_PULL_B : push_v;
+  void *wsp = nullptr;
+  rc = scratch_address(&wsp);
+  if (rc) return rc;
+  Workspace w = carve_single(wsp, g->n);
+  const auto t0 = std::chrono::steady_clock::now();
+  int syncs = 0;
+  if (opt->flags & BFS_F_VALIDATE) {
+    u64 *flag = w.gsum + 8;
+    hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, s, flag, 1);
+    BFS_HIP(launch_validate(g->n, g->nnz, g->row_ptr, g->col_idx, flag, s));
+    if (g->csc_ptr && g->csc_ptr != g->row_ptr) BFS_HIP(launch_validate(g->n, g->nnz, g->csc_ptr, g->csc_idx, flag, s));
+    u64 bad = 0;
+    rc = read_back(&bad, flag, 8, s);
+    if (rc) return rc;
+    ++syncs;
+    if (bad) {
+      set_error("malformed graph: %s%s", (bad & 1) ? "bad offsets " : "", (bad & 2) ? "column id out of range" : "");
+      return BFS_EGRAPH;
+    }
+  }
+  const int *vmap = opt->vertex_map;
+  int *levels_out = levels;
+  const MapBufs mb = map_bufs(wsp, g->n);
+  if (vmap) {
+    int nsrc = -1;
+    rc = read_back(&nsrc, vmap + src, sizeof(int), s);
+    if (rc) return rc;
+    ++syncs;
+    if (nsrc < 0 || nsrc >= g->n) {
+      set_error("vertex_map maps the source to %d, outside [0, %d)", nsrc, g->n);
+      return BFS_EINVAL;
+    }
+    src = nsrc;
+    levels = mb.lv;
+  }
+  const long long maxlev = opt->max_levels > 0 ? opt->max_levels : (long long)g->n + 1;
+  u64 gld = 0, gld2 = 0;
+  if (learned) {
+    if (opt->flags & BFS_F_GRAPH_SUMS) {
+      gld = (u64)opt->graph_ld;
+      gld2 = (u64)opt->graph_ld2;
+    } else {
+      BFS_HIP(launch_graph_ld(g->n, g->row_ptr, w.gsum, s));
+      u64 sums[2] = {0, 0};
+      rc = read_back(sums, w.gsum, 16, s);
+      if (rc) return rc;
+      ++syncs;
+      gld = sums[0];
+      gld2 = sums[1];
+    }
+  }
+  int cands[2 + NC];  // the variants a device-decided level may run
+  int ncand = 0;
+  if (device_decides) {
+    cands[ncand++] = push_v;
+    if (pull_v != push_v) cands[ncand++] = pull_v;
+    if (learned) {
+      SelDevice probe = selector_device(w, push_v, pull_v);
+      for (int c = 0; c < NC; ++c) {
+        const int v = probe.cls[c];
+        if (is_pull(v) && !have_csc) continue;
+        if (std::find(cands, cands + ncand, v) == cands + ncand) cands[ncand++] = v;
+      }
+    }
+  }
+  hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, s, reinterpret_cast<u64 *>(w.ctl), (int)(sizeof(LoopCtl) / 8));
+  StepArgs a = level_args(g, w, levels, nullptr, 0, DEFAULT_HUB);
+  SelDevice seldev = selector_device(w, push_v, pull_v);
+  seldev.gld = gld;
+  seldev.gld2 = gld2;
+  BFS_HIP(launch_reset(a, src, w.ring, s));
+  BFS_HIP(launch_finish_f0(w, s));
+  if (device_decides) BFS_HIP(launch_select(seldev, w.ring, 0, g->n, g->nnz, s, true, learned, w.log));
+  constexpr int BATCH = 16;
+  LoopCtl ctl;
+  memset(&ctl, 0, sizeof(ctl));
+  int k = 0;
+  for (bool done = false; !done;) {
+    for (int i = 0; i < BATCH; ++i, ++k) {
+      a = level_args(g, w, levels, nullptr, k, DEFAULT_HUB);
+      if (device_decides) {
+        for (int c = 0; c < ncand; ++c) {
+          a.gate = cands[c];
+          BFS_HIP(launch_step(cands[c], a, -1, -1, s));
+        }
+      } else {
+        a.gate = -2;
+        const int v = mode == BFS_SCHEDULE ? opt->schedule_host[std::min(k, opt->schedule_len - 1)] : mode;
+        BFS_HIP(launch_step(v, a, -1, -1, s));
+      }
+      BFS_HIP(launch_finish_select(&w.ring[(k + 1) % RING], w.qcap, k + 1, w.log, w.ctl, seldev, w.ring, g->n, g->nnz,
+                                   device_decides, learned, nullptr, nullptr, 0, s));
+    }
+    rc = read_back(&ctl, w.ctl, sizeof(LoopCtl), s);
+    if (rc) return rc;
+    ++syncs;
+    done = ctl.done != 0;
+    if (!done && k >= maxlev) {
+      set_error("level loop reached max_levels = %lld", maxlev);
+      return BFS_ELEVELCAP;
+    }
+  }
+  if ((long long)ctl.levels > maxlev) {
+    set_error("level loop reached max_levels = %lld", maxlev);
+    return BFS_ELEVELCAP;
+  }
+  if (vmap) {
+    const int grid = std::min(4096, (g->n + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_unmap, dim3(grid), dim3(BLOCK), 0, s, vmap, (const int *)nullptr, (const int *)mb.lv,
+                       (const int *)nullptr, levels_out, (int *)nullptr, g->n);
+    BFS_HIP(hipGetLastError());
+    BFS_HIP(hipStreamSynchronize(s));
+    ++syncs;
+  }
+  if (st) {
+    st->num_levels = (int)ctl.levels;
+    st->reached = (int64_t)ctl.reached;
+    st->component_edges = (int64_t)ctl.comp_edges;
+    st->elapsed_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st->host_syncs = syncs;
+    st->fell_back = fell_back_all;
+  }
+  return BFS_OK;
+}
+
 }  // namespace bfs
 
 // ------------------------------------------------------------------ C ABI
@@ -740,6 +989,11 @@ int bfs_parents(const bfs_graph *g, int32_t source, int32_t *levels, int32_t *pa
     return BFS_EINVAL;
   }
   return run_single(g, source, levels, parents, opt, st, (hipStream_t)stream);
+}
+
+int bfs_levels_noalloc(const bfs_graph *g, int32_t source, int32_t *levels, const bfs_options *opt, bfs_stats *st,
+                       void *stream) {
+  return run_single_noalloc(g, source, levels, opt, st, (hipStream_t)stream);
 }
 
 int bfs_graph_sums(const bfs_graph *g, int64_t *ld, int64_t *ld2, void *stream) {
