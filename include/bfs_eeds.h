@@ -91,6 +91,15 @@ int bfs_version(void);
  *                  to [2^16, 2^22]), larger frontiers go in chunks
  *  PUSH_B_FILTER   the same with a bitmap frontier (Table 3, variant 14): the
  *                  edge space is flattened word by word over the bitmap
+ *  PUSH_Q_DEDUP    top-down, queue, the advance keeps duplicates and removes
+ *                  them best-effort, without sorting (Table 3, variant 9): an
+ *                  atomic-free block-mapped advance writes the depth and parent
+ *                  of every target still unvisited in P_k and appends it to the
+ *                  temporary list after dropping duplicates among the wave's
+ *                  current candidates (an LDS hash of lane ids); a filter pass
+ *                  then claims each entry as the atomic push does, so the next
+ *                  frontier is exact.  Candidates beyond the list's
+ *                  tmp_entries(n) are claimed in the advance itself
  * Every step emits the next frontier both as a queue and as a bitmap, so the
  * format of the next level is a free choice.
  */
@@ -105,7 +114,8 @@ int bfs_version(void);
 #define BFS_V_PUSH_P3 8
 #define BFS_V_PUSH_Q_FILTER 9
 #define BFS_V_PUSH_B_FILTER 10
-#define BFS_NUM_VARIANTS 11
+#define BFS_V_PUSH_Q_DEDUP 11
+#define BFS_NUM_VARIANTS 12
 /* bfs_multi level_variant only: a split bottom-up level (options.hub_split). */
 #define BFS_MS_SPLIT 200
 /* Per-level choice modes. */
@@ -300,8 +310,9 @@ int bfs_levels_noalloc(const bfs_graph *g, int32_t source, int32_t *levels, cons
  * vertices missing some lane when the step started (bottom-up steps only,
  * else 0); level_unvisited_edges = in-edges of vertices missing some lane;
  * level_scanned = edges examined; level_next = (lane, vertex) pairs found;
- * level_frontier_ld = vertices with a lane found; level_frontier_ld2 = examined
- * edges whose source vertex is in the frontier (frontier words gathered);
+ * level_frontier_ld = vertices with a lane found; level_frontier_ld2 = frontier
+ * words gathered (one per examined in-edge whose source passed the frontier
+ * bitmap probe, or per examined in-edge where a step gathers without it);
  * level_ms = step time.  Depths are written to `levels` once, by an output
  * pass after each group's last level (and by a flush pass every 255 levels).
  * With options.vertex_map (a graph from bfs_reorder_degree), sources_host

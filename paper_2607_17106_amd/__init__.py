@@ -7,6 +7,7 @@ does, and fails loudly when it is not built.
 """
 from ._lib import (  # noqa: F401
     PUSH_Q_THREAD, PUSH_Q_BLOCK, PUSH_Q_MERGE, PUSH_B_ATOMIC, PUSH_B_NOATOMIC, PUSH_Q_NOATOMIC, PULL_B, PULL_VIS, PUSH_P3, PUSH_Q_FILTER, PUSH_B_FILTER,
+    PUSH_Q_DEDUP,
     NUM_VARIANTS, MS_SPLIT, AUTO_HEURISTIC, AUTO_LEARNED, SCHEDULE, VARIANT_NAMES, F_VALIDATE, F_STRICT_SELECTOR,
     F_LEVEL_STATS, F_DEVICE_LOOP, F_LEVEL_TIMING, F_GRAPH_SUMS, F_HUB_ORDER, F_MAIN_TIMING, BfsError, load,
 )

@@ -31,7 +31,8 @@ PULL_VIS = 7
 PUSH_P3 = 8
 PUSH_Q_FILTER = 9
 PUSH_B_FILTER = 10
-NUM_VARIANTS = 11
+PUSH_Q_DEDUP = 11
+NUM_VARIANTS = 12
 MS_SPLIT = 200  # bfs_multi level_variant: a split bottom-up level
 AUTO_HEURISTIC = 100
 AUTO_LEARNED = 101
@@ -42,6 +43,7 @@ VARIANT_NAMES = {
     PUSH_B_ATOMIC: "push_b_atomic", PUSH_B_NOATOMIC: "push_b_noatomic",
     PUSH_Q_NOATOMIC: "push_q_noatomic", PULL_B: "pull_b", PULL_VIS: "pull_vis",
     PUSH_P3: "push_p3", PUSH_Q_FILTER: "push_q_filter", PUSH_B_FILTER: "push_b_filter",
+    PUSH_Q_DEDUP: "push_q_dedup",
     AUTO_HEURISTIC: "heuristic", AUTO_LEARNED: "learned", SCHEDULE: "schedule",
 }
 

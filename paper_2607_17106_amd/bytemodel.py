@@ -24,6 +24,9 @@ Per variant (p = 4 when parents are written, else 0):
   push, advance then filter       20nF (queue, offsets, degree scan) + 4eF + 8eF (list
                                   written) + 8eF (read back) + eF/8 + (8+p)nN + nN/8
   (bitmap frontier)               2n/8 + 16nF + 4W (word scan) + the same per edge and nN
+  push, best-effort dedup         12nF + 4eF + eF/8 + (4+p)nN (depth, parent of each candidate;
+                                  about nN of them) + 16nN (list written, read back) + nN/8
+                                  (filter's visited test) + 4nN + nN/8 (queue, next bitmap)
 """
 from __future__ import annotations
 
@@ -51,6 +54,8 @@ def step_bytes(variant: int, n: int, nF: int, eF: int, nU: int, nN: int, scan: i
         return 20.0 * nF + 4.0 * eF + 16.0 * eF + eF / 8.0 + (8 + p) * nN + nN / 8.0
     if variant == L.PUSH_B_FILTER:  # word weights scanned, then the same list
         return 2 * bm + 16.0 * nF + 4.0 * (n / 64.0) + 4.0 * eF + 16.0 * eF + eF / 8.0 + (8 + p) * nN + nN / 8.0
+    if variant == L.PUSH_Q_DEDUP:  # atomic-free advance: nN candidates (depth, parent, list entry), then the filter
+        return 12.0 * nF + 4.0 * eF + eF / 8.0 + (4 + p) * nN + 8.0 * nN + 8.0 * nN + nN / 8.0 + 4.0 * nN + nN / 8.0
     if variant == L.PUSH_P3:  # frontier from two visited arrays; update also writes P_{k-1}
         return 2 * bm + 8.0 * nF + 4.0 * eF + eF / 8.0 + (4 + p) * nN + bm + 4.0 * nU + 3 * bm + 4.0 * nN
     raise ValueError(variant)

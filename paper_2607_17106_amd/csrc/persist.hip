@@ -94,6 +94,7 @@ __device__ __forceinline__ void set_level(StepArgs &a, const PersistArgs &P, int
 
 __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs P) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ int s_dedup[SM_DEDUP / 4];
   u32 epoch = 0;
   StepArgs a = P.base;
   a.gate = -1;
@@ -192,6 +193,13 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs P) {
         }
         break;
       }
+      case BFS_V_PUSH_Q_DEDUP:
+        body_push_q_block<false, true>(a, smem, s_dedup);
+        ok = grid_sync(P.bar, epoch);
+        if (ok) body_push_hubs<false, true>(a, smem, s_dedup);
+        ok = ok && grid_sync(P.bar, epoch);
+        if (ok) body_filter_tmp(a, 0);
+        break;
       case BFS_V_PUSH_P3:
         body_push_p3(a, smem);
         ok = grid_sync(P.bar, epoch);

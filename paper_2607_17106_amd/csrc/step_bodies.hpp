@@ -191,6 +191,57 @@ __device__ __forceinline__ void visit_edge(const StepArgs &a, int u, int v, NewS
   }
 }
 
+// ------------------------------------- best-effort deduplication (variant 9)
+// Per-wave LDS scratch of the advance that keeps duplicates (Table 3, variant
+// 9): a 128-slot table of lane ids and the lanes' candidate vertices.
+constexpr int DEDUP_SLOTS = 128;
+constexpr int SM_DEDUP = (BLOCK / WAVE) * (DEDUP_SLOTS + WAVE) * 4;
+
+// Edge (u -> v) in the atomic-free advance of variant 9.  A target still
+// unvisited in P_k (which no lane changes during the advance) is a candidate:
+// its depth and parent are written without atomics (every candidate writer
+// stores depth k+1 and a valid parent), and it is appended to the temporary
+// list with its source -- after a best-effort removal of duplicates among the
+// wave's current candidates, without sorting: each candidate lane writes its
+// id into the slot of its vertex's hash, and a lane whose slot names another
+// lane holding the same vertex drops out.  Duplicates that survive (two
+// waves, a hash collision) are removed by the filter, whose claims are exact.
+// A candidate that finds the list full is claimed here as the atomic push
+// claims it.  Called by the active lanes of a wave together.
+__device__ __forceinline__ void visit_edge_dedup(const StepArgs &a, int u, int v, NewStats &st, int *tab, int *vals) {
+  const u64 bit = 1ull << (v & 63);
+  const bool cand = !(a.vis[v >> 6] & bit);
+  if (cand) {
+    a.levels[v] = a.k + 1;
+    if (a.parents) a.parents[v] = u;
+  }
+  const int l = lane();
+  const int h = (int)(((u32)v * 2654435761u) >> 25);  // 0 .. DEDUP_SLOTS-1
+  vals[l] = v;
+  if (cand) tab[h] = l;
+  __builtin_amdgcn_wave_barrier();
+  bool keep = cand;
+  if (cand) {
+    const int o = tab[h];
+    if (o != l && vals[o] == v) keep = false;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int pos = wave_append(keep, &a.c_cur->total_e);
+  const bool fits = keep && pos < a.tmpcap;
+  if (fits) {
+    a.tmp_v[pos] = v;
+    a.tmp_u[pos] = u;
+  }
+  if (keep && !fits) {  // the list is full: claim now
+    const bool win = !(atomicOr(a.vis + (v >> 6), bit) & bit);
+    if (win) {
+      atomicOr(a.fb_next + (v >> 6), bit);
+      st.add_vertex(a, v);
+    }
+    queue_push(win, v, a);
+  }
+}
+
 // ------------------------------------------------ push, thread-mapped (V2)
 template <bool ATOM>
 __device__ __forceinline__ void body_push_q_thread(const StepArgs &a, char *smem) {
@@ -220,8 +271,8 @@ __device__ __forceinline__ int find_owner(const int *incl, int m, int e) {
 }
 
 // ------------------------------------------- push, block-mapped (V1) + hubs
-template <bool ATOM>
-__device__ __forceinline__ void body_push_q_block(const StepArgs &a, char *smem) {
+template <bool ATOM, bool DEDUP = false>
+__device__ __forceinline__ void body_push_q_block(const StepArgs &a, char *smem, int *dedup = nullptr) {
   int *s_incl = reinterpret_cast<int *>(smem), *s_u = s_incl + BLOCK, *s_off = s_u + BLOCK;
   int *s_w = s_off + BLOCK, *s_seg = s_w + BLOCK / WAVE;
   stage_seg(s_seg, a.seg_cur);
@@ -249,7 +300,11 @@ __device__ __forceinline__ void body_push_q_block(const StepArgs &a, char *smem)
     __syncthreads();
     for (int e = threadIdx.x; e < total; e += BLOCK) {
       int j = find_owner(s_incl, BLOCK, e);
-      visit_edge<ATOM>(a, s_u[j], a.ci[s_off[j] + e], st);
+      if (DEDUP)
+        visit_edge_dedup(a, s_u[j], a.ci[s_off[j] + e], st, dedup + (threadIdx.x / WAVE) * (DEDUP_SLOTS + WAVE),
+                         dedup + (threadIdx.x / WAVE) * (DEDUP_SLOTS + WAVE) + DEDUP_SLOTS);
+      else
+        visit_edge<ATOM>(a, s_u[j], a.ci[s_off[j] + e], st);
       st.scanned++;
     }
     __syncthreads();
@@ -260,8 +315,8 @@ __device__ __forceinline__ void body_push_q_block(const StepArgs &a, char *smem)
 // Hub list of the current level, split across the whole grid: groups of 256
 // hubs are flattened in LDS by every block, and block b takes edges
 // b*256 + tid, stepping by the grid size.
-template <bool ATOM>
-__device__ __forceinline__ void body_push_hubs(const StepArgs &a, char *smem) {
+template <bool ATOM, bool DEDUP = false>
+__device__ __forceinline__ void body_push_hubs(const StepArgs &a, char *smem, int *dedup = nullptr) {
   int *s_incl = reinterpret_cast<int *>(smem), *s_u = s_incl + BLOCK, *s_off = s_u + BLOCK;
   int *s_w = s_off + BLOCK;
   NewStats st;
@@ -282,7 +337,11 @@ __device__ __forceinline__ void body_push_hubs(const StepArgs &a, char *smem) {
     __syncthreads();
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < total; e += gridDim.x * BLOCK) {
       int j = find_owner(s_incl, BLOCK, e);
-      visit_edge<ATOM>(a, s_u[j], a.ci[s_off[j] + e], st);
+      if (DEDUP)
+        visit_edge_dedup(a, s_u[j], a.ci[s_off[j] + e], st, dedup + (threadIdx.x / WAVE) * (DEDUP_SLOTS + WAVE),
+                         dedup + (threadIdx.x / WAVE) * (DEDUP_SLOTS + WAVE) + DEDUP_SLOTS);
+      else
+        visit_edge<ATOM>(a, s_u[j], a.ci[s_off[j] + e], st);
       st.scanned++;
     }
     __syncthreads();

@@ -81,6 +81,23 @@ __global__ __launch_bounds__(BLOCK) void k_push_hubs(StepArgs a) {
   body_push_hubs<ATOM>(a, smem);
 }
 
+// advance of variant 9 (best-effort deduplication), block-mapped with hubs
+// deferred, then the hubs grid-wide; the filter (k_filter_tmp) claims
+__global__ __launch_bounds__(BLOCK) void k_push_q_dedup(StepArgs a) {
+  __shared__ __align__(16) char smem[SM_BLOCK];
+  __shared__ int s_dedup[SM_DEDUP / 4];
+  clear_dead(a);
+  if (gated_off(a)) return;
+  body_push_q_block<false, true>(a, smem, s_dedup);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_push_hubs_dedup(StepArgs a) {
+  __shared__ __align__(16) char smem[SM_HUBS];
+  __shared__ int s_dedup[SM_DEDUP / 4];
+  if (gated_off(a)) return;
+  body_push_hubs<false, true>(a, smem, s_dedup);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_merge_scan_local(StepArgs a) {
   __shared__ __align__(16) char smem[SM_SCAN_LOCAL];
   clear_dead(a);
@@ -354,6 +371,14 @@ hipError_t launch_step(int variant, const StepArgs &a, int count, long long edge
       hipLaunchKernelGGL(k_push_hubs<false>, dim3(ghub), dim3(BLOCK), 0, s, a);
       hipLaunchKernelGGL(k_noatom_update, dim3(gw), dim3(BLOCK), 0, s, a);
       break;
+    case BFS_V_PUSH_Q_DEDUP: {
+      // candidates (at most the frontier's out-edges, and the list's size)
+      const long long span = std::min(dev ? (long long)a.nnz : edges, (long long)a.tmpcap);
+      hipLaunchKernelGGL(k_push_q_dedup, dim3(gq), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL(k_push_hubs_dedup, dim3(ghub), dim3(BLOCK), 0, s, a);
+      hipLaunchKernelGGL(k_filter_tmp, dim3(clampi(cdiv(std::max(span, 1ll), BLOCK), 1, GMAX)), dim3(BLOCK), 0, s, a, 0);
+      break;
+    }
     case BFS_V_PUSH_Q_NOATOMIC:
       hipLaunchKernelGGL(k_push_q_block<false>, dim3(gq), dim3(BLOCK), 0, s, a);
       hipLaunchKernelGGL(k_push_hubs<false>, dim3(ghub), dim3(BLOCK), 0, s, a);

@@ -238,7 +238,7 @@ def test_push_scanned_equals_frontier_edges():
     dg = B.DeviceGraph.from_graph(g)
     (s,) = gg.pick_sources(g, 1, 1402)
     for v in (B.PUSH_Q_THREAD, B.PUSH_Q_BLOCK, B.PUSH_Q_MERGE, B.PUSH_B_ATOMIC, B.PUSH_B_NOATOMIC, B.PUSH_P3,
-              B.PUSH_Q_FILTER, B.PUSH_B_FILTER):
+              B.PUSH_Q_FILTER, B.PUSH_B_FILTER, B.PUSH_Q_DEDUP):
         _, _, st = _run(dg, g, s, v, level_stats=True)
         np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
         np.testing.assert_array_equal(st["next"][:-1], st["frontier"][1:])
@@ -307,3 +307,30 @@ def test_filter_variant_many_chunks(variant):
         _check(g, s, lv, par, f"flags {flags}")
         assert int(st["frontier_edges"].max()) > 8 * 65536
         np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
+
+
+def test_dedup_variant_list_overflow():
+    """Best-effort deduplication (Table 3, variant 9).  A complete bipartite
+    level (source -> 300 vertices -> the same 300 others) makes 90,000
+    candidates, duplicates across waves, against a temporary list of 65,536
+    entries, so the candidates past the list are claimed in the advance;
+    R-MAT 16 is the ordinary case.  Host loop and device loop, and mixed into
+    random schedules with bitmap consumers (pull, bitmap push)."""
+    a_side = list(range(1, 301))
+    b_side = list(range(301, 601))
+    e = [(0, x) for x in a_side] + [(x, y) for x in a_side for y in b_side] + [(600, 601), (601, 602)]
+    bip = gg.from_edge_list(603, e, True)
+    r16 = gg.rmat(16, seed=1616)
+    for g, (s,) in ((bip, (0,)), (r16, gg.pick_sources(r16, 1, 17))):
+        dg = B.DeviceGraph.from_graph(g)
+        for flags in (0, B.F_DEVICE_LOOP):
+            lv, par, st = _run(dg, g, s, B.PUSH_Q_DEDUP, flags=flags, level_stats=True)
+            _check(g, s, lv, par, f"{g.name} flags {flags}")
+            np.testing.assert_array_equal(st["scanned"], st["frontier_edges"])
+            np.testing.assert_array_equal(st["next"][:-1], st["frontier"][1:])
+        rng = np.random.default_rng(9)
+        for _ in range(4):
+            sched = rng.choice([B.PUSH_Q_DEDUP, B.PULL_B, B.PUSH_B_ATOMIC, B.PUSH_Q_DEDUP, B.PUSH_P3], 12).tolist()
+            lv, par, _ = _run(dg, g, s, B.SCHEDULE, schedule=sched)
+            _check(g, s, lv, par, f"{g.name} schedule {sched}")
+    assert int(np.diff(bip.row_ptr)[1:301].sum()) - 300 > 65536  # the bipartite level overflows the list
