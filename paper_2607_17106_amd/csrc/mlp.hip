@@ -26,12 +26,13 @@ namespace bfs {
 __global__ __launch_bounds__(64) void k_select(SelDevice sd, RingSlot *ring, int k, int n, int nnz, int init,
                                                int use_net, LevelLog *log) {
   __shared__ __align__(16) char smem[SM_SELECT];
-  __shared__ SelLds s_sel;
   if (use_net) {
-    stage_selector<64>(sd, &s_sel);
-    __syncthreads();
+    NetRegs nr;
+    load_net(sd, nr);
+    body_select<true>(sd, ring, k, n, nnz, init, use_net, log, smem, nr);
+  } else {
+    body_select(sd, ring, k, n, nnz, init, use_net, log, smem);
   }
-  body_select(sd, ring, k, n, nnz, init, use_net, log, smem, use_net ? &s_sel : nullptr);
 }
 
 // The per-level counter reduction (body_finish) followed, in the same
@@ -43,14 +44,18 @@ __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap,
                                                        SelDevice sd, RingSlot *ring, int n, int nnz, int select,
                                                        int use_net, LevelCtr *host, u64 *host_seq, u64 seq) {
   __shared__ __align__(16) char smem[SM_FINISH + SM_SELECT];
-  __shared__ SelLds s_sel;
   const bool net = select && use_net;
-  if (net) stage_selector<NSH>(sd, &s_sel);  // its loads overlap the reduction's
+  NetRegs nr;
+  if (net && threadIdx.x < WAVE) load_net(sd, nr);  // its loads overlap the reduction's
   body_finish(slot, qcap, k, log, ctl, smem);
   __syncthreads();
   __threadfence_block();
-  if (select && threadIdx.x < WAVE)
-    body_select(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH, net ? &s_sel : nullptr);
+  if (select && threadIdx.x < WAVE) {
+    if (net)
+      body_select<true>(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH, nr);
+    else
+      body_select(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH);
+  }
   if (threadIdx.x == 0 && host) {  // lane 0 wrote the decision above
     *host = slot->tot;
     __threadfence_system();

@@ -20,25 +20,38 @@ constexpr int NF = BFS_MLP_NFEAT, NH = 64, NC = BFS_MLP_NCLASS;
 constexpr int OFF_W1 = 0, OFF_B1 = 768, OFF_W2 = 832, OFF_B2 = 4928, OFF_W3 = 4992, OFF_B3 = 5248;
 constexpr int NPARAM = BFS_MLP_NPARAM;
 
-// Raw features of one level (see bfs_eeds.h).  Evaluated in fp64 and rounded
-// to fp32, on the host (trainer) and on the device (selector) alike.
+// Raw feature i of one level (see bfs_eeds.h).  Evaluated in fp64 and
+// rounded to fp32, on the host (trainer) and on the device (selector) alike;
+// the device computes the 12 on 12 lanes at once.
+__host__ __device__ inline float level_feature(int i, double n, double nnz, double k, double nF, double eF, double nU,
+                                               double eU, double fld, double fld2, double gld, double gld2) {
+  switch (i) {
+    case 0: return (float)log2(1.0 + nF);
+    case 1: return (float)log2(1.0 + eF);
+    case 2: return (float)log2(1.0 + nU);
+    case 3: return (float)log2(1.0 + eU);
+    case 4: return (float)(nF / n);
+    case 5: return (float)(nnz > 0 ? eF / nnz : 0.0);
+    case 6: return (float)(nU / n);
+    case 7: return (float)(nF > 0 ? fld / nF : 0.0);
+    case 8: {
+      const double fm = nF > 0 ? fld / nF : 0.0;
+      return (float)(nF > 0 ? fld2 / nF - fm * fm : 0.0);
+    }
+    case 9: return (float)(gld / n);
+    case 10: {
+      const double gm = gld / n;
+      return (float)(gld2 / n - gm * gm);
+    }
+    default: return (float)log2(1.0 + k);
+  }
+}
+
+// All 12 raw features of one level.
 __host__ __device__ inline void level_features(double n, double nnz, double k, double nF, double eF, double nU,
                                                double eU, double fld, double fld2, double gld, double gld2,
                                                float *out) {
-  out[0] = (float)log2(1.0 + nF);
-  out[1] = (float)log2(1.0 + eF);
-  out[2] = (float)log2(1.0 + nU);
-  out[3] = (float)log2(1.0 + eU);
-  out[4] = (float)(nF / n);
-  out[5] = (float)(nnz > 0 ? eF / nnz : 0.0);
-  out[6] = (float)(nU / n);
-  double fm = nF > 0 ? fld / nF : 0.0;
-  out[7] = (float)fm;
-  out[8] = (float)(nF > 0 ? fld2 / nF - fm * fm : 0.0);
-  double gm = gld / n;
-  out[9] = (float)gm;
-  out[10] = (float)(gld2 / n - gm * gm);
-  out[11] = (float)log2(1.0 + k);
+  for (int i = 0; i < NF; ++i) out[i] = level_feature(i, n, nnz, k, nF, eF, nU, eU, fld, fld2, gld, gld2);
 }
 
 // Device-resident selector parameters (set by bfs_selector_set).

@@ -72,90 +72,103 @@ __device__ inline float forward_row(const W &wt, const float *p, const float *x,
   return out;
 }
 
-// Selector parameters staged in LDS as fp32 for the per-level kernels: each
-// weight matrix transposed (input k of every output adjacent, at [k][out]),
-// so the forward pass's lanes read consecutive words.  Read in place, a lane's
-// own row lies 128 bytes from the next lane's and all 64 lanes hit one LDS
-// bank on every product.
-struct SelLds {
-  float w1t[NF * NH], w2t[NH * NH], w3t[NH * NC], b1[NH], b2[NH], b3[NC];
+// One lane's rows of the network, kept in registers by the wave that
+// evaluates it: lane l holds W1[l][*] and W2[l][*] (bf16 pairs as stored) and
+// its two biases; lanes 0..3 also W3[l][*] and b3[l].  The per-level kernel
+// loads them at its start, so the loads overlap its counter reduction, and
+// the forward pass then reads only the layer inputs (LDS broadcasts) -- not
+// two LDS words per product as a staged copy of the matrices would.
+struct NetRegs {
+  u32 w1[NF / 2], w2[NH / 2], w3[NH / 2];
+  float b1, b2, b3;
 };
 
-// Stages the parameters with the NT threads of the workgroup, every global
-// load issued before the first LDS store; a __syncthreads() must follow.
-template <int NT>
-__device__ inline void stage_selector(const SelDevice &sd, SelLds *L) {
-  static_assert(NF * NH % NT == 0 && NH * NH % NT == 0 && NH * NC % NT == 0 && NT >= NH, "whole rounds");
-  constexpr int N1 = NF * NH / NT, N2 = NH * NH / NT, N3 = NH * NC / NT;
-  const int t = threadIdx.x;
-  float v1[N1], v2[N2], v3[N3], b1 = 0.f, b2 = 0.f, b3 = 0.f;
+// Loads lane l's rows (one wave).  Byte offsets of the rows: W1 24 l,
+// W2 1664 + 128 l, W3 9984 + 128 l in a 256-byte aligned buffer, so the
+// 8- and 16-byte loads are aligned.
+__device__ __forceinline__ void load_net(const SelDevice &sd, NetRegs &r) {
+  const int l = lane();
+  const uint2 *p1 = reinterpret_cast<const uint2 *>(sd.w + OFF_W1 + l * NF);
 #pragma unroll
-  for (int j = 0; j < N1; ++j) {  // w1t[k][l] = W1[l][k]
-    const int i = t + j * NT;
-    v1[j] = bf2f(sd.w[OFF_W1 + (i % NH) * NF + i / NH]);
+  for (int i = 0; i < NF / 4; ++i) {
+    const uint2 x = p1[i];
+    r.w1[2 * i] = x.x;
+    r.w1[2 * i + 1] = x.y;
   }
+  const uint4 *p2 = reinterpret_cast<const uint4 *>(sd.w + OFF_W2 + l * NH);
 #pragma unroll
-  for (int j = 0; j < N2; ++j) {
-    const int i = t + j * NT;
-    v2[j] = bf2f(sd.w[OFF_W2 + (i % NH) * NH + i / NH]);
+  for (int i = 0; i < NH / 8; ++i) {
+    const uint4 x = p2[i];
+    r.w2[4 * i] = x.x;
+    r.w2[4 * i + 1] = x.y;
+    r.w2[4 * i + 2] = x.z;
+    r.w2[4 * i + 3] = x.w;
   }
+  r.b1 = sd.p[OFF_B1 + l];
+  r.b2 = sd.p[OFF_B2 + l];
+  r.b3 = 0.f;
 #pragma unroll
-  for (int j = 0; j < N3; ++j) {
-    const int i = t + j * NT;
-    v3[j] = bf2f(sd.w[OFF_W3 + (i % NC) * NH + i / NC]);
+  for (int i = 0; i < NH / 2; ++i) r.w3[i] = 0u;
+  if (l < NC) {
+    const uint4 *p3 = reinterpret_cast<const uint4 *>(sd.w + OFF_W3 + l * NH);
+#pragma unroll
+    for (int i = 0; i < NH / 8; ++i) {
+      const uint4 x = p3[i];
+      r.w3[4 * i] = x.x;
+      r.w3[4 * i + 1] = x.y;
+      r.w3[4 * i + 2] = x.z;
+      r.w3[4 * i + 3] = x.w;
+    }
+    r.b3 = sd.p[OFF_B3 + l];
   }
-  if (t < NH) {
-    b1 = sd.p[OFF_B1 + t];
-    b2 = sd.p[OFF_B2 + t];
-  }
-  if (t < NC) b3 = sd.p[OFF_B3 + t];
-#pragma unroll
-  for (int j = 0; j < N1; ++j) L->w1t[t + j * NT] = v1[j];
-#pragma unroll
-  for (int j = 0; j < N2; ++j) L->w2t[t + j * NT] = v2[j];
-#pragma unroll
-  for (int j = 0; j < N3; ++j) L->w3t[t + j * NT] = v3[j];
-  if (t < NH) {
-    L->b1[t] = b1;
-    L->b2[t] = b2;
-  }
-  if (t < NC) L->b3[t] = b3;
 }
 
-// forward_row from the staged parameters: the same values, the same order of
-// accumulation, so the same logits.
-__device__ inline float forward_row_lds(const SelLds &L, const float *x, float *h0, float *h1, float *h2) {
+// Element k of a row of bf16 pairs (little-endian: the even element is the
+// low half).
+__device__ __forceinline__ float bf_at(const u32 *row, int k) {
+  const u32 u = row[k >> 1];
+  union { u32 u; float f; } x;
+  x.u = (k & 1) ? (u & 0xffff0000u) : (u << 16);
+  return x.f;
+}
+
+// forward_row from register rows: the same values, the same order of
+// accumulation (from the bias, ascending input), so the same logits.
+__device__ __forceinline__ float forward_row_regs(const NetRegs &r, const float *x, float *h0, float *h1, float *h2) {
   const int l = lane();
   if (l < NF) h0[l] = bfr(x[l]);
   __builtin_amdgcn_wave_barrier();
-  float acc = L.b1[l];
-  for (int k = 0; k < NF; ++k) acc = acc + h0[k] * L.w1t[k * NH + l];
+  float acc = r.b1;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) acc = acc + h0[k] * bf_at(r.w1, k);
   h1[l] = bfr(fmaxf(acc, 0.f));
   __builtin_amdgcn_wave_barrier();
-  acc = L.b2[l];
-#pragma unroll 8
-  for (int k = 0; k < NH; ++k) acc = acc + h1[k] * L.w2t[k * NH + l];
+  acc = r.b2;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) acc = acc + h1[k] * bf_at(r.w2, k);
   h2[l] = bfr(fmaxf(acc, 0.f));
   __builtin_amdgcn_wave_barrier();
-  float out = 0.f;
-  if (l < NC) {
-    acc = L.b3[l];
-    for (int k = 0; k < NH; ++k) acc = acc + h2[k] * L.w3t[k * NC + l];
-    out = acc;
-  }
-  return out;
+  acc = r.b3;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) acc = acc + h2[k] * bf_at(r.w3, k);
+  return l < NC ? acc : 0.f;
 }
 
 // Argmax over lanes 0..3 (ties to the lowest index) and the top softmax
 // probability, 1 / sum_j exp(l_j - l_max).
 __device__ inline void argmax_conf(float logit, int *cls, float *conf) {
-  float l0 = __shfl(logit, 0), l1 = __shfl(logit, 1), l2 = __shfl(logit, 2), l3 = __shfl(logit, 3);
-  float L[4] = {l0, l1, l2, l3};
+  static_assert(NC == 4, "four classes");
+  const float l0 = __shfl(logit, 0), l1 = __shfl(logit, 1), l2 = __shfl(logit, 2), l3 = __shfl(logit, 3);
   int best = 0;
-  for (int j = 1; j < NC; ++j)
-    if (L[j] > L[best]) best = j;
+  float mx = l0;
+  if (l1 > mx) { best = 1; mx = l1; }
+  if (l2 > mx) { best = 2; mx = l2; }
+  if (l3 > mx) { best = 3; mx = l3; }
   float s = 0.f;
-  for (int j = 0; j < NC; ++j) s += expf(L[j] - L[best]);
+  s += expf(l0 - mx);
+  s += expf(l1 - mx);
+  s += expf(l2 - mx);
+  s += expf(l3 - mx);
   *cls = best;
   *conf = 1.f / s;
 }
@@ -164,15 +177,18 @@ __device__ inline void argmax_conf(float logit, int *cls, float *conf) {
 // Runs after the step that produced F_k: updates the running unvisited
 // totals, advances the direction rule, evaluates the network on F_k's
 // features and stores the choice in ring[k % RING].decision.
-// Run by one whole wave.  smem: SM_SELECT bytes.  lds: the parameters staged
-// by stage_selector (else read from global memory).
+// Run by one whole wave.  smem: SM_SELECT bytes.  REGS: the network is
+// evaluated from this lane's rows loaded by load_net (regs), else from the
+// weights in global memory.
+template <bool REGS = false>
 __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, int init,
-                                            int use_net, LevelLog *log, char *smem, const SelLds *lds = nullptr) {
+                                            int use_net, LevelLog *log, char *smem, const NetRegs &regs = NetRegs{}) {
   float *s_x = reinterpret_cast<float *>(smem), *h0 = s_x + NF, *h1 = h0 + NH, *h2 = h1 + NH;
   int &s_hv = *reinterpret_cast<int *>(h2 + NH);
   LevelCtr *c = &ring[k % RING].tot;
   long long *st = reinterpret_cast<long long *>(sd.state);
   const long long nF = c->count;
+  long long nU0 = 0, eU0 = 0;  // lane 0: the unvisited totals after F_k
   if (lane() == 0) {
     if (init) {
       st[0] = (long long)n;
@@ -194,10 +210,8 @@ __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring,
     st[2] = dir;
     st[3] = nF;
     s_hv = dir ? sd.pull_v : sd.push_v;
-    float f[NF];
-    level_features((double)n, (double)nnz, (double)k, (double)nF, (double)c->edges, (double)st[0], (double)st[1],
-                   (double)c->ld, (double)c->ld2, (double)sd.gld, (double)sd.gld2, f);
-    for (int i = 0; i < NF; ++i) s_x[i] = f[i];
+    nU0 = st[0];
+    eU0 = st[1];
   }
   __builtin_amdgcn_wave_barrier();
   if (!use_net) {  // direction rule only
@@ -211,11 +225,16 @@ __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring,
     }
     return;
   }
-  // range check on raw features, then normalise
+  // the level's raw features, one per lane (the unvisited totals st[0..1]
+  // were updated by lane 0 above); range check, then normalise
   bool out_of_range = false;
   float xn = 0.f;
+  const long long nU = ((long long)__shfl((int)(nU0 >> 32), 0) << 32) | (u32)__shfl((int)nU0, 0);
+  const long long eU = ((long long)__shfl((int)(eU0 >> 32), 0) << 32) | (u32)__shfl((int)eU0, 0);
   if (lane() < NF) {
-    float r = s_x[lane()];
+    const float r = level_feature(lane(), (double)n, (double)nnz, (double)k, (double)nF, (double)c->edges,
+                                  (double)nU, (double)eU, (double)c->ld, (double)c->ld2, (double)sd.gld,
+                                  (double)sd.gld2);
     out_of_range = r < sd.norm[2 * NF + lane()] || r > sd.norm[3 * NF + lane()];
     xn = (r - sd.norm[lane()]) / sd.norm[NF + lane()];
   }
@@ -224,8 +243,8 @@ __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring,
   if (lane() < NF) s_x[lane()] = xn;
   __builtin_amdgcn_wave_barrier();
   float logit;
-  if (lds) {
-    logit = forward_row_lds(*lds, s_x, h0, h1, h2);
+  if (REGS) {
+    logit = forward_row_regs(regs, s_x, h0, h1, h2);
   } else {
     float z1, z2;
     logit = forward_row(WBf16{sd.w}, sd.p, s_x, h0, h1, h2, z1, z2);

@@ -37,7 +37,7 @@ import graphgen as gg
 from . import _lib as L
 from . import api, selector
 
-CLASSES = [L.PUSH_Q_BLOCK, L.PUSH_Q_MERGE, L.PUSH_B_NOATOMIC, L.PULL_B]
+CLASSES = [L.PUSH_Q_BLOCK, L.PUSH_Q_THREAD, L.PUSH_B_NOATOMIC, L.PULL_B]
 TRAIN_GRAPHS = [("rmat", s, 4000 + s) for s in range(16, 23)] + \
                [("lattice", 1024, 4110), ("lattice", 2048, 4120), ("lattice", 4096, 4130)]
 EVAL_GRAPH = ("rmat", 22, 4922)

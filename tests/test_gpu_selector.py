@@ -1,9 +1,9 @@
 """The trained selector, loaded through the C ABI (bfs_selector_load of the
 shipped selector_weights.bin; the reference reads the same values from
 selector_weights.npz): levels stay exact under its choices, its device-side
-choices equal the reference's,
-and on freshly measured per-level step times of a held-out R-MAT graph it
-costs no more than the direction heuristic (the gain it was trained for)."""
+choices equal the reference's, and on a held-out R-MAT graph the steps it
+chooses cost no more device time than the direction heuristic's (the gain it
+was trained for), with the end-to-end ratio reported."""
 import os
 
 import numpy as np
@@ -53,22 +53,41 @@ def test_trained_selector_exact_and_matches_reference(weights):
 
 
 def test_trained_selector_gain_over_heuristic(weights):
-    """Per-level step times measured now, from the exact state of every level
-    of 8 searches on a held-out scale-20 R-MAT: the schedule the trained
-    selector picks must cost no more than the direction heuristic's (with 10%
-    slack for timing noise); the measured gain is printed."""
+    """Whole searches on a held-out R-MAT (scale 20, graph seed 4920; the
+    network never saw it), 16 sources, the trained selector against the
+    direction heuristic alone:
+    * the gain the network is trained for -- the device time of the steps its
+      schedule runs, summed over the searches (each level timed by HIP events
+      around its step), must not exceed the heuristic schedule's, with no
+      slack;
+    * end to end (wall time of whole searches, median of 5 passes taken in
+      turns) the per-level evaluation of the network is paid as well: the
+      measured ratio is printed, and the learned mode must stay within 10% of
+      the heuristic."""
+    import time
     g = gg.rmat(20, seed=4920).with_csc()
     dg = B.DeviceGraph.from_graph(g)
-    classes = [int(c) for c in weights["classes"]]
-    depths = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    cost = {"learned": 0.0, "heuristic": 0.0, "best": 0.0}
-    for s in gg.pick_sources(g, 8, 4921):
-        _, st_l = B.bfs_levels(dg, int(s), variant=B.AUTO_LEARNED, level_stats=True, levels=depths)
-        _, st_h = B.bfs_levels(dg, int(s), variant=B.AUTO_HEURISTIC, level_stats=True)
-        for k in range(st_l["num_levels"]):
-            t = {v: B.step_time(dg, depths, k, v, reps=3) for v in set(classes) | {B.PUSH_Q_BLOCK, B.PULL_B}}
-            cost["learned"] += t[int(st_l["variant"][k])]
-            cost["heuristic"] += t[int(st_h["variant"][k])]
-            cost["best"] += min(t[v] for v in classes)
-    print("summed step ms:", cost)
-    assert cost["learned"] <= 1.10 * cost["heuristic"]
+    srcs = gg.pick_sources(g, 16, 4921)
+    ws = torch.empty(B.workspace_size(g.n), dtype=torch.uint8, device="cuda")
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    step_ms = {}
+    for name, mode in (("learned", B.AUTO_LEARNED), ("heuristic", B.AUTO_HEURISTIC)):
+        tot = 0.0
+        for s in srcs:
+            _, st = B.bfs_levels(dg, int(s), variant=mode, flags=B.F_LEVEL_TIMING, workspace=ws, levels=lv)
+            tot += float(st["ms"].sum())
+        step_ms[name] = tot
+    wall = {"learned": [], "heuristic": []}
+    for _ in range(5):
+        for name, mode in (("learned", B.AUTO_LEARNED), ("heuristic", B.AUTO_HEURISTIC)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in srcs:
+                B.bfs_levels(dg, int(s), variant=mode, workspace=ws, levels=lv)
+            torch.cuda.synchronize()
+            wall[name].append(time.perf_counter() - t0)
+    med = {k: float(np.median(v)) for k, v in wall.items()}
+    ratio = med["heuristic"] / med["learned"]
+    print(f"summed step ms {step_ms}; whole-search wall s {med}; learned / heuristic rate {ratio:.3f}")
+    assert step_ms["learned"] <= step_ms["heuristic"]
+    assert ratio >= 0.90
