@@ -790,10 +790,8 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a, int phase) {
         if (hit[r]) {
           const u64 w = a.front[u[r]];
           f |= w;
-          if (PROBE || w) {
-            st.c[C_HITS] += 1;
-            st.c[C_HHITS] += 1;
-          }
+          st.c[C_HITS] += 1;  // a gathered word (zero as well, on paths without the probe)
+          st.c[C_HHITS] += 1;
         }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
@@ -950,7 +948,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
         if (hit[i]) {
           const u64 w = a.front[u[i]];
           acc[j] |= w;
-          st.c[C_HITS] += (PROBE || w) ? 1 : 0;
+          st.c[C_HITS] += 1;
         }
       st.c[C_SCAN] += (u32)min(d[j], MS_HEAD);
       if (more && (acc[j] & need[j]) != need[j]) {
@@ -1054,7 +1052,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
   #pragma unroll
           for (int i = 0; i < MS_EPT; ++i) {
             const u64 f = hit[i] ? a.front[u[i]] : 0ull;
-            st.c[C_HITS] += (PROBE ? hit[i] : f != 0ull) ? 1 : 0;
+            st.c[C_HITS] += hit[i] ? 1 : 0;
             if (own[i] != ro) {
               if (run) atomicOr(&s_acc[ro], run);
               run = 0ull;
@@ -1104,7 +1102,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
   #pragma unroll
           for (int i = 0; i < MS_EPT; ++i) {
             u64 f = hit[i] ? a.front[u[i]] : 0ull;
-            st.c[C_HITS] += (PROBE ? hit[i] : f != 0ull) ? 1 : 0;
+            st.c[C_HITS] += hit[i] ? 1 : 0;
             if (__ballot(f != 0ull)) {
               const int oi = own[i];
   #pragma unroll
