@@ -248,7 +248,7 @@ __device__ __forceinline__ int queue_slot(const int *seg, int qcap, int i) {
 }
 
 __device__ __forceinline__ void stage_seg(int *s_seg, const int *seg) {
-  for (int i = threadIdx.x; i < NSH + 2; i += blockDim.x) s_seg[i] = seg[i];
+  for (int i = threadIdx.x; i < NSH + 2; i += BLOCK) s_seg[i] = seg[i];  // BLOCK-wide workgroups
   __syncthreads();
 }
 
@@ -296,8 +296,8 @@ struct NewStats {
 // Zeroes the dead frontier bitmap (it receives F_{k+2} at the next level)
 // and the counter shards of level k+2.  Called by the first kernel of a step.
 __device__ __forceinline__ void clear_dead(const StepArgs &a) {
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nthr = gridDim.x * blockDim.x;
+  const int tid = blockIdx.x * BLOCK + threadIdx.x;  // BLOCK-wide workgroups
+  const int nthr = gridDim.x * BLOCK;
   for (int i = tid; i < a.W; i += nthr) a.fb_dead[i] = 0ull;
   u32 *z = reinterpret_cast<u32 *>(a.sh_zero);
   const int nz = (NSH + 1) * (int)(sizeof(LevelCtr) / sizeof(u32));

@@ -148,6 +148,13 @@ struct MsArgs {
   int sshift;           // in the frontier; MS_SUM_WORDS words, staged in LDS by bottom-up kernels
                         // when the frontier is sparse
   MsCtr *sh;            // NSH shards of this level's counters
+  // Sparse top-down level: k_ms_push clears the dead buffer at the vertices
+  // of its bitmap (nbits before it is rewritten: the dead buffer is nonzero
+  // only there) and appends every vertex whose next word it turns nonzero to
+  // tq; k_ms_push_update_sparse then updates only those.
+  int sparse;
+  int *tq;              // touched list (n entries)
+  u32 *tqn;             // its length
 };
 
 struct MsCarve {
@@ -157,8 +164,10 @@ struct MsCarve {
   u64 *hubst;
   long long *bwt;       // per heavy-list block: tile weight of its chunks, then their exclusive prefix
   MsCtr *sh, *tot;
+  int *tq;              // sparse top-down levels: vertices whose next word turned nonzero
   int *src;             // [64] sources of the group, [64] their degrees, [192..196] heavy and tile
-                        // totals, [200] the top-down heavy-source flag
+                        // totals, [200] the top-down heavy-source flag, [203] the touched-list
+                        // length
   size_t bytes;
 };
 
@@ -205,6 +214,8 @@ static MsCarve ms_carve(uintptr_t p, int n) {
   c.sh = reinterpret_cast<MsCtr *>(p + off);
   c.tot = c.sh + NSH;
   off += (size_t)(NSH + 1) * sizeof(MsCtr);
+  c.tq = reinterpret_cast<int *>(p + off);
+  off += ib;
   c.src = reinterpret_cast<int *>(p + off);
   off += 1024;
   c.bytes = off;
@@ -306,14 +317,47 @@ __device__ __forceinline__ void ms_flush_block(MsStats &st, MsCtr *sh) {
   }
 }
 
+// Reduces the NSH counter shards of a level into *tot (pinned host memory)
+// and clears each shard after reading it, ready for the next level.  One
+// thread writes the totals, then -- after a system-scope fence -- `seq` into
+// the last word, which the host polls instead of waiting for the stream.
+// tqn (after a sparse top-down level): the touched-list length, reset.
+__global__ __launch_bounds__(NSH) void k_ms_finish(MsCtr *sh, MsCtr *tot, u64 seq, u32 *tqn) {
+  __shared__ u64 s_red[MS_NCTR][NSH / WAVE];
+  const int t = threadIdx.x;
+  u64 *f = reinterpret_cast<u64 *>(sh + t);
+  u64 x[MS_NCTR];  // all of the shard's loads in flight before the first reduction
+#pragma unroll
+  for (int j = 0; j < MS_NCTR; ++j) x[j] = f[j];
+#pragma unroll
+  for (int j = 0; j < MS_NCTR; ++j) f[j] = 0ull;
+#pragma unroll
+  for (int j = 0; j < MS_NCTR; ++j) {
+    const u64 r = wave_sum_u64(x[j]);
+    if (lane() == 0) s_red[j][t / WAVE] = r;
+  }
+  __syncthreads();
+  if (t == 0) {
+    if (tqn) *tqn = 0u;
+    u64 *o = reinterpret_cast<u64 *>(tot);
+    for (int j = 0; j < MS_NCTR - 1; ++j) {
+      u64 r = 0;
+      for (int i = 0; i < NSH / WAVE; ++i) r += s_red[j][i];
+      o[j] = r;
+    }
+    __threadfence_system();
+    reinterpret_cast<volatile u64 *>(o)[MS_NCTR - 1] = seq;
+  }
+}
+
 // Clears the dead frontier buffer and, when the host asks for it, the depth
 // plane the next level will use for the first time (zeroed here, one level
 // ahead, instead of by a launch on the host's critical path).  dead = null:
 // another kernel of the level does it.
 __device__ __forceinline__ void ms_clear_dead(const MsArgs &a) {
   if (!a.dead) return;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nthr = gridDim.x * blockDim.x;
+  const int tid = blockIdx.x * BLOCK + threadIdx.x;  // BLOCK-wide workgroups
+  const int nthr = gridDim.x * BLOCK;
   for (int i = tid; i < a.n; i += nthr) {
     a.dead[i] = 0ull;
     if (a.zplane) a.zplane[i] = 0ull;
@@ -385,21 +429,32 @@ __device__ __forceinline__ void ms_out_body(const MsArgs &a, int flush) {
 }
 
 // ------------------------------------------------------------------ init
-// Clears a group's state: visited words, two frontier buffers, the first
-// frontier bitmap, depth plane 0, the counter shards (k_ms_finish keeps
-// those clear afterwards) and the heavy-source flag.
-__global__ __launch_bounds__(BLOCK) void k_ms_init(MsArgs a, u64 *f0, u64 *f1, u64 *b0) {
+// Clears a group's state: visited words, the three frontier buffers, both
+// frontier bitmaps, depth planes 0 and 1 (relative depths 1..3), the
+// counter shards (k_ms_finish keeps those clear afterwards), the
+// heavy-source flag and the touched-list length.  With every frontier buffer
+// and bitmap zero, the first level, like any later sparse top-down level,
+// clears only what it finds set.
+__global__ __launch_bounds__(BLOCK) void k_ms_init(MsArgs a, u64 *f0, u64 *f1, u64 *f2, u64 *b0, u64 *b1) {
   const int nw = (a.n + 63) / 64;
   for (int v = blockIdx.x * BLOCK + threadIdx.x; v < a.n; v += gridDim.x * BLOCK) {
     a.vis[v] = 0ull;
     f0[v] = 0ull;
     f1[v] = 0ull;
+    f2[v] = 0ull;
     a.planes[v] = 0ull;
-    if (v < nw) b0[v] = 0ull;
+    a.planes[(size_t)a.n + v] = 0ull;
+    if (v < nw) {
+      b0[v] = 0ull;
+      b1[v] = 0ull;
+    }
   }
   u64 *sh = reinterpret_cast<u64 *>(a.sh);
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < NSH * MS_NCTR; i += gridDim.x * BLOCK) sh[i] = 0ull;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.hsrc = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *a.hsrc = 0u;
+    *a.tqn = 0u;
+  }
 }
 
 // One thread per lane: sets the source bit (duplicates OR); depth 0 is
@@ -896,15 +951,28 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       d[j] = 0;
       heavy[j] = false;
     }
+    // in-edge offsets (and on a split level what the light sources pushed)
+    // for every vertex of the tile, loaded with the visited words rather
+    // than after them: the range is read in whole lines either way, and the
+    // head loads below wait for one round trip less
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = vb + j * BLOCK + t;
+      if (v < ve) {
+        b[j] = a.cp[v];
+        d[j] = a.cp[v + 1];
+        if (SPLIT) acc[j] = a.next[v];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       if (need[j]) {
-        const int v = vb + j * BLOCK + t;
         st.c[C_UNVIS] += 1;
-        b[j] = a.cp[v];
-        d[j] = a.cp[v + 1] - b[j];
+        d[j] -= b[j];
         heavy[j] = d[j] > MS_HEAVY;
-        if (SPLIT) acc[j] = a.next[v];  // what the light sources pushed
+      } else {
+        b[j] = d[j] = 0;
+        if (SPLIT) acc[j] = 0ull;
       }
     }
 #pragma unroll
@@ -1148,8 +1216,77 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
 }
 
 // ------------------------------------------------------------------ push
+// ORs lanes m[r] into the next words of v[r] (m[r] = 0: nothing), NR per
+// lane at once.  On a sparse level the ORs return the old words, and the
+// targets they found zero (first touches: each vertex once per level) are
+// appended to the touched list, all NR rounds with one atomic per wave.
+// The whole wave calls it.
+template <bool SPARSE, int NR>
+__device__ __forceinline__ void ms_push_or(const MsArgs &a, const int (&v)[NR], const u64 (&m)[NR]) {
+  if (!SPARSE) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (m[r]) atomicOr(a.next + v[r], m[r]);
+    return;
+  }
+  bool first[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) first[r] = m[r] ? atomicOr(a.next + v[r], m[r]) == 0ull : false;
+  u64 bm[NR];
+  u32 tot = 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    bm[r] = __ballot(first[r]);
+    tot += (u32)__popcll(bm[r]);
+  }
+  if (tot == 0u) return;  // uniform
+  u32 pos = 0;
+  if (lane() == 0) pos = atomicAdd(a.tqn, tot);
+  pos = __shfl(pos, 0);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (first[r]) a.tq[pos + __popcll(bm[r] & __lanemask_lt())] = v[r];
+    pos += (u32)__popcll(bm[r]);
+  }
+}
+
+// Sparse level: the dead buffer (F_{k-1}'s words) is nonzero only at the
+// vertices whose bits the bitmap nbits still holds, so only those words are
+// cleared, and the bitmap with them (the sparse update sets F_{k+1}'s bits
+// into it).  One wave per 64 bitmap words; the words of one nonzero bitmap
+// word go out in one masked store of whole lines.  (On the first level both
+// are zero: k_ms_init cleared them.)  The next level's new depth plane, if
+// any, is cleared whole.
+__device__ __forceinline__ void ms_clear_dead_sparse(const MsArgs &a) {
+  const int nwords = (a.n + WAVE - 1) / WAVE;
+  const int gw = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE, nwv = gridDim.x * (BLOCK / WAVE);
+  for (int w0 = gw * WAVE; w0 < nwords; w0 += nwv * WAVE) {  // uniform per wave
+    const int w = w0 + lane();
+    const u64 x = w < nwords ? a.nbits[w] : 0ull;
+    if (x) a.nbits[w] = 0ull;
+    // whole 64-byte lines: each byte of the bitmap word that has a bit set
+    // clears its eight words (the others are zero already), so no line is
+    // written in part
+    u64 y = x | (x >> 1);
+    y |= y >> 2;
+    y |= y >> 4;
+    const u64 lines = (y & 0x0101010101010101ull) * 0xFFull;
+    for (u64 nz = __ballot(x != 0ull); nz; nz &= nz - 1ull) {
+      const int i = __ffsll((long long)nz) - 1;
+      const u64 li = __shfl(lines, i);
+      if ((li >> lane()) & 1ull) a.dead[(size_t)(w0 + i) * WAVE + lane()] = 0ull;
+    }
+  }
+  if (a.zplane)
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < a.n; i += gridDim.x * BLOCK) a.zplane[i] = 0ull;
+}
+
+template <bool SPARSE>
 __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
-  ms_clear_dead(a);
+  if (SPARSE)
+    ms_clear_dead_sparse(a);
+  else
+    ms_clear_dead(a);
   MsStats st;
   const int wv = threadIdx.x / WAVE;
   const int nwords = (a.n + WAVE - 1) / WAVE;
@@ -1159,7 +1296,6 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
     const int u = w * WAVE + lane();
     const u64 fu = ((wb >> lane()) & 1ull) ? a.front[u] : 0ull;
     int b = 0, e = 0;
-    bool pending = false;
     if (fu) {
       b = a.rp[u];
       e = a.rp[u + 1];
@@ -1167,18 +1303,20 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
         e = b;
         atomicOr(a.hsrc, 1u);
       }
-      const int d = e - b;
-#pragma unroll
-      for (int t = 0; t < MS_T; ++t)
-        if (t < d) {
-          const int v = a.ci[b + t];
-          const u64 m = fu & ~a.vis[v];
-          if (m) atomicOr(a.next + v, m);
-        }
-      st.c[C_SCAN] += (u32)min(d, MS_T);
-      pending = d > MS_T;
-      b += MS_T;
     }
+    const int d = e - b;  // 0 off the frontier
+    {
+      int v[MS_T];
+      u64 m[MS_T];
+#pragma unroll
+      for (int t = 0; t < MS_T; ++t) v[t] = t < d ? a.ci[b + t] : -1;
+#pragma unroll
+      for (int t = 0; t < MS_T; ++t) m[t] = v[t] >= 0 ? fu & ~a.vis[v[t]] : 0ull;
+      ms_push_or<SPARSE>(a, v, m);
+    }
+    st.c[C_SCAN] += (u32)min(d, MS_T);
+    const bool pending = d > MS_T;
+    b += MS_T;
     u64 pm = __ballot(pending);
     while (pm) {
       const int l = __ffsll((long long)pm) - 1;
@@ -1195,9 +1333,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
         u64 m[MS_HU];
 #pragma unroll
         for (int r = 0; r < MS_HU; ++r) m[r] = v[r] >= 0 ? lf & ~a.vis[v[r]] : 0ull;
-#pragma unroll
-        for (int r = 0; r < MS_HU; ++r)
-          if (m[r]) atomicOr(a.next + v[r], m[r]);
+        ms_push_or<SPARSE>(a, v, m);
       }
       if (lane() == l) st.c[C_SCAN] += (u32)(ve - vb);
     }
@@ -1299,6 +1435,7 @@ static_assert(MS_PQ_GRID % MS_PQ_ROWS == 0, "staging rows split evenly");
 // Top-down, heavy part: one wave per chunk of MS_HCHUNK out-edges of a
 // heavy source (out-degree > MS_HEAVY) that is in the frontier, so a hub's
 // list is spread over many waves.
+template <bool SPARSE>
 __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
   if (__hip_atomic_load(a.hsrc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;  // uniform
   if (a.ochunks < 0) {  // the first level, enqueued before the host read the heavy-list totals
@@ -1323,9 +1460,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_heavy(MsArgs a) {
       u64 m[MS_HU];
 #pragma unroll
       for (int r = 0; r < MS_HU; ++r) m[r] = v[r] >= 0 ? fu & ~a.vis[v[r]] : 0ull;
-#pragma unroll
-      for (int r = 0; r < MS_HU; ++r)
-        if (m[r]) atomicOr(a.next + v[r], m[r]);
+      ms_push_or<SPARSE>(a, v, m);
     }
     if (lane() == 0) {
       st.c[C_SCAN] += (u32)(se - sb);
@@ -1351,6 +1486,22 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push_update(MsArgs a) {
   ms_flush_block<MS_M_FOUND>(st, a.sh);
 }
 
+// The update of a sparse top-down level: only the touched vertices (each
+// listed once, its next word nonzero and already masked); their bits go into
+// the bitmap k_ms_push cleared.
+__global__ __launch_bounds__(BLOCK) void k_ms_push_update_sparse(MsArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.hsrc = 0u;  // k_ms_push_heavy has finished
+  if (a.hub_t < 0) a.hub_t = a.otot[0];  // the first level (see MsArgs::hub_t)
+  MsStats st;
+  const int cnt = (int)*a.tqn;
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < cnt; i += gridDim.x * BLOCK) {
+    const int v = a.tq[i];
+    ms_discover(a, v, a.vis[v], a.next[v], st);
+    atomicOr(a.nbits + (v >> 6), 1ull << (v & 63));
+  }
+  ms_flush_block<MS_M_FOUND>(st, a.sh);
+}
+
 // Output pass.  flush = 0: the final pass, every lane not yet written (depth
 // from the planes, or -1).  flush = 1: the lanes visited since the last
 // flush, which are then marked in `flushed`.
@@ -1368,35 +1519,10 @@ __global__ __launch_bounds__(BLOCK) void k_ms_out(MsArgs a, int flush) {
   }
 }
 
-// Reduces the NSH counter shards of a level into *tot (pinned host memory)
-// and clears each shard after reading it, ready for the next level.  One
-// thread writes the totals, then -- after a system-scope fence -- `seq` into
-// the last word, which the host polls instead of waiting for the stream.
-__global__ __launch_bounds__(NSH) void k_ms_finish(MsCtr *sh, MsCtr *tot, u64 seq) {
-  __shared__ u64 s_red[MS_NCTR][NSH / WAVE];
-  const int t = threadIdx.x;
-  u64 *f = reinterpret_cast<u64 *>(sh + t);
-  u64 x[MS_NCTR];  // all of the shard's loads in flight before the first reduction
-#pragma unroll
-  for (int j = 0; j < MS_NCTR; ++j) x[j] = f[j];
-#pragma unroll
-  for (int j = 0; j < MS_NCTR; ++j) f[j] = 0ull;
-#pragma unroll
-  for (int j = 0; j < MS_NCTR; ++j) {
-    const u64 r = wave_sum_u64(x[j]);
-    if (lane() == 0) s_red[j][t / WAVE] = r;
-  }
-  __syncthreads();
-  if (t == 0) {
-    u64 *o = reinterpret_cast<u64 *>(tot);
-    for (int j = 0; j < MS_NCTR - 1; ++j) {
-      u64 r = 0;
-      for (int i = 0; i < NSH / WAVE; ++i) r += s_red[j][i];
-      o[j] = r;
-    }
-    __threadfence_system();
-    o[MS_NCTR - 1] = seq;
-  }
+// One output pass over all n columns.
+static void launch_ms_out(const MsArgs &a, int flush, hipStream_t s) {
+  const int grid = std::min(4096, (a.n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_ms_out, dim3(grid), dim3(BLOCK), 0, s, a, flush);
 }
 
 
@@ -1517,12 +1643,15 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.levels = levels + (size_t)g0 * n;
     a.vmap = opt ? opt->vertex_map : nullptr;
     a.hsrc = reinterpret_cast<u32 *>(src_dev + 200);
+    a.tqn = reinterpret_cast<u32 *>(src_dev + 203);
+    a.tq = W.tq;
+    a.sparse = 0;
     a.hubst = W.hubst;
     a.sh = sh;
     a.base = 0;
-    a.np = 1;  // plane 0 is cleared by k_ms_init
+    a.np = 2;  // planes 0 and 1 are cleared by k_ms_init
     a.nflush = 0;
-    hipLaunchKernelGGL(k_ms_init, dim3(grid_v), dim3(BLOCK), 0, s, a, fr[0], fr[1], W.fb[0]);
+    hipLaunchKernelGGL(k_ms_init, dim3(grid_v), dim3(BLOCK), 0, s, a, fr[0], fr[1], fr[2], W.fb[0], W.fb[1]);
     // sources by value; the seed kernel posts the counts of F_0 for the
     // direction rule (distinct source vertices and their degrees) and the
     // heavy-list and tile totals, which the host polls for
@@ -1615,7 +1744,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       }
       // relative depth of this step's discoveries; a full window is written out first
       if (lev + 1 - a.base >= (1 << MS_PLANES)) {
-        hipLaunchKernelGGL(k_ms_out, dim3(grid_v), dim3(BLOCK), 0, s, a, 1);
+        launch_ms_out(a, 1, s);
         ++a.nflush;
         a.base = lev;
         a.np = 0;
@@ -1633,6 +1762,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         ++a.np;
       }
       a.k = lev;
+      a.sparse = 0;
       a.front = fr[lev % 3];
       a.next = fr[(lev + 1) % 3];
       a.dead = fr[(lev + 2) % 3];
@@ -1726,21 +1856,37 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         if (mtiming) BFS_HIP(hipEventRecord(E[2], s));
         a.split_t = 0;
       } else {
+        // Sparse level (few frontier out-edges, or the first level, whose
+        // counts the host reads with its totals): the vertices it reaches are
+        // listed and only they are updated, and the dead buffer is cleared at
+        // F_{k-1}'s vertices only, instead of passes over all n words.
+        const bool sparse = !seed_read || ef * 8 < (long long)n;
+        a.sparse = sparse ? 1 : 0;
         if (mtiming) BFS_HIP(hipEventRecord(E[1], s));
-        hipLaunchKernelGGL(k_ms_push, dim3(grid_w), dim3(BLOCK), 0, s, a);
+        if (sparse)
+          hipLaunchKernelGGL(k_ms_push<true>, dim3(grid_w), dim3(BLOCK), 0, s, a);
+        else
+          hipLaunchKernelGGL(k_ms_push<false>, dim3(grid_w), dim3(BLOCK), 0, s, a);
         if (mtiming) BFS_HIP(hipEventRecord(E[2], s));
         // chunk count not read back yet (first level): a grid for any graph; the kernel
         // reads the count, and returns at once unless a heavy source is in the frontier
         const long long och = a.ochunks >= 0 ? a.ochunks : 2 * (long long)g->nnz / MS_HCHUNK + 1;
-        if (och > 0)
-          hipLaunchKernelGGL(k_ms_push_heavy, dim3((int)std::min<long long>(4096, (och + 3) / 4)), dim3(BLOCK), 0,
-                             s, a);
-        hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
+        const dim3 gph((unsigned)std::min<long long>(4096, (och + 3) / 4));
+        if (och > 0 && sparse)
+          hipLaunchKernelGGL(k_ms_push_heavy<true>, gph, dim3(BLOCK), 0, s, a);
+        else if (och > 0)
+          hipLaunchKernelGGL(k_ms_push_heavy<false>, gph, dim3(BLOCK), 0, s, a);
+        if (sparse) {  // at most ef vertices touched (any number on the first level)
+          const long long gu = seed_read ? std::max(1LL, std::min(4096LL, (ef + BLOCK - 1) / BLOCK)) : 1024LL;
+          hipLaunchKernelGGL(k_ms_push_update_sparse, dim3((unsigned)gu), dim3(BLOCK), 0, s, a);
+        } else {
+          hipLaunchKernelGGL(k_ms_push_update, dim3(grid_v), dim3(BLOCK), 0, s, a);
+        }
       }
       if (timing) BFS_HIP(hipEventRecord(E[3], s));
       MsCtr *tot_host = reinterpret_cast<MsCtr *>(hc.pinned);
       const u64 seq = ++hc.seq;
-      hipLaunchKernelGGL(k_ms_finish, dim3(1), dim3(NSH), 0, s, sh, tot_host, seq);
+      hipLaunchKernelGGL(k_ms_finish, dim3(1), dim3(NSH), 0, s, sh, tot_host, seq, a.sparse ? a.tqn : nullptr);
       BFS_HIP(hipGetLastError());
       rc = resolve_timing();  // the previous level's events, while this one runs
       if (rc) return rc;
@@ -1791,7 +1937,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       }
     }
     comp += src_comp;  // each lane's source belongs to its component
-    hipLaunchKernelGGL(k_ms_out, dim3(grid_v), dim3(BLOCK), 0, s, a, 0);
+    launch_ms_out(a, 0, s);
     BFS_HIP(hipGetLastError());
     max_levels = std::max(max_levels, lev);
     rc = resolve_timing();

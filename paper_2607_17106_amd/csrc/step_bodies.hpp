@@ -48,8 +48,8 @@ __device__ __forceinline__ void body_reset(const StepArgs &a, int src, RingSlot 
     }
   }
   // zero every shard of every slot
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nthr = gridDim.x * blockDim.x;
+  const int tid = blockIdx.x * BLOCK + threadIdx.x;  // BLOCK-wide workgroups
+  const int nthr = gridDim.x * BLOCK;
   const int per = (int)(sizeof(RingSlot) / sizeof(u32));
   u32 *z = reinterpret_cast<u32 *>(ring);
   for (int i = tid; i < RING * per; i += nthr) z[i] = 0u;
@@ -875,7 +875,7 @@ __device__ __forceinline__ void body_pull(const StepArgs &a) {
 
 // After a visited-as-frontier pull: P_{k+1} = P_k OR F_{k+1}.
 __device__ __forceinline__ void body_merge_vis(const StepArgs &a) {
-  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < a.W; w += gridDim.x * blockDim.x) {
+  for (int w = blockIdx.x * BLOCK + threadIdx.x; w < a.W; w += gridDim.x * BLOCK) {  // BLOCK-wide workgroups
     const u64 m = a.fb_next[w];
     if (m) a.vis[w] |= m;
   }
