@@ -237,10 +237,21 @@ def main():
 
     # ---------------------------------------------------------- timed step
     # timing: 0 none, 1 the main kernel of each level (HIP events around it:
-    # the tile kernel's duration for the roofline), 2 every level's step too
-    def step(timing, graph=rg, vmap=new_of_old):
+    # the tile kernel's duration for the roofline), 2 every level's step too.
+    # config None: the configuration bfs_multi_autotune stored for the graph.
+    def step(timing, graph=rg, vmap=new_of_old, config=None):
         flags = (0, B.F_MAIN_TIMING, B.F_LEVEL_TIMING)[timing]
-        return B.bfs_multi(graph, sources, flags=flags, workspace=ws_multi, levels=lv_multi, vertex_map=vmap)[1]
+        return B.bfs_multi(graph, sources, flags=flags, workspace=ws_multi, levels=lv_multi, vertex_map=vmap,
+                           config=config)[1]
+
+    def autotune(graph, vmap):
+        return timed(lambda: B.bfs_multi_autotune(graph, sources, workspace=ws_multi, levels=lv_multi,
+                                                  vertex_map=vmap))
+
+    # autotuning, like the renumbering, is per-graph preparation outside the
+    # timed region; the defaults are timed too, after the tuned steps
+    (tuned, tuned_ms), tune_s = autotune(rg, new_of_old)
+    log(f"[bench] autotuned in {tune_s:.2f} s: {tuned} ({tuned_ms:.3f} ms)")
 
     for _ in range(args.warmup):
         step(0)
@@ -256,10 +267,21 @@ def main():
     # per-level step times for the diagnostics below, from the same steps run
     # again after the timed region
     stats_lev = [step(2) for _ in range(args.steps)]
+    # the library defaults (no tuning), for comparison: the same steps with
+    # the same main-kernel events
+    step(1, config=B.MultiConfig())
+    torch.cuda.synchronize()
+    t_d = time.perf_counter()
+    for _ in range(args.steps):
+        step(1, config=B.MultiConfig())
+    torch.cuda.synchronize()
+    default_ms = (time.perf_counter() - t_d) * 1e3 / args.steps
+    log(f"[bench] library defaults: {default_ms:.3f} ms per step")
 
     # the same search on the graph as generated (no renumbering), for comparison
     input_order = rcm_order = None
     if not args.no_input_order:
+        (tuned_in, _), tune_in_s = autotune(dg, None)
         step(0, dg, None)
         torch.cuda.synchronize()
         t_in = time.perf_counter()
@@ -267,7 +289,8 @@ def main():
         torch.cuda.synchronize()
         el_in = time.perf_counter() - t_in
         input_order = {"gteps": round(sum(st["component_edges"] for st in st_in) / 2 / el_in / 1e9, 3),
-                       "ms_per_step": round(el_in * 1e3 / args.steps, 3)}
+                       "ms_per_step": round(el_in * 1e3 / args.steps, 3), "multi_config": vars(tuned_in),
+                       "autotune_s": round(tune_in_s, 2)}
         # the tile kernel's roofline on this graph, from steps run again with
         # the main-kernel events (outside the timed loop above)
         t_in = b_in = 0.0
@@ -288,6 +311,7 @@ def main():
         log(f"[bench] input order: {input_order}")
         # and on the graph renumbered by reverse Cuthill-McKee
         (cg, cmap, _), rcm_s = timed(lambda: B.reorder_rcm(dg))
+        autotune(cg, cmap)
         step(0, cg, cmap)
         torch.cuda.synchronize()
         t_c = time.perf_counter()
@@ -350,7 +374,8 @@ def main():
                       "method": "64-lane bit-packed multi-source BFS (bfs_multi)", "output": "depths [64][n]",
                       "vertex_order": "renumbered by decreasing out-degree (bfs_reorder_degree, preprocessing, "
                                       "outside the timed region); sources and depths in the original numbering",
-                      "reorder_ms": round(reorder_s * 1e3, 2)},
+                      "reorder_ms": round(reorder_s * 1e3, 2), "multi_config": vars(tuned),
+                      "autotune_s": round(tune_s, 2), "library_defaults_ms_per_step": round(default_ms, 3)},
            "roofline": roof, "input_order": input_order, "rcm_order": rcm_order}
 
     # ------------------------------------------- single-source comparisons

@@ -156,6 +156,35 @@ typedef struct bfs_graph {
                               deterministic early exit */
 } bfs_graph;
 
+/* Tunable choices of bfs_multi's level steps (bfs_options.multi_config).  A
+ * zero field takes the default in brackets.  No choice changes the depths,
+ * only the time; bfs_multi_autotune picks them per graph.
+ *   wide_ratio  non-split bottom-up levels run one vertex per thread while
+ *               the in-edges of the vertices still missing a lane exceed
+ *               wide_ratio * n, four per thread otherwise [8]
+ *   split_vpt   vertices per thread on split bottom-up levels, 1 or 4 [4]
+ *   cap0        in-edges per pending vertex in the first round of a
+ *               bottom-up level whose frontier holds more than a quarter of
+ *               those in-edges (rounds grow 4x; sparser frontiers take every
+ *               list in one round) [32]
+ *   tile_alpha  bottom-up tiles: a 64-vertex chunk weighs at least
+ *               tile_alpha per vertex, or its in-degree sum if larger, and a
+ *               tile holds 256 * tile_alpha of weight, 16 .. 1024 [64]
+ *   alpha       direction: bottom-up once the frontier's out-edges exceed
+ *               1/alpha of the in-edges of the vertices still missing a lane
+ *               (and n/8) [7]
+ *   split_lout  with BFS_F_HUB_ORDER: a bottom-up level is split when the
+ *               frontier holds at most a quarter of those in-edges and its
+ *               light vertices' out-edges times split_lout are fewer [16] */
+typedef struct bfs_multi_config {
+  int32_t wide_ratio;
+  int32_t split_vpt;
+  int32_t cap0;
+  int32_t tile_alpha;
+  int32_t alpha;
+  int32_t split_lout;
+} bfs_multi_config;
+
 typedef struct bfs_options {
   int32_t variant;               /* BFS_V_* or BFS_AUTO_* / BFS_SCHEDULE */
   int32_t flags;                 /* BFS_F_* */
@@ -185,6 +214,9 @@ typedef struct bfs_options {
                                     vertices >= T are few; otherwise no split.  > 0: T =
                                     min(hub_split, n) on every bottom-up level.  < 0: never.
                                     A split needs every in-edge list in ascending order */
+  const bfs_multi_config *multi_config; /* bfs_multi only: NULL => the configuration
+                                    bfs_multi_autotune stored for this graph (same n, nnz,
+                                    array addresses and BFS_F_HUB_ORDER), else the defaults */
 } bfs_options;
 
 typedef struct bfs_stats {
@@ -321,6 +353,17 @@ int bfs_levels_noalloc(const bfs_graph *g, int32_t source, int32_t *levels, cons
  * state at its new id. */
 int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_t *levels,
               const bfs_options *opt, bfs_stats *st, void *stream);
+
+/* Tunes bfs_multi's configuration for one graph and source set: runs the
+ * search (k sources, the same options otherwise) with candidate values of
+ * each bfs_multi_config field in turn, keeping the fastest by device time
+ * (best of two runs), starting from options.multi_config or the defaults.
+ * The result is returned in *best (and the time in *ms_best, may be NULL)
+ * and stored for the graph, so later bfs_multi calls on it with
+ * multi_config = NULL use it.  levels: device [k][n] scratch (holds the last
+ * run's depths on return).  Takes some 20 configurations x 2 runs. */
+int bfs_multi_autotune(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_t *levels,
+                       const bfs_options *opt, bfs_multi_config *best, float *ms_best, void *stream);
 
 /* ----------------------------------------------------------------- batch
  * Many independent graphs stored back to back (a disjoint union).  Instance b

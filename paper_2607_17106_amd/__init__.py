@@ -12,7 +12,8 @@ from ._lib import (  # noqa: F401
     F_LEVEL_STATS, F_DEVICE_LOOP, F_LEVEL_TIMING, F_GRAPH_SUMS, F_HUB_ORDER, F_MAIN_TIMING, BfsError, load,
 )
 from .api import (  # noqa: F401
-    DeviceGraph, DeviceBatch, bfs_levels, bfs_levels_noalloc, bfs_parents, bfs_multi, bfs_batch, bfs_batch_autotune,
+    DeviceGraph, DeviceBatch, bfs_levels, bfs_levels_noalloc, bfs_parents, bfs_multi, bfs_multi_autotune,
+    MultiConfig, bfs_batch, bfs_batch_autotune,
     workspace_size, selector_set, selector_clear, selector_loaded, mlp_forward, mlp_loss_grad, mlp_adam,
     mlp_predict, level_features, step_time, reorder_degree, reorder_rcm,
 )

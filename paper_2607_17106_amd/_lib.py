@@ -66,11 +66,17 @@ class BfsGraph(ctypes.Structure):
                 ("csc_ptr", c_void_p), ("csc_idx", c_void_p)]
 
 
+class BfsMultiConfig(ctypes.Structure):
+    _fields_ = [("wide_ratio", c_int32), ("split_vpt", c_int32), ("cap0", c_int32), ("tile_alpha", c_int32),
+                ("alpha", c_int32), ("split_lout", c_int32)]
+
+
 class BfsOptions(ctypes.Structure):
     _fields_ = [("variant", c_int32), ("flags", c_int32), ("schedule_host", POINTER(c_int32)),
                 ("schedule_len", c_int32), ("max_levels", c_int32), ("heuristic_push", c_int32),
                 ("heuristic_pull", c_int32), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
-                ("graph_ld", c_int64), ("graph_ld2", c_int64), ("vertex_map", c_void_p), ("hub_split", c_int32)]
+                ("graph_ld", c_int64), ("graph_ld2", c_int64), ("vertex_map", c_void_p), ("hub_split", c_int32),
+                ("multi_config", POINTER(BfsMultiConfig))]
 
 
 class BfsStats(ctypes.Structure):
@@ -116,6 +122,8 @@ SIGNATURES = {
                                      c_void_p]),
     "bfs_multi": (c_int32, [POINTER(BfsGraph), POINTER(c_int32), c_int32, c_void_p, POINTER(BfsOptions),
                             POINTER(BfsStats), c_void_p]),
+    "bfs_multi_autotune": (c_int32, [POINTER(BfsGraph), POINTER(c_int32), c_int32, c_void_p, POINTER(BfsOptions),
+                                     POINTER(BfsMultiConfig), POINTER(c_float), c_void_p]),
     "bfs_batch": (c_int32, [POINTER(BfsGraphBatch), POINTER(c_int32), c_void_p, POINTER(BfsBatchConfig),
                             POINTER(BfsStats), c_void_p]),
     "bfs_batch_autotune": (c_int32, [POINTER(BfsGraphBatch), POINTER(c_int32), c_void_p,

@@ -299,14 +299,44 @@ def bfs_levels_noalloc(g: DeviceGraph, source: int, variant: int = L.AUTO_HEURIS
     return levels, sb.as_dict(False)
 
 
+@dataclass
+class MultiConfig:
+    """bfs_multi_config: the tunable choices of bfs_multi's level steps (0 = the library default)."""
+    wide_ratio: int = 0
+    split_vpt: int = 0
+    cap0: int = 0
+    tile_alpha: int = 0
+    alpha: int = 0
+    split_lout: int = 0
+
+    def c(self):
+        return L.BfsMultiConfig(self.wide_ratio, self.split_vpt, self.cap0, self.tile_alpha, self.alpha,
+                                self.split_lout)
+
+
+def _multi_options(g, variant, flags, workspace, vertex_map, hub_split, config):
+    if getattr(g, "hub_order", False):
+        flags |= L.F_HUB_ORDER
+    opt, keep = _options(variant, flags, None, workspace, 0, None)
+    if vertex_map is not None:
+        opt.vertex_map = _check_vmap(g, vertex_map)
+    opt.hub_split = int(hub_split)
+    if config is not None:
+        cc = config.c()
+        keep.append(cc)
+        opt.multi_config = ctypes.pointer(cc)
+    return opt, keep
+
+
 def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: int = 0, workspace=None,
               levels=None, stream=None, level_stats: bool = False, stats_capacity: int = 1 << 14,
-              vertex_map=None, hub_split: int = 0):
+              vertex_map=None, hub_split: int = 0, config: MultiConfig = None):
     """Depths [k][n] from k sources in 64-lane bit-packed groups.  vertex_map:
     the new_of_old of reorder_degree when g is the renumbered graph (sources
     and depth columns then use the original ids).  hub_split: the split id of
     split bottom-up levels (0 automatic, > 0 that id on every bottom-up level,
-    < 0 never; bfs_options.hub_split)."""
+    < 0 never; bfs_options.hub_split).  config: a MultiConfig, or None for the
+    one bfs_multi_autotune stored for this graph (else the defaults)."""
     lib = L.load()
     src = np.ascontiguousarray(sources, dtype=np.int32)
     k = int(src.size)
@@ -317,16 +347,33 @@ def bfs_multi(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: i
     if level_stats:
         flags |= L.F_LEVEL_STATS
     sb = _StatsBuf.get(stats_capacity if level_stats else 0)
-    if getattr(g, "hub_order", False):
-        flags |= L.F_HUB_ORDER
-    opt, keep = _options(variant, flags, None, workspace, 0, None)
-    if vertex_map is not None:
-        opt.vertex_map = _check_vmap(g, vertex_map)
-    opt.hub_split = int(hub_split)
+    opt, keep = _multi_options(g, variant, flags, workspace, vertex_map, hub_split, config)
     rc = lib.bfs_multi(g.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k, _ptr(levels),
                        ctypes.byref(opt), ctypes.byref(sb.s), _stream(stream))
     L.check(rc, "bfs_multi")
+    del keep
     return levels[:k], sb.as_dict(level_stats)
+
+
+def bfs_multi_autotune(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC, flags: int = 0, workspace=None,
+                       levels=None, stream=None, vertex_map=None, hub_split: int = 0, config: MultiConfig = None):
+    """bfs_multi_autotune: the fastest MultiConfig for this graph and source
+    set (stored by the library for later bfs_multi calls on the graph) and
+    its device time in ms."""
+    lib = L.load()
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.size)
+    if levels is None:
+        levels = torch.empty((max(k, 1), g.n), dtype=torch.int32, device=g.row_ptr.device)
+    opt, keep = _multi_options(g, variant, flags, workspace, vertex_map, hub_split, config)
+    best = L.BfsMultiConfig()
+    ms = ctypes.c_float(0.0)
+    rc = lib.bfs_multi_autotune(g.c, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k, _ptr(levels),
+                                ctypes.byref(opt), ctypes.byref(best), ctypes.byref(ms), _stream(stream))
+    L.check(rc, "bfs_multi_autotune")
+    del keep
+    return MultiConfig(best.wide_ratio, best.split_vpt, best.cap0, best.tile_alpha, best.alpha,
+                       best.split_lout), float(ms.value)
 
 
 @dataclass

@@ -31,6 +31,7 @@
 // marks them, and a new window starts at base = k.
 #include <string.h>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -41,7 +42,6 @@ namespace bfs {
 constexpr int MS_T = 4;   // out-edges per lane before the wave-cooperative walk (push)
 constexpr int MS_HEAD = 8; // in-edges a light vertex's own thread reads before the merged walk (pull)
 static_assert(MS_HEAD % 4 == 0, "the head is read in 16-byte pieces");
-constexpr long long MS_ALPHA = 7;  // bottom-up when frontier out-edges exceed 1/7 of eu (and n/8)
 constexpr int MS_PLANES = 8;       // relative depths 0..255 per window
 constexpr int MS_HEAVY = 1024;     // in-degree above which a vertex's in-edges are split over waves
 constexpr int MS_HCHUNK = 1024;    // in-edges per wave in the heavy pass (<= MS_HEAVY)
@@ -50,27 +50,39 @@ struct __attribute__((packed, aligned(4))) I4u {  // four ints at any 4-byte-ali
   int x, y, z, w;
 };
 constexpr int MS_VPT_SPARSE = 4;   // vertices per thread in the bottom-up tile when few in-edges remain
-constexpr int MS_CAP0 = 32;        // in-edges per pending vertex in the first merged round (dense frontiers)
 constexpr int MS_HB = 1024;        // vertices per workgroup in the heavy-list build
 constexpr int MS_SUM_WORDS = 8192; // frontier summary: 2^18 bits = 32 KB of LDS
 constexpr int MS_SUM_GRID = 1024;  // persistent workgroups of the summary-filtered bottom-up kernels
 // Bottom-up tiles: runs of whole 64-vertex chunks.  A chunk weighs the larger
-// of MS_TALPHA per vertex and the in-degrees of its light (not heavy-listed)
+// of talpha per vertex and the in-degrees of its light (not heavy-listed)
 // vertices, and tile t takes the chunks whose running weight starts in
-// [t, t + 1) * MS_TWEIGHT: BLOCK vertices where in-degrees are low, fewer
+// [t, t + 1) * BLOCK * talpha: BLOCK vertices where in-degrees are low, fewer
 // where they are high (a graph ordered by degree puts those together), so no
-// tile walks many more in-edges than MS_TWEIGHT + 64 * MS_HEAVY.
+// tile walks many more in-edges than BLOCK * talpha + 64 * MS_HEAVY.
+// (talpha: MsTune::talpha, bfs_multi_config.tile_alpha.)
 // Split levels' push (k_ms_push_split): hub targets ORed in LDS (64 KB), workgroups
 // of 1024 threads, MS_PQ_GRID of them, staging rows merged MS_PQ_ROWS per thread.
 constexpr int MS_PQ_HUB = 8192;   // 64 KB of LDS
 constexpr int MS_PQ_BLOCK = 1024;
 constexpr int MS_PQ_GRID = 256;
 constexpr int MS_PQ_ROWS = 32;    // staging rows merged per k_ms_hub_or thread
-constexpr int MS_TALPHA = 64;
-constexpr long long MS_TWEIGHT = (long long)BLOCK * MS_TALPHA;
-// tiles for n vertices and any int32 edge count (a chunk weighs at most
-// 64 * MS_TALPHA plus its in-edges)
-constexpr long long ms_tile_cap(long long n) { return n / BLOCK + (1ll << 31) / MS_TWEIGHT + 4; }
+constexpr int MS_TALPHA_MIN = 16, MS_TALPHA_MAX = 1024;
+// tiles for n vertices and any int32 edge count at any talpha >= MS_TALPHA_MIN
+// (a chunk weighs at most 64 * talpha plus its in-edges)
+constexpr long long ms_tile_cap(long long n) {
+  return n / BLOCK + (1ll << 31) / ((long long)BLOCK * MS_TALPHA_MIN) + 4;
+}
+
+// The tunable choices of the level steps (bfs_multi_config, whose zero
+// fields take these defaults); none changes the depths.
+struct MsTune {
+  int wide_ratio = 8;   // non-split bottom-up: one vertex per thread while eu > wide_ratio * n
+  int split_vpt = 4;    // split levels: vertices per thread (1 or 4)
+  int cap0 = 32;        // first-round in-edges per pending vertex on dense-frontier levels
+  int talpha = 64;      // tile weight per vertex (see above)
+  int alpha = 7;        // bottom-up once frontier out-edges exceed eu / alpha (and n / 8)
+  int split_lout = 16;  // split when light frontier out-edges * split_lout < eu
+};
 // Chunk-to-owner tables of the heavy lists: entries for chunks below this
 // many; later chunks (graphs with far more edges than vertices) search hpre.
 constexpr long long ms_hq_cap(long long n) { return n * 2 + 1024 < (1ll << 22) ? n * 2 + 1024 : (1ll << 22); }
@@ -102,6 +114,7 @@ struct MsArgs {
   int rel;              // relative depth of this step's discoveries (k + 1 - base)
   u64 full;             // mask of the L lanes
   const int *rp, *ci, *cp, *cx;
+  int ncx;              // entries of cx (the in-edge count)
   const u64 *front;     // F_k words
   const u64 *fbits;     // any-lane bitmap of F_k: bit v%64 of word v/64
   u64 *next;            // F_{k+1} words
@@ -553,10 +566,10 @@ __device__ __forceinline__ void ms_quad(const int *cp, int v, int v1, int (&h)[4
 // Tile weight of the 64-vertex chunk starting at cw (see MS_TALPHA) from the
 // 16 lanes holding it: every lane of the group passes its `light`; the
 // result is valid in all 16.
-__device__ __forceinline__ long long ms_chunk_weight16(u64 light, int cw, int n) {
+__device__ __forceinline__ long long ms_chunk_weight16(u64 light, int cw, int n, int talpha) {
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) light += __shfl_xor(light, o);
-  const long long floor_w = (long long)min(n - cw, WAVE) * MS_TALPHA;
+  const long long floor_w = (long long)min(n - cw, WAVE) * talpha;
   return max(floor_w, (long long)light);
 }
 
@@ -584,7 +597,7 @@ __device__ __forceinline__ long long block_excl_scan_ll(long long x, long long *
 // Per MS_HB vertices: heavy vertices, their chunks and (bwt given) the tile
 // weight of the 64-vertex chunks.
 __global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, int *bcnt, int *bchk,
-                                                          long long *bwt) {
+                                                          long long *bwt, int talpha) {
   __shared__ int s_w[BLOCK / WAVE];
   __shared__ long long s_wl[BLOCK / WAVE];
   const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
@@ -601,7 +614,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, 
   long long wt = 0;
   if (bwt) {  // uniform
     const int cw = v0 + WAVE * (int)(threadIdx.x / 16);
-    const long long w = ms_chunk_weight16(light, cw, n);
+    const long long w = ms_chunk_weight16(light, cw, n, talpha);
     if ((threadIdx.x & 15) == 0 && cw < v1) wt = w;
   }
   int tc, tk;
@@ -617,13 +630,13 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_count(const int *cp, int n, 
 }
 
 // In place: bcnt/bchk (and bwt) become exclusive offsets; tot = {heavy
-// vertices, chunks}, *tiles = bottom-up tiles (total weight / MS_TWEIGHT + 1).
+// vertices, chunks}, *tiles = bottom-up tiles (total weight / (BLOCK * talpha) + 1).
 // One workgroup, MS_SCAN_CH entries at a time staged in LDS (coalesced loads
 // and stores): each thread sums a contiguous segment, one block scan per array
 // gives the segments' offsets, each thread rewrites its segment.
 constexpr int MS_SCAN_CH = 4096;
 __global__ __launch_bounds__(BLOCK) void k_ms_heavy_scan(int nb, int *bcnt, int *bchk, int *tot, long long *bwt,
-                                                         int *tiles) {
+                                                         int *tiles, int talpha) {
   __shared__ int s_c[MS_SCAN_CH], s_k[MS_SCAN_CH];
   __shared__ long long s_x[MS_SCAN_CH];
   __shared__ int s_w[BLOCK / WAVE];
@@ -697,7 +710,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_scan(int nb, int *bcnt, int 
   if (threadIdx.x == 0) {
     tot[0] = rc;
     tot[1] = rk;
-    if (bwt) *tiles = (int)(rw / MS_TWEIGHT) + 1;
+    if (bwt) *tiles = (int)(rw / ((long long)BLOCK * talpha)) + 1;
   }
 }
 static_assert(MS_SCAN_CH % BLOCK == 0, "whole segments");
@@ -705,12 +718,12 @@ static_assert(MS_SCAN_CH % BLOCK == 0, "whole segments");
 // Also clears accb of every heavy vertex (the only entries the pull uses)
 // when accb is given.
 // With bwt: chunk c starting at running weight key writes tstart[t] = its end
-// for each tile t whose first weight t * MS_TWEIGHT lies in (key, key + w_c]
+// for each tile t whose first weight t * BLOCK * talpha lies in (key, key + w_c]
 // (tiles inside one chunk's span are empty); tstart[0] = 0, tstart[tiles] = n.
 __global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, const int *bcnt, const int *bchk,
                                                           int *hv, int *hpre, int *hq, int hqcap, u64 *accb,
                                                           const int *tot, const long long *bwt, int *tstart,
-                                                          const int *tiles) {
+                                                          const int *tiles, int talpha) {
   __shared__ int s_w[BLOCK / WAVE];
   __shared__ long long s_wl[BLOCK / WAVE];
   const int v0 = blockIdx.x * MS_HB, v1 = min(v0 + MS_HB, n);
@@ -739,13 +752,14 @@ __global__ __launch_bounds__(BLOCK) void k_ms_heavy_write(const int *cp, int n, 
     }
   if (bwt) {  // uniform
     const int cw = v0 + WAVE * (int)(threadIdx.x / 16);
-    const long long w = ms_chunk_weight16(light, cw, n);
+    const long long w = ms_chunk_weight16(light, cw, n, talpha);
     const bool lead = (threadIdx.x & 15) == 0 && cw < v1;
+    const long long tw_all = (long long)BLOCK * talpha;
     long long tw;
     const long long key = bwt[blockIdx.x] + block_excl_scan_ll(lead ? w : 0, &tw, s_wl);
     if (lead) {
       const int e = min(cw + WAVE, n), last = *tiles - 1;
-      for (long long t = key / MS_TWEIGHT + 1; t <= (key + w) / MS_TWEIGHT && t <= last; ++t) tstart[t] = e;
+      for (long long t = key / tw_all + 1; t <= (key + w) / tw_all && t <= last; ++t) tstart[t] = e;
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -987,16 +1001,22 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       }
       if (SPLIT && (acc[j] & need[j]) == need[j]) continue;  // covered by the push
       int u[MS_HEAD];
-      if (d[j] >= MS_HEAD) {  // a whole head inside the list: 16-byte loads
+      if (b[j] + MS_HEAD <= a.ncx) {  // the head window lies inside the column array: 16-byte loads
+        // (only the pieces that hold list entries); a short list's window runs
+        // into the next lists, whose entries are masked off
         const I4u *p = reinterpret_cast<const I4u *>(a.cx + b[j]);
 #pragma unroll
         for (int q = 0; q < MS_HEAD / 4; ++q) {
-          const I4u w = p[q];
+          I4u w = {-1, -1, -1, -1};
+          if (4 * q < d[j]) w = p[q];
           u[4 * q] = w.x;
           u[4 * q + 1] = w.y;
           u[4 * q + 2] = w.z;
           u[4 * q + 3] = w.w;
         }
+#pragma unroll
+        for (int i = 0; i < MS_HEAD; ++i)
+          if (i >= d[j]) u[i] = -1;
       } else {
 #pragma unroll
         for (int i = 0; i < MS_HEAD; ++i) u[i] = i < d[j] ? a.cx[b[j] + i] : -1;
@@ -1526,6 +1546,79 @@ static void launch_ms_out(const MsArgs &a, int flush, hipStream_t s) {
 }
 
 
+// ------------------------------------------------------------ tuning
+// Configurations bfs_multi_autotune found, per graph (array addresses, sizes
+// and the degree-order flag); bfs_multi uses one when the caller passes none.
+// Only the time depends on it, so an entry left from a freed graph whose
+// addresses are reused costs speed, never correctness.
+struct MsTuneKey {
+  const void *rp, *ci, *cp, *cx;
+  int n, nnz, hub;
+  bool operator==(const MsTuneKey &o) const {
+    return rp == o.rp && ci == o.ci && cp == o.cp && cx == o.cx && n == o.n && nnz == o.nnz && hub == o.hub;
+  }
+};
+static std::mutex g_tune_mu;
+static std::vector<std::pair<MsTuneKey, MsTune>> g_tuned;  // most recent last, at most 64
+
+static MsTuneKey ms_tune_key(const bfs_graph *g, int flags) {
+  return MsTuneKey{g->row_ptr, g->col_idx, g->csc_ptr, g->csc_idx, g->n, g->nnz, (flags & BFS_F_HUB_ORDER) ? 1 : 0};
+}
+
+static int ms_tune_from(const bfs_multi_config &c, MsTune *t) {
+  MsTune d;
+  if (c.wide_ratio < 0 || (c.split_vpt != 0 && c.split_vpt != 1 && c.split_vpt != 4) || c.cap0 < 0 ||
+      (c.tile_alpha != 0 && (c.tile_alpha < MS_TALPHA_MIN || c.tile_alpha > MS_TALPHA_MAX)) || c.alpha < 0 ||
+      c.split_lout < 0) {
+    set_error("bfs_multi_config: wide_ratio, cap0, alpha and split_lout must be >= 0, split_vpt 0, 1 or 4, "
+              "tile_alpha 0 or in [%d, %d]",
+              MS_TALPHA_MIN, MS_TALPHA_MAX);
+    return BFS_EINVAL;
+  }
+  t->wide_ratio = c.wide_ratio ? c.wide_ratio : d.wide_ratio;
+  t->split_vpt = c.split_vpt ? c.split_vpt : d.split_vpt;
+  t->cap0 = c.cap0 ? c.cap0 : d.cap0;
+  t->talpha = c.tile_alpha ? c.tile_alpha : d.talpha;
+  t->alpha = c.alpha ? c.alpha : d.alpha;
+  t->split_lout = c.split_lout ? c.split_lout : d.split_lout;
+  return BFS_OK;
+}
+
+static bfs_multi_config ms_config_of(const MsTune &t) {
+  bfs_multi_config c;
+  c.wide_ratio = t.wide_ratio;
+  c.split_vpt = t.split_vpt;
+  c.cap0 = t.cap0;
+  c.tile_alpha = t.talpha;
+  c.alpha = t.alpha;
+  c.split_lout = t.split_lout;
+  return c;
+}
+
+// The configuration of one call: the caller's, else the stored one for the
+// graph, else the defaults.
+static int ms_resolve_tune(const bfs_graph *g, const bfs_options *opt, MsTune *t) {
+  if (opt && opt->multi_config) return ms_tune_from(*opt->multi_config, t);
+  *t = MsTune();
+  const MsTuneKey key = ms_tune_key(g, opt ? opt->flags : 0);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto &e : g_tuned)
+    if (e.first == key) *t = e.second;
+  return BFS_OK;
+}
+
+static void ms_store_tune(const bfs_graph *g, int flags, const MsTune &t) {
+  const MsTuneKey key = ms_tune_key(g, flags);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (size_t i = 0; i < g_tuned.size(); ++i)
+    if (g_tuned[i].first == key) {
+      g_tuned.erase(g_tuned.begin() + (long)i);
+      break;
+    }
+  if (g_tuned.size() >= 64) g_tuned.erase(g_tuned.begin());
+  g_tuned.push_back({key, t});
+}
+
 }  // namespace bfs
 
 using namespace bfs;
@@ -1560,6 +1653,9 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     rc = cached_workspace(need, &wsp);
     if (rc) return rc;
   }
+  MsTune tune;
+  rc = ms_resolve_tune(g, opt, &tune);
+  if (rc) return rc;
   const MsCarve W = ms_carve(reinterpret_cast<uintptr_t>(wsp), n);
   u64 *const *fr = W.fr;
   MsCtr *sh = W.sh;
@@ -1576,21 +1672,23 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
   const int *htot_host = post_host;
   const int *deg_host = post_host + 64;
   // with the bottom-up tiles (their count in htot[4])
-  hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.bwt);
+  hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.bwt,
+                     tune.talpha);
   hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev, W.bwt,
-                     htot_dev + 4);
+                     htot_dev + 4, tune.talpha);
   const int hqcap = (int)ms_hq_cap(n);
   hipLaunchKernelGGL(k_ms_heavy_write, dim3(nbh), dim3(BLOCK), 0, s, g->csc_ptr, n, W.bcnt, W.bchk, W.hv, W.hpre,
-                     W.hq, hqcap, W.accb, htot_dev, (const long long *)W.bwt, W.tstart, (const int *)(htot_dev + 4));
+                     W.hq, hqcap, W.accb, htot_dev, (const long long *)W.bwt, W.tstart, (const int *)(htot_dev + 4),
+                     tune.talpha);
   // the same over out-degrees for the top-down step (a symmetric graph passes one array twice)
   if (g->row_ptr != g->csc_ptr) {
     hipLaunchKernelGGL(k_ms_heavy_count, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk,
-                       (long long *)nullptr);
+                       (long long *)nullptr, tune.talpha);
     hipLaunchKernelGGL(k_ms_heavy_scan, dim3(1), dim3(BLOCK), 0, s, nbh, W.bcnt, W.bchk, htot_dev + 2,
-                       (long long *)nullptr, (int *)nullptr);
+                       (long long *)nullptr, (int *)nullptr, tune.talpha);
     hipLaunchKernelGGL(k_ms_heavy_write, dim3(nbh), dim3(BLOCK), 0, s, g->row_ptr, n, W.bcnt, W.bchk, W.ov, W.opre,
                        W.oq, hqcap, (u64 *)nullptr, htot_dev + 2, (const long long *)nullptr, (int *)nullptr,
-                       (const int *)nullptr);
+                       (const int *)nullptr, tune.talpha);
   }
   BFS_HIP(hipGetLastError());
   long long reached = 0, comp = 0;
@@ -1630,6 +1728,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.ci = g->col_idx;
     a.cp = g->csc_ptr;
     a.cx = g->csc_idx;
+    a.ncx = g->nnz;
     a.vis = W.vis;
     a.planes = W.planes;
     a.flushed = W.flushed;
@@ -1732,10 +1831,10 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         // only once every lane a vertex misses is found, so it costs close to
         // all in-edges of the vertices still missing a lane (eu) plus a pass
         // over all n vertices; top-down costs the frontier's out-edges (ef),
-        // one atomic each.  Bottom-up when ef > eu / MS_ALPHA and ef > n / 8;
+        // one atomic each.  Bottom-up when ef > eu / alpha and ef > n / 8;
         // back to top-down under Beamer's beta test.
         if (msdir == 0) {
-          if (ef * MS_ALPHA > eu && ef * 8 > (long long)n) msdir = 1;
+          if (ef * tune.alpha > eu && ef * 8 > (long long)n) msdir = 1;
         } else if (nf * HeuristicState::kBeta < (long long)n && prev_nf >= 0 && nf < prev_nf) {
           msdir = 0;
         }
@@ -1777,11 +1876,12 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       // (no early exits expected, so the plain step reads every in-edge of the
       // vertices missing a lane) and the light frontier vertices' out-edges,
       // one atomic each, cost less than the in-edges skipped.
-      const bool split = dir == 1 && a.hub_t > 0 && (hub_req > 0 || (ef * 4 <= eu && lout * 16 < eu));
+      const bool split =
+          dir == 1 && a.hub_t > 0 && (hub_req > 0 || (ef * 4 <= eu && lout * (long long)tune.split_lout < eu));
       if (dir == 1) {
         // early exits pay for extra rounds only when the frontier carries a
         // large share of the remaining in-edges
-        a.cap0 = ef * 4 > eu ? MS_CAP0 : (1 << 30);
+        a.cap0 = ef * 4 > eu ? tune.cap0 : (1 << 30);
         if (split) {
           // the light sources push first; the tile kernel clears the dead buffer
           MsArgs ap = a;
@@ -1822,10 +1922,12 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           }
         }
         // one vertex per thread while many in-edges remain to be scanned (more
-        // workgroups in flight); four when few do (fixed costs amortised)
+        // workgroups in flight); four when few do, and on split levels, which
+        // read only the hubs' part of each list (fixed costs amortised, and
+        // four vertices' loads in flight per thread)
         if (mtiming) BFS_HIP(hipEventRecord(E[1], s));
         const bool rounds = a.cap0 < (1 << 30);  // dense frontier: per-position walk
-        const bool wide = eu > 2 * (long long)n;
+        const bool wide = split ? tune.split_vpt == 1 : eu > (long long)tune.wide_ratio * n;
         const dim3 gt(wide ? (sum ? std::min(grid_t1, MS_SUM_GRID) : grid_t1)
                            : (sum ? std::min(grid_t4, MS_SUM_GRID) : grid_t4));
         if (sum) {
@@ -1954,5 +2056,78 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     st->elapsed_ms = ms;
     st->host_syncs = syncs;
   }
+  return BFS_OK;
+}
+
+extern "C" int bfs_multi_autotune(const bfs_graph *g, const int32_t *sources, int32_t k, int32_t *levels,
+                                  const bfs_options *opt, bfs_multi_config *best, float *ms_best, void *stream) {
+  if (!best) {
+    set_error("bfs_multi_autotune: best is NULL");
+    return BFS_EINVAL;
+  }
+  bfs_options o;
+  if (opt) {
+    o = *opt;
+  } else {
+    memset(&o, 0, sizeof(o));
+    o.variant = BFS_AUTO_HEURISTIC;
+  }
+  o.flags &= ~(BFS_F_LEVEL_STATS | BFS_F_LEVEL_TIMING | BFS_F_MAIN_TIMING);
+  MsTune cur;
+  if (opt && opt->multi_config) {
+    const int rc = ms_tune_from(*opt->multi_config, &cur);
+    if (rc) return rc;
+  }
+  // device time of one configuration: best of two runs (the first also
+  // warms the caches and the library's workspace)
+  auto time_of = [&](const MsTune &t, float *ms) -> int {
+    const bfs_multi_config c = ms_config_of(t);
+    o.multi_config = &c;
+    float bestv = 0.f;
+    for (int r = 0; r < 2; ++r) {
+      bfs_stats st;
+      memset(&st, 0, sizeof(st));
+      const int rc = bfs_multi(g, sources, k, levels, &o, &st, stream);
+      if (rc) return rc;
+      if (r == 0 || st.elapsed_ms < bestv) bestv = st.elapsed_ms;
+    }
+    *ms = bestv;
+    return BFS_OK;
+  };
+  float cur_ms = 0.f;
+  int rc = time_of(cur, &cur_ms);
+  if (rc) return rc;
+  // one field at a time, each over its candidates, keeping the fastest
+  static const int wide_c[] = {2, 4, 8, 16, 64, 1 << 20};
+  static const int vpt_c[] = {1, 4};
+  static const int cap_c[] = {16, 32, 64, 128};
+  static const int talpha_c[] = {32, 64, 128};
+  static const int alpha_c[] = {4, 7, 14};
+  static const int lout_c[] = {4, 16, 64};
+  struct Field {
+    int MsTune::*f;
+    const int *c;
+    int nc;
+  };
+  const Field fields[] = {{&MsTune::wide_ratio, wide_c, 6}, {&MsTune::split_vpt, vpt_c, 2},
+                          {&MsTune::cap0, cap_c, 4},        {&MsTune::talpha, talpha_c, 3},
+                          {&MsTune::alpha, alpha_c, 3},     {&MsTune::split_lout, lout_c, 3}};
+  for (const Field &fd : fields) {
+    for (int i = 0; i < fd.nc; ++i) {
+      if (cur.*(fd.f) == fd.c[i]) continue;
+      MsTune t = cur;
+      t.*(fd.f) = fd.c[i];
+      float ms = 0.f;
+      rc = time_of(t, &ms);
+      if (rc) return rc;
+      if (ms < cur_ms) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+  }
+  ms_store_tune(g, o.flags, cur);
+  *best = ms_config_of(cur);
+  if (ms_best) *ms_best = cur_ms;
   return BFS_OK;
 }
