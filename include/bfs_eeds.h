@@ -159,10 +159,10 @@ typedef struct bfs_graph {
 /* Tunable choices of bfs_multi's level steps (bfs_options.multi_config).  A
  * zero field takes the default in brackets.  No choice changes the depths,
  * only the time; bfs_multi_autotune picks them per graph.
- *   wide_ratio  non-split bottom-up levels run one vertex per thread while
- *               the in-edges of the vertices still missing a lane exceed
- *               wide_ratio * n, four per thread otherwise [8]
- *   split_vpt   vertices per thread on split bottom-up levels, 1 or 4 [4]
+ *   wide_ratio  non-split bottom-up levels run wide_vpt vertices per thread
+ *               while the in-edges of the vertices still missing a lane
+ *               exceed wide_ratio * n, narrow_vpt otherwise [8]
+ *   split_vpt   vertices per thread on split bottom-up levels, 1, 2 or 4 [4]
  *   cap0        in-edges per pending vertex in the first round of a
  *               bottom-up level whose frontier holds more than a quarter of
  *               those in-edges (rounds grow 4x; sparser frontiers take every
@@ -175,7 +175,9 @@ typedef struct bfs_graph {
  *               (and n/8) [7]
  *   split_lout  with BFS_F_HUB_ORDER: a bottom-up level is split when the
  *               frontier holds at most a quarter of those in-edges and its
- *               light vertices' out-edges times split_lout are fewer [16] */
+ *               light vertices' out-edges times split_lout are fewer [16]
+ *   wide_vpt    see wide_ratio: 1, 2 or 4 [1]
+ *   narrow_vpt  see wide_ratio: 1, 2 or 4 [4] */
 typedef struct bfs_multi_config {
   int32_t wide_ratio;
   int32_t split_vpt;
@@ -183,6 +185,8 @@ typedef struct bfs_multi_config {
   int32_t tile_alpha;
   int32_t alpha;
   int32_t split_lout;
+  int32_t wide_vpt;
+  int32_t narrow_vpt;
 } bfs_multi_config;
 
 typedef struct bfs_options {
@@ -361,7 +365,7 @@ int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_
  * The result is returned in *best (and the time in *ms_best, may be NULL)
  * and stored for the graph, so later bfs_multi calls on it with
  * multi_config = NULL use it.  levels: device [k][n] scratch (holds the last
- * run's depths on return).  Takes some 20 configurations x 2 runs. */
+ * run's depths on return).  Takes some 25 configurations x 2 runs. */
 int bfs_multi_autotune(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_t *levels,
                        const bfs_options *opt, bfs_multi_config *best, float *ms_best, void *stream);
 

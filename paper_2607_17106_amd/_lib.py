@@ -68,7 +68,7 @@ class BfsGraph(ctypes.Structure):
 
 class BfsMultiConfig(ctypes.Structure):
     _fields_ = [("wide_ratio", c_int32), ("split_vpt", c_int32), ("cap0", c_int32), ("tile_alpha", c_int32),
-                ("alpha", c_int32), ("split_lout", c_int32)]
+                ("alpha", c_int32), ("split_lout", c_int32), ("wide_vpt", c_int32), ("narrow_vpt", c_int32)]
 
 
 class BfsOptions(ctypes.Structure):

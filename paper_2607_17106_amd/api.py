@@ -308,10 +308,12 @@ class MultiConfig:
     tile_alpha: int = 0
     alpha: int = 0
     split_lout: int = 0
+    wide_vpt: int = 0
+    narrow_vpt: int = 0
 
     def c(self):
         return L.BfsMultiConfig(self.wide_ratio, self.split_vpt, self.cap0, self.tile_alpha, self.alpha,
-                                self.split_lout)
+                                self.split_lout, self.wide_vpt, self.narrow_vpt)
 
 
 def _multi_options(g, variant, flags, workspace, vertex_map, hub_split, config):
@@ -373,7 +375,7 @@ def bfs_multi_autotune(g: DeviceGraph, sources, variant: int = L.AUTO_HEURISTIC,
     L.check(rc, "bfs_multi_autotune")
     del keep
     return MultiConfig(best.wide_ratio, best.split_vpt, best.cap0, best.tile_alpha, best.alpha,
-                       best.split_lout), float(ms.value)
+                       best.split_lout, best.wide_vpt, best.narrow_vpt), float(ms.value)
 
 
 @dataclass

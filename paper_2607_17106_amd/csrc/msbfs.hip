@@ -49,7 +49,6 @@ constexpr int MS_EPT = 8;          // in-edges per thread per tile iteration (a 
 struct __attribute__((packed, aligned(4))) I4u {  // four ints at any 4-byte-aligned address
   int x, y, z, w;
 };
-constexpr int MS_VPT_SPARSE = 4;   // vertices per thread in the bottom-up tile when few in-edges remain
 constexpr int MS_HB = 1024;        // vertices per workgroup in the heavy-list build
 constexpr int MS_SUM_WORDS = 8192; // frontier summary: 2^18 bits = 32 KB of LDS
 constexpr int MS_SUM_GRID = 1024;  // persistent workgroups of the summary-filtered bottom-up kernels
@@ -76,12 +75,14 @@ constexpr long long ms_tile_cap(long long n) {
 // The tunable choices of the level steps (bfs_multi_config, whose zero
 // fields take these defaults); none changes the depths.
 struct MsTune {
-  int wide_ratio = 8;   // non-split bottom-up: one vertex per thread while eu > wide_ratio * n
-  int split_vpt = 4;    // split levels: vertices per thread (1 or 4)
+  int wide_ratio = 8;   // non-split bottom-up: wide_vpt vertices per thread while eu > wide_ratio * n
+  int split_vpt = 4;    // split levels: vertices per thread (1, 2 or 4)
   int cap0 = 32;        // first-round in-edges per pending vertex on dense-frontier levels
   int talpha = 64;      // tile weight per vertex (see above)
   int alpha = 7;        // bottom-up once frontier out-edges exceed eu / alpha (and n / 8)
   int split_lout = 16;  // split when light frontier out-edges * split_lout < eu
+  int wide_vpt = 1;     // vertices per thread on non-split levels with eu > wide_ratio * n
+  int narrow_vpt = 4;   // and on the others
 };
 // Chunk-to-owner tables of the heavy lists: entries for chunks below this
 // many; later chunks (graphs with far more edges than vertices) search hpre.
@@ -1546,6 +1547,24 @@ static void launch_ms_out(const MsArgs &a, int flush, hipStream_t s) {
 }
 
 
+// One bottom-up tile launch: VPT vertices per thread; sum: the frontier is
+// tested against its LDS summary first (lds bytes); split: a split level;
+// rounds: a dense frontier (capped rounds, gathers without the bitmap probe,
+// one owner search per position); otherwise one round of consecutive walks.
+template <int VPT>
+static void launch_tile(const MsArgs &a, bool sum, bool split, bool rounds, dim3 g, size_t lds, hipStream_t s) {
+  if (sum)
+    hipLaunchKernelGGL((k_ms_pull_tile<VPT, true, true>), g, dim3(BLOCK), lds, s, a);
+  else if (split && rounds)
+    hipLaunchKernelGGL((k_ms_pull_tile<VPT, false, false, true, false>), g, dim3(BLOCK), 0, s, a);
+  else if (split)
+    hipLaunchKernelGGL((k_ms_pull_tile<VPT, false, true, true, false>), g, dim3(BLOCK), 0, s, a);
+  else if (rounds)
+    hipLaunchKernelGGL((k_ms_pull_tile<VPT, false, false, false, false>), g, dim3(BLOCK), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_ms_pull_tile<VPT, false, true>), g, dim3(BLOCK), 0, s, a);
+}
+
 // ------------------------------------------------------------ tuning
 // Configurations bfs_multi_autotune found, per graph (array addresses, sizes
 // and the degree-order flag); bfs_multi uses one when the caller passes none.
@@ -1567,11 +1586,12 @@ static MsTuneKey ms_tune_key(const bfs_graph *g, int flags) {
 
 static int ms_tune_from(const bfs_multi_config &c, MsTune *t) {
   MsTune d;
-  if (c.wide_ratio < 0 || (c.split_vpt != 0 && c.split_vpt != 1 && c.split_vpt != 4) || c.cap0 < 0 ||
+  const auto vpt_ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
+  if (c.wide_ratio < 0 || !vpt_ok(c.split_vpt) || !vpt_ok(c.wide_vpt) || !vpt_ok(c.narrow_vpt) || c.cap0 < 0 ||
       (c.tile_alpha != 0 && (c.tile_alpha < MS_TALPHA_MIN || c.tile_alpha > MS_TALPHA_MAX)) || c.alpha < 0 ||
       c.split_lout < 0) {
-    set_error("bfs_multi_config: wide_ratio, cap0, alpha and split_lout must be >= 0, split_vpt 0, 1 or 4, "
-              "tile_alpha 0 or in [%d, %d]",
+    set_error("bfs_multi_config: wide_ratio, cap0, alpha and split_lout must be >= 0, split_vpt, wide_vpt and "
+              "narrow_vpt 0, 1, 2 or 4, tile_alpha 0 or in [%d, %d]",
               MS_TALPHA_MIN, MS_TALPHA_MAX);
     return BFS_EINVAL;
   }
@@ -1581,6 +1601,8 @@ static int ms_tune_from(const bfs_multi_config &c, MsTune *t) {
   t->talpha = c.tile_alpha ? c.tile_alpha : d.talpha;
   t->alpha = c.alpha ? c.alpha : d.alpha;
   t->split_lout = c.split_lout ? c.split_lout : d.split_lout;
+  t->wide_vpt = c.wide_vpt ? c.wide_vpt : d.wide_vpt;
+  t->narrow_vpt = c.narrow_vpt ? c.narrow_vpt : d.narrow_vpt;
   return BFS_OK;
 }
 
@@ -1592,6 +1614,8 @@ static bfs_multi_config ms_config_of(const MsTune &t) {
   c.tile_alpha = t.talpha;
   c.alpha = t.alpha;
   c.split_lout = t.split_lout;
+  c.wide_vpt = t.wide_vpt;
+  c.narrow_vpt = t.narrow_vpt;
   return c;
 }
 
@@ -1775,7 +1799,6 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.oq = sym ? W.hq : W.oq;
     a.hqcap = hqcap;
     a.otot = sym ? htot_dev : htot_dev + 2;
-    int grid_t1 = 0, grid_t4 = 0;
     long long nf = 0, ef = 0, src_comp = 0;
     // What the seed kernel posted: the heavy-list and tile totals, and the
     // count and out-edges of F_0 for the direction rule.
@@ -1783,8 +1806,6 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
       a.hcount = htot_host[0];
       a.hchunks = htot_host[1];
       a.ntiles = htot_host[4];
-      grid_t1 = std::min(65536, a.ntiles);
-      grid_t4 = std::min(65536, (a.ntiles + MS_VPT_SPARSE - 1) / MS_VPT_SPARSE);
       a.ocount = sym ? a.hcount : htot_host[2];
       a.ochunks = sym ? a.hchunks : htot_host[3];
       a.hub_t = hub_req > 0 ? std::min(hub_req, n) : hub_auto ? a.ocount : 0;
@@ -1927,33 +1948,13 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
         // four vertices' loads in flight per thread)
         if (mtiming) BFS_HIP(hipEventRecord(E[1], s));
         const bool rounds = a.cap0 < (1 << 30);  // dense frontier: per-position walk
-        const bool wide = split ? tune.split_vpt == 1 : eu > (long long)tune.wide_ratio * n;
-        const dim3 gt(wide ? (sum ? std::min(grid_t1, MS_SUM_GRID) : grid_t1)
-                           : (sum ? std::min(grid_t4, MS_SUM_GRID) : grid_t4));
-        if (sum) {
-          if (wide)
-            hipLaunchKernelGGL((k_ms_pull_tile<1, true, true>), gt, dim3(BLOCK), lds, s, a);
-          else
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, true, true>), gt, dim3(BLOCK), lds, s, a);
-        } else if (split) {
-          if (wide && rounds)
-            hipLaunchKernelGGL((k_ms_pull_tile<1, false, false, true, false>), gt, dim3(BLOCK), 0, s, a);
-          else if (wide)
-            hipLaunchKernelGGL((k_ms_pull_tile<1, false, true, true, false>), gt, dim3(BLOCK), 0, s, a);
-          else if (rounds)
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false, true, false>), gt, dim3(BLOCK), 0, s, a);
-          else
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true, true, false>), gt, dim3(BLOCK), 0, s, a);
-        } else if (wide) {
-          if (rounds)  // dense frontier: gathers without the bitmap probe
-            hipLaunchKernelGGL((k_ms_pull_tile<1, false, false, false, false>), gt, dim3(BLOCK), 0, s, a);
-          else
-            hipLaunchKernelGGL((k_ms_pull_tile<1, false, true>), gt, dim3(BLOCK), 0, s, a);
-        } else {
-          if (rounds)
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, false, false, false>), gt, dim3(BLOCK), 0, s, a);
-          else
-            hipLaunchKernelGGL((k_ms_pull_tile<MS_VPT_SPARSE, false, true>), gt, dim3(BLOCK), 0, s, a);
+        const int vpt = split ? tune.split_vpt : eu > (long long)tune.wide_ratio * n ? tune.wide_vpt : tune.narrow_vpt;
+        const int gtiles = std::min(65536, (a.ntiles + vpt - 1) / vpt);
+        const dim3 gt(sum ? std::min(gtiles, MS_SUM_GRID) : gtiles);
+        switch (vpt) {
+          case 1: launch_tile<1>(a, sum, split, rounds, gt, lds, s); break;
+          case 2: launch_tile<2>(a, sum, split, rounds, gt, lds, s); break;
+          default: launch_tile<4>(a, sum, split, rounds, gt, lds, s); break;
         }
         if (mtiming) BFS_HIP(hipEventRecord(E[2], s));
         a.split_t = 0;
@@ -2099,7 +2100,7 @@ extern "C" int bfs_multi_autotune(const bfs_graph *g, const int32_t *sources, in
   if (rc) return rc;
   // one field at a time, each over its candidates, keeping the fastest
   static const int wide_c[] = {2, 4, 8, 16, 64, 1 << 20};
-  static const int vpt_c[] = {1, 4};
+  static const int vpt_c[] = {1, 2, 4};
   static const int cap_c[] = {16, 32, 64, 128};
   static const int talpha_c[] = {32, 64, 128};
   static const int alpha_c[] = {4, 7, 14};
@@ -2109,7 +2110,8 @@ extern "C" int bfs_multi_autotune(const bfs_graph *g, const int32_t *sources, in
     const int *c;
     int nc;
   };
-  const Field fields[] = {{&MsTune::wide_ratio, wide_c, 6}, {&MsTune::split_vpt, vpt_c, 2},
+  const Field fields[] = {{&MsTune::wide_ratio, wide_c, 6}, {&MsTune::wide_vpt, vpt_c, 3},
+                          {&MsTune::narrow_vpt, vpt_c, 3},  {&MsTune::split_vpt, vpt_c, 3},
                           {&MsTune::cap0, cap_c, 4},        {&MsTune::talpha, talpha_c, 3},
                           {&MsTune::alpha, alpha_c, 3},     {&MsTune::split_lout, lout_c, 3}};
   for (const Field &fd : fields) {

@@ -28,6 +28,9 @@ CONFIGS = [
     B.MultiConfig(alpha=1000),                    # bottom-up as soon as the frontier holds n/8 out-edges
     B.MultiConfig(split_lout=1, wide_ratio=2),
     B.MultiConfig(split_lout=1 << 20, split_vpt=1, cap0=7, tile_alpha=17),
+    B.MultiConfig(wide_vpt=2, narrow_vpt=2, split_vpt=2),
+    B.MultiConfig(wide_ratio=1, wide_vpt=4, narrow_vpt=1),
+    B.MultiConfig(wide_ratio=1 << 20, narrow_vpt=1, split_vpt=2, cap0=3),
 ]
 
 
@@ -76,7 +79,7 @@ def test_autotune_stores_a_config_the_next_call_uses():
     cfg, ms = B.bfs_multi_autotune(rg, srcs, vertex_map=new_of_old)
     assert ms > 0
     assert cfg.wide_ratio in (2, 4, 8, 16, 64, 1 << 20)
-    assert cfg.split_vpt in (1, 4)
+    assert cfg.split_vpt in (1, 2, 4) and cfg.wide_vpt in (1, 2, 4) and cfg.narrow_vpt in (1, 2, 4)
     assert cfg.cap0 in (16, 32, 64, 128)
     assert cfg.tile_alpha in (32, 64, 128)
     assert cfg.alpha in (4, 7, 14)
@@ -90,7 +93,8 @@ def test_autotune_stores_a_config_the_next_call_uses():
 def test_config_errors():
     g = gg.rmat(10, seed=3)
     dg = B.DeviceGraph.from_graph(g)
-    for bad in (B.MultiConfig(split_vpt=2), B.MultiConfig(tile_alpha=8), B.MultiConfig(tile_alpha=2048),
+    for bad in (B.MultiConfig(split_vpt=3), B.MultiConfig(wide_vpt=8), B.MultiConfig(narrow_vpt=-1),
+                B.MultiConfig(tile_alpha=8), B.MultiConfig(tile_alpha=2048),
                 B.MultiConfig(cap0=-1), B.MultiConfig(wide_ratio=-3), B.MultiConfig(alpha=-1),
                 B.MultiConfig(split_lout=-2)):
         with pytest.raises(B.BfsError) as e:
