@@ -314,7 +314,8 @@ __device__ __forceinline__ bool gated_off(const StepArgs &a) {
 
 // ---------------------------------------------------------------- launch
 // Launchers (defined in the .hip files).  All enqueue on `s`.
-hipError_t launch_reset(const StepArgs &a, int src, RingSlot *ring, hipStream_t s);
+// k_reset (clears the state and the ring) and, with f0, k_reset_f0 (F_0 = {src} in slot 0).
+hipError_t launch_reset(const StepArgs &a, int src, RingSlot *ring, hipStream_t s, bool f0 = true);
 // count < 0: sizes unknown on the host (device loop); fixed grids are used.
 hipError_t launch_step(int variant, const StepArgs &a, int count, long long edges, hipStream_t s);
 hipError_t launch_finish(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl, hipStream_t s);

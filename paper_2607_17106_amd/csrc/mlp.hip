@@ -35,32 +35,289 @@ __global__ __launch_bounds__(64) void k_select(SelDevice sd, RingSlot *ring, int
   }
 }
 
-// The per-level counter reduction (body_finish) followed, in the same
-// workgroup, by the choice for the next level (when `select`): one launch per
-// level instead of two.  With `host` (pinned host memory) the level's totals,
-// decision included, are also copied there, and then -- after a system-scope
-// fence -- `seq` is written to *host_seq for the host loop to poll.
+// The per-level counter reduction followed, in the same workgroup, by the
+// choice for the next level (when `select`): one launch per level instead of
+// two.  With `host` (pinned host memory) the level's totals, decision
+// included, are also copied there, and then -- after a system-scope fence --
+// `seq` is written to *host_seq for the host loop to poll.
+// The work is that of body_finish then body_select (the same values are
+// written: segment offsets, totals, log entry, loop control, selector state,
+// decision), arranged for latency, as this launch sits between two steps on
+// the host loop's critical path: every global load it needs (the shards, the
+// loop control, the selector state, and for the network this lane's weight
+// rows and its feature's normalisation) is issued at the start, the totals
+// and state then travel through registers and LDS instead of being written
+// and read back, and the host copy is written from registers.
 __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl,
                                                        SelDevice sd, RingSlot *ring, int n, int nnz, int select,
                                                        int use_net, LevelCtr *host, u64 *host_seq, u64 seq) {
-  __shared__ __align__(16) char smem[SM_FINISH + SM_SELECT];
+  (void)ring;  // slot is ring[k % RING]
+  __shared__ u64 s_red[5][NSH / WAVE];
+  __shared__ int s_w[NSH / WAVE];
+  __shared__ __align__(16) float s_net[NF + 3 * NH];
+  __shared__ u64 s_tot[4];      // count, edges, ld, ld2 of F_k
+  __shared__ long long s_u[2];  // nU, eU after F_k
+  __shared__ int s_hv;
+  const int t = threadIdx.x;
+  const bool net = select && use_net;
+  long long *st = reinterpret_cast<long long *>(sd.state);
+  // loads first
+  const LevelCtr c = slot->sh[t];
+  u32 ovf = 0;
+  u64 done = 0, reached = 0, comp = 0;
+  long long st0 = 0, st1 = 0, st2 = 0, st3 = 0;
+  if (t == 0) {
+    ovf = slot->sh[NSH].count;
+    done = ctl->done;
+    reached = ctl->reached;
+    comp = ctl->comp_edges;
+    if (select) {
+      st0 = st[0];
+      st1 = st[1];
+      st2 = st[2];
+      st3 = st[3];
+    }
+  }
+  NetRegs nr;
+  float nmean = 0.f, nstd = 1.f, nmin = 0.f, nmax = 0.f;
+  if (net && t < WAVE) {
+    load_net(sd, nr);
+    if (t < NF) {
+      nmean = sd.norm[t];
+      nstd = sd.norm[NF + t];
+      nmin = sd.norm[2 * NF + t];
+      nmax = sd.norm[3 * NF + t];
+    }
+  }
+  // counter reduction and queue segment offsets (body_finish)
+  const int cnt = (int)min(c.count, (u32)qcap);
+  const int w = t / WAVE;
+  const int incl = wave_incl_scan(cnt);
+  if (lane() == WAVE - 1) s_w[w] = incl;
+  const u64 v[5] = {c.edges, c.in_edges, c.ld, c.ld2, c.scanned};
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const u64 r = wave_sum_u64(v[j]);
+    if (lane() == 0) s_red[j][w] = r;
+  }
+  __syncthreads();
+  int off = 0, total = 0;
+  for (int i = 0; i < NSH / WAVE; ++i) {
+    off += (i < w) ? s_w[i] : 0;
+    total += s_w[i];
+  }
+  slot->seg[t] = off + incl - cnt;
+  LevelCtr o;  // thread 0: the totals of F_k
+  int hv = -1;
+  if (t == 0) {
+    u64 r[5] = {0, 0, 0, 0, 0};
+    for (int j = 0; j < 5; ++j)
+      for (int i = 0; i < NSH / WAVE; ++i) r[j] += s_red[j][i];
+    o.count = (u32)(total + (int)ovf);
+    o.nhub = 0;
+    o.edges = r[0];
+    o.in_edges = r[1];
+    o.ld = r[2];
+    o.ld2 = r[3];
+    o.scanned = r[4];
+    o.ntiles = 0;
+    o.total_e = 0;
+    o.decision = -1;
+    o.fallback = 0;
+    slot->seg[NSH] = total;
+    slot->seg[NSH + 1] = total + (int)ovf;
+    if (o.count == 0) {
+      ctl->done = 1;
+    } else if (!done) {
+      ctl->levels = (u64)k + 1;
+      ctl->reached = reached + o.count;
+      ctl->comp_edges = comp + o.edges;
+    }
+    if (select) {  // the unvisited totals after F_k and the direction rule (body_select)
+      const long long nF = o.count;
+      st0 -= nF;
+      st1 -= (long long)o.in_edges;
+      const long long eF = (long long)o.edges, eU = st1;
+      int dir = (int)st2;
+      if (dir == 0) {
+        if (eF * HeuristicState::kAlpha > eU) dir = 1;
+      } else {
+        const bool shrinking = st3 >= 0 && nF < st3;
+        if (nF * HeuristicState::kBeta < (long long)n && shrinking) dir = 0;
+      }
+      st[0] = st0;
+      st[1] = st1;
+      st[2] = dir;
+      st[3] = nF;
+      hv = dir ? sd.pull_v : sd.push_v;
+      s_u[0] = st0;
+      s_u[1] = st1;
+      s_hv = hv;
+      s_tot[0] = o.count;
+      s_tot[1] = o.edges;
+      s_tot[2] = o.ld;
+      s_tot[3] = o.ld2;
+    }
+  }
+  int dec = -1, fb = 0;
+  if (net) {
+    __syncthreads();  // uniform: the totals and state are in LDS
+    if (t < WAVE) {
+      hv = s_hv;
+      dec = hv;
+      // the level's raw features, one per lane; range check, then normalise
+      bool out_of_range = false;
+      float xn = 0.f;
+      if (lane() < NF) {
+        const float r = level_feature(lane(), (double)n, (double)nnz, (double)k, (double)s_tot[0],
+                                      (double)s_tot[1], (double)s_u[0], (double)s_u[1], (double)s_tot[2],
+                                      (double)s_tot[3], (double)sd.gld, (double)sd.gld2);
+        out_of_range = r < nmin || r > nmax;
+        xn = (r - nmean) / nstd;
+      }
+      const bool any_oor = __ballot(out_of_range) != 0ull;
+      float *s_x = s_net, *h0 = s_net + NF, *h1 = h0 + NH, *h2 = h1 + NH;
+      if (lane() < NF) s_x[lane()] = xn;
+      __builtin_amdgcn_wave_barrier();
+      const float logit = forward_row_regs(nr, s_x, h0, h1, h2);
+      int cls;
+      float conf;
+      argmax_conf(logit, &cls, &conf);
+      fb = any_oor || !(conf >= sd.min_conf);
+      dec = fb ? hv : sd.cls[cls];
+    }
+  } else if (select) {
+    dec = hv;  // thread 0: the direction rule's choice
+  }
+  if (t == 0) {
+    o.decision = select ? dec : -1;
+    o.fallback = select ? fb : 0;
+    slot->tot = o;
+    if (k < LOGCAP) {
+      LevelLog &L = log[k];
+      L.count = o.count;
+      L.variant = o.decision;
+      L.edges = o.edges;
+      L.in_edges = o.in_edges;
+      L.ld = o.ld;
+      L.ld2 = o.ld2;
+      L.scanned = o.scanned;
+      L.fallback = o.fallback;
+    }
+    if (host) {
+      *host = o;
+      __threadfence_system();
+      *reinterpret_cast<volatile u64 *>(host_seq) = seq;
+    }
+  }
+}
+
+// Level 0 of the host loop in one launch: F_0 = {src} into slot 0 (its
+// totals and queue segment offsets, as k_reset_f0 writes them), its log
+// entry and the loop control (as k_log_f0), the choice for level 0 when
+// `select` (the selector state initialised and the direction rule applied,
+// then the network, as body_select with init), and the totals posted to
+// host memory as k_finish_select does.  One wave; k_reset has cleared the
+// ring.
+__global__ __launch_bounds__(WAVE) void k_start_select(const int *rp, const int *cp, int src, RingSlot *slot0,
+                                                       LevelLog *log, LoopCtl *ctl, SelDevice sd, int n, int nnz,
+                                                       int select, int use_net, LevelCtr *host, u64 *host_seq,
+                                                       u64 seq) {
+  __shared__ __align__(16) float s_net[NF + 3 * NH];
+  const int l = lane();
   const bool net = select && use_net;
   NetRegs nr;
-  if (net && threadIdx.x < WAVE) load_net(sd, nr);  // its loads overlap the reduction's
-  body_finish(slot, qcap, k, log, ctl, smem);
-  __syncthreads();
-  __threadfence_block();
-  if (select && threadIdx.x < WAVE) {
-    if (net)
-      body_select<true>(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH, nr);
-    else
-      body_select(sd, ring, k, n, nnz, 0, use_net, log, smem + SM_FINISH);
+  float nmean = 0.f, nstd = 1.f, nmin = 0.f, nmax = 0.f;
+  if (net) {
+    load_net(sd, nr);
+    if (l < NF) {
+      nmean = sd.norm[l];
+      nstd = sd.norm[NF + l];
+      nmin = sd.norm[2 * NF + l];
+      nmax = sd.norm[3 * NF + l];
+    }
   }
-  if (threadIdx.x == 0 && host) {  // lane 0 wrote the decision above
-    *host = slot->tot;
-    __threadfence_system();
-    *host_seq = seq;
+  for (int i = l; i < NSH + 2; i += WAVE) slot0->seg[i] = (i == 0) ? 0 : 1;
+  const int d = rp[src + 1] - rp[src];
+  const int di = cp ? cp[src + 1] - cp[src] : d;
+  const int lg = ilog2p1(d);
+  LevelCtr o;
+  o.count = 1;
+  o.nhub = 0;
+  o.edges = (u64)d;
+  o.in_edges = (u64)di;
+  o.ld = (u64)lg;
+  o.ld2 = (u64)(lg * lg);
+  o.scanned = 0;
+  o.ntiles = 0;
+  o.total_e = 0;
+  int dec = -1, fb = 0;
+  if (select) {
+    // selector state after F_0 = {src}: nU = n - 1, eU = nnz - in-degree,
+    // and the direction rule from top-down with no previous frontier
+    const long long nU = (long long)n - 1, eU = (long long)nnz - di;
+    const int dir = (long long)d * HeuristicState::kAlpha > eU ? 1 : 0;
+    if (l == 0) {
+      long long *st = reinterpret_cast<long long *>(sd.state);
+      st[0] = nU;
+      st[1] = eU;
+      st[2] = dir;
+      st[3] = 1;
+    }
+    const int hv = dir ? sd.pull_v : sd.push_v;
+    dec = hv;
+    if (net) {
+      bool out_of_range = false;
+      float xn = 0.f;
+      if (l < NF) {
+        const float r = level_feature(l, (double)n, (double)nnz, 0.0, 1.0, (double)d, (double)nU, (double)eU,
+                                      (double)lg, (double)(lg * lg), (double)sd.gld, (double)sd.gld2);
+        out_of_range = r < nmin || r > nmax;
+        xn = (r - nmean) / nstd;
+      }
+      const bool any_oor = __ballot(out_of_range) != 0ull;
+      float *s_x = s_net, *h0 = s_net + NF, *h1 = h0 + NH, *h2 = h1 + NH;
+      if (l < NF) s_x[l] = xn;
+      __builtin_amdgcn_wave_barrier();
+      const float logit = forward_row_regs(nr, s_x, h0, h1, h2);
+      int cls;
+      float conf;
+      argmax_conf(logit, &cls, &conf);
+      fb = any_oor || !(conf >= sd.min_conf);
+      dec = fb ? hv : sd.cls[cls];
+    }
   }
+  if (l == 0) {
+    o.decision = dec;
+    o.fallback = fb;
+    slot0->tot = o;
+    LevelLog &L = log[0];
+    L.count = 1;
+    L.variant = dec;
+    L.edges = o.edges;
+    L.in_edges = o.in_edges;
+    L.ld = o.ld;
+    L.ld2 = o.ld2;
+    L.scanned = 0;
+    L.fallback = fb;
+    ctl->done = 0;
+    ctl->levels = 1;
+    ctl->reached = 1;
+    ctl->comp_edges = o.edges;
+    if (host) {
+      *host = o;
+      __threadfence_system();
+      *reinterpret_cast<volatile u64 *>(host_seq) = seq;
+    }
+  }
+}
+
+hipError_t launch_start_select(const int *rp, const int *cp, int src, RingSlot *slot0, LevelLog *log, LoopCtl *ctl,
+                               const SelDevice &sd, int n, int nnz, bool select, bool use_net, LevelCtr *host,
+                               u64 *host_seq, u64 seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_start_select, dim3(1), dim3(WAVE), 0, s, rp, cp, src, slot0, log, ctl, sd, n, nnz,
+                     select ? 1 : 0, (use_net && sd.use_net) ? 1 : 0, host, host_seq, seq);
+  return hipGetLastError();
 }
 
 hipError_t launch_finish_select(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl, const SelDevice &sd,

@@ -464,7 +464,14 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
       persistent = false;
     }
   }
-  if (!persistent) {
+  u64 start_seq = 0;
+  if (!persistent && !device_loop) {
+    // host loop: level 0 set up, chosen and posted by one launch after the reset
+    BFS_HIP(launch_reset(a, src, w.ring, s, false));
+    start_seq = ++hc.seq;
+    BFS_HIP(launch_start_select(g->row_ptr, g->csc_ptr, src, w.ring, w.log, w.ctl, seldev, g->n, g->nnz,
+                                device_decides, learned, hc.pinned, hc.pinned_u64 + 255, start_seq, s));
+  } else if (!persistent) {
     BFS_HIP(launch_reset(a, src, w.ring, s));
     BFS_HIP(launch_finish_f0(w, s));
     if (device_decides) BFS_HIP(launch_select(seldev, w.ring, 0, g->n, g->nnz, s, true, learned, w.log));
@@ -475,8 +482,8 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   std::vector<int> host_variant;  // variants the host chose (fixed / schedule modes)
   std::vector<float> level_ms;
   if (!device_loop) {
-    BFS_HIP(hipMemcpyAsync(hc.pinned, &w.ring[0].tot, sizeof(LevelCtr), hipMemcpyDeviceToHost, s));
-    BFS_HIP(hipStreamSynchronize(s));
+    rc = wait_posted(hc.pinned_u64 + 255, start_seq, s);
+    if (rc) return rc;
     ++syncs;
     long long cnt = hc.pinned[0].count;
     long long eF = (long long)hc.pinned[0].edges;

@@ -73,6 +73,11 @@ SelDevice selector_device(const Workspace &w, int push_v, int pull_v);
 // network when use_net and weights are loaded, else the direction rule.
 hipError_t launch_select(const SelDevice &sd, RingSlot *ring, int k, int n, int nnz, hipStream_t s, bool init,
                          bool use_net, LevelLog *log);
+// Level 0 of the host loop (after k_reset alone): F_0 = {src}, its log entry
+// and loop control, the choice for level 0 (select), posted to host memory.
+hipError_t launch_start_select(const int *rp, const int *cp, int src, RingSlot *slot0, LevelLog *log, LoopCtl *ctl,
+                               const SelDevice &sd, int n, int nnz, bool select, bool use_net, LevelCtr *host,
+                               u64 *host_seq, u64 seq, hipStream_t s);
 // Level-k counter reduction and (select) the choice for level k in one
 // launch; with host / host_seq the totals are posted to pinned memory.
 hipError_t launch_finish_select(RingSlot *slot, int qcap, int k, LevelLog *log, LoopCtl *ctl, const SelDevice &sd,

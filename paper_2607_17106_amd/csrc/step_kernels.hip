@@ -288,10 +288,10 @@ constexpr int GMAX = 4096;  // grid cap: grid-stride loops cover the rest
 
 int min_first_grid(int W) { return clampi(cdiv(W, BLOCK * 4), 1, GMAX); }
 
-hipError_t launch_reset(const StepArgs &a, int src, RingSlot *ring, hipStream_t s) {
+hipError_t launch_reset(const StepArgs &a, int src, RingSlot *ring, hipStream_t s, bool f0) {
   int grid = clampi(cdiv(a.W, BLOCK / WAVE), 1, GMAX);
   hipLaunchKernelGGL(k_reset, dim3(grid), dim3(BLOCK), 0, s, a, src, ring);
-  hipLaunchKernelGGL(k_reset_f0, dim3(1), dim3(NSH + 64), 0, s, a, src, ring);
+  if (f0) hipLaunchKernelGGL(k_reset_f0, dim3(1), dim3(NSH + 64), 0, s, a, src, ring);
   return hipGetLastError();
 }
 
