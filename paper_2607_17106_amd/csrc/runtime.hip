@@ -410,8 +410,9 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     return opt->schedule_host[std::min(k, opt->schedule_len - 1)];
   };
 
+  const bool host_loop = !device_loop;  // the level totals reach the host by posts, level by level
   BFS_HIP(hipEventRecord(hc.ev[0], s));
-  BFS_HIP(hipMemsetAsync(w.ctl, 0, sizeof(LoopCtl), s));
+  if (!host_loop) BFS_HIP(hipMemsetAsync(w.ctl, 0, sizeof(LoopCtl), s));  // the host loop's first launch sets it
   const bool graph_sums = learned || want_levels;
   u64 gld = 0, gld2 = 0;
   if (graph_sums) {
@@ -481,6 +482,10 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   int k = 0;
   std::vector<int> host_variant;  // variants the host chose (fixed / schedule modes)
   std::vector<float> level_ms;
+  // host loop: the loop control's totals and the fallback flags, gathered
+  // from the posts (the same sums the device keeps in LoopCtl)
+  long long h_levels = 0, h_reached = 0, h_comp = 0;
+  int h_fb = 0;
   if (!device_loop) {
     rc = wait_posted(hc.pinned_u64 + 255, start_seq, s);
     if (rc) return rc;
@@ -488,6 +493,10 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     long long cnt = hc.pinned[0].count;
     long long eF = (long long)hc.pinned[0].edges;
     int dec = hc.pinned[0].decision;
+    h_levels = 1;
+    h_reached = cnt;
+    h_comp = eF;
+    h_fb = hc.pinned[0].fallback;
     for (;;) {
       int v = device_decides ? dec : fixed_variant(k);
       if (v < 0 || v >= BFS_NUM_VARIANTS || (is_pull(v) && !have_csc)) v = push_v;
@@ -516,6 +525,10 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
       cnt = c.count;
       eF = (long long)c.edges;
       dec = c.decision;
+      h_levels = k + 2;
+      h_reached += cnt;
+      h_comp += eF;
+      h_fb |= c.fallback;
       ++k;
       if (k >= maxlev) {
         set_error("level loop reached max_levels = %lld", maxlev);
@@ -576,11 +589,20 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
     BFS_HIP(hipGetLastError());
   }
   BFS_HIP(hipEventRecord(hc.ev[1], s));
-  BFS_HIP(hipMemcpyAsync(hc.pinned_u64, w.ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
-  BFS_HIP(hipEventSynchronize(hc.ev[1]));
-  BFS_HIP(hipStreamSynchronize(s));
   LoopCtl ctl;
-  memcpy(&ctl, hc.pinned_u64, sizeof(ctl));
+  if (host_loop) {  // every total is on the host already: wait for the last kernel only
+    BFS_HIP(hipEventSynchronize(hc.ev[1]));
+    memset(&ctl, 0, sizeof(ctl));
+    ctl.done = 1;
+    ctl.levels = (u64)h_levels;
+    ctl.reached = (u64)h_reached;
+    ctl.comp_edges = (u64)h_comp;
+  } else {
+    BFS_HIP(hipMemcpyAsync(hc.pinned_u64, w.ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
+    BFS_HIP(hipEventSynchronize(hc.ev[1]));
+    BFS_HIP(hipStreamSynchronize(s));
+    memcpy(&ctl, hc.pinned_u64, sizeof(ctl));
+  }
   if (persistent) {
     BFS_HIP(hipMemcpy(hc.pinned_u64 + 16, &reinterpret_cast<GridBar *>(w.bar)->err.v, 4, hipMemcpyDeviceToHost));
     if (reinterpret_cast<u32 *>(hc.pinned_u64 + 16)[0] != 0u) {
@@ -617,6 +639,8 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
   }
   // per-level statistics from the device log (entry k+1 also carries the
   // scan length of the step that expanded F_k)
+  if (host_loop) st->fell_back |= h_fb;
+  if (host_loop && !want_levels) return BFS_OK;
   const int L = std::min(nlev + 1, LOGCAP);
   std::vector<LevelLog> lg(L);
   BFS_HIP(hipMemcpy(lg.data(), w.log, L * sizeof(LevelLog), hipMemcpyDeviceToHost));
