@@ -22,29 +22,33 @@ constexpr int NPARAM = BFS_MLP_NPARAM;
 
 // Raw feature i of one level (see bfs_eeds.h).  Evaluated in fp64 and
 // rounded to fp32, on the host (trainer) and on the device (selector) alike;
-// the device computes the 12 on 12 lanes at once.
+// the device computes the 12 on 12 lanes at once.  Every feature is either
+// log2(1 + a) or a / b - (c / b)^2 (c = 0 for a plain ratio, which leaves
+// a / b unchanged), so the lanes pick their operands and then all run the
+// same two operations -- one log2 and one division path instead of a
+// branch per feature, which a wave would run one after another.
 __host__ __device__ inline float level_feature(int i, double n, double nnz, double k, double nF, double eF, double nU,
                                                double eU, double fld, double fld2, double gld, double gld2) {
+  double a = 0.0, b = 1.0, c = 0.0;
+  bool lg = false;
   switch (i) {
-    case 0: return (float)log2(1.0 + nF);
-    case 1: return (float)log2(1.0 + eF);
-    case 2: return (float)log2(1.0 + nU);
-    case 3: return (float)log2(1.0 + eU);
-    case 4: return (float)(nF / n);
-    case 5: return (float)(nnz > 0 ? eF / nnz : 0.0);
-    case 6: return (float)(nU / n);
-    case 7: return (float)(nF > 0 ? fld / nF : 0.0);
-    case 8: {
-      const double fm = nF > 0 ? fld / nF : 0.0;
-      return (float)(nF > 0 ? fld2 / nF - fm * fm : 0.0);
-    }
-    case 9: return (float)(gld / n);
-    case 10: {
-      const double gm = gld / n;
-      return (float)(gld2 / n - gm * gm);
-    }
-    default: return (float)log2(1.0 + k);
+    case 0: lg = true; a = nF; break;
+    case 1: lg = true; a = eF; break;
+    case 2: lg = true; a = nU; break;
+    case 3: lg = true; a = eU; break;
+    case 4: a = nF; b = n; break;
+    case 5: if (nnz > 0) { a = eF; b = nnz; } break;
+    case 6: a = nU; b = n; break;
+    case 7: if (nF > 0) { a = fld; b = nF; } break;
+    case 8: if (nF > 0) { a = fld2; b = nF; c = fld; } break;  // variance: E[ld^2] - E[ld]^2
+    case 9: a = gld; b = n; break;
+    case 10: a = gld2; b = n; c = gld; break;
+    default: lg = true; a = k; break;
   }
+  const double lv = log2(1.0 + a);
+  const double m = c / b;
+  const double rv = a / b - m * m;
+  return (float)(lg ? lv : rv);
 }
 
 // All 12 raw features of one level.
