@@ -4,10 +4,8 @@ The network (not in the paper; its shape is the selector's contract):
 12 features -> 64 -> 64 -> 4 logits, ReLU between layers.  Weights are kept as
 fp32 master copies and used rounded to bfloat16 (round to nearest even); each
 layer's input activations are rounded to bfloat16; products are accumulated in
-fp32 in a fixed order: the 12-input layer from the bias, in ascending input
-index; each 64-input layer as four partial sums over the consecutive blocks
-of 16 inputs (each from zero, ascending), added to the bias in block order.
-The loss is mean softmax cross-entropy over the batch; training uses Adam.
+fp32 starting from the bias, in ascending input index.  The loss is mean
+softmax cross-entropy over the batch; training uses Adam.
 
 Flat parameter layout (5,252 fp32 values):
   W1[64][12] @0, b1[64] @768, W2[64][64] @832, b2[64] @4928,
@@ -15,8 +13,8 @@ Flat parameter layout (5,252 fp32 values):
 
 Two accumulation modes:
   acc="fp32"  the arithmetic the network is specified with: a bf16*bf16
-              product is exact in fp32, and every running sum is rounded to
-              fp32 after every addition, in the order above.
+              product is exact in fp32, and the running sum is rounded to fp32
+              after every addition, in ascending input order.
   acc="fp64"  the same expression evaluated in float64 (used to pin the fp32
               mode within its rounding bound and, with rounding switched off,
               to pin the backward pass by central finite differences).
@@ -54,19 +52,6 @@ def unpack(params):
             p[OFF_W3:OFF_B3].reshape(NOUT, NH), p[OFF_B3:NPARAM])
 
 
-BLOCK = 16  # inputs per partial sum of the 64-input layers
-
-
-def _fp32_sum(start, h, W, ks):
-    """start + sum over k in ks of h[:, k] * W[:, k], rounded to fp32 after
-    every addition, in the order of ks."""
-    z = start
-    for k in ks:
-        prod = (h[:, k:k + 1].astype(np.float64) * W[None, :, k].astype(np.float64)).astype(np.float32)
-        z = (z.astype(np.float64) + prod.astype(np.float64)).astype(np.float32)
-    return z
-
-
 def _layer(h, W, b, acc):
     """z[r, j] = b[j] + sum_k h[r, k] * W[j, k] in the given accumulation."""
     if acc == "fp64":
@@ -74,13 +59,9 @@ def _layer(h, W, b, acc):
     h = np.asarray(h, np.float32)
     W = np.asarray(W, np.float32)
     z = np.broadcast_to(np.asarray(b, np.float32), (h.shape[0], W.shape[0])).copy()
-    K = W.shape[1]
-    if K == NIN:  # from the bias, ascending
-        return _fp32_sum(z, h, W, range(K))
-    zero = np.zeros_like(z)
-    for q in range(K // BLOCK):  # block partial sums from zero, added in block order
-        part = _fp32_sum(zero, h, W, range(q * BLOCK, (q + 1) * BLOCK))
-        z = (z.astype(np.float64) + part.astype(np.float64)).astype(np.float32)
+    for k in range(W.shape[1]):
+        prod = (h[:, k:k + 1].astype(np.float64) * W[None, :, k].astype(np.float64)).astype(np.float32)
+        z = (z.astype(np.float64) + prod.astype(np.float64)).astype(np.float32)
     return z
 
 

@@ -52,10 +52,9 @@ __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap,
                                                        SelDevice sd, RingSlot *ring, int n, int nnz, int select,
                                                        int use_net, LevelCtr *host, u64 *host_seq, u64 seq) {
   (void)ring;  // slot is ring[k % RING]
-  static_assert(NSH == NBLK * WAVE, "the network is split over the workgroup's waves");
   __shared__ u64 s_red[5][NSH / WAVE];
   __shared__ int s_w[NSH / WAVE];
-  __shared__ __align__(16) NetLds s_net;
+  __shared__ __align__(16) float s_net[NF + 3 * NH];
   __shared__ u64 s_tot[4];      // count, edges, ld, ld2 of F_k
   __shared__ long long s_u[2];  // nU, eU after F_k
   __shared__ int s_hv;
@@ -79,10 +78,10 @@ __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap,
       st3 = st[3];
     }
   }
-  NetSlice nr;
+  NetRegs nr;
   float nmean = 0.f, nstd = 1.f, nmin = 0.f, nmax = 0.f;
-  if (net) load_net_slice(sd, t / WAVE, nr);
   if (net && t < WAVE) {
+    load_net(sd, nr);
     if (t < NF) {
       nmean = sd.norm[t];
       nstd = sd.norm[NF + t];
@@ -163,8 +162,9 @@ __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap,
   int dec = -1, fb = 0;
   if (net) {
     __syncthreads();  // uniform: the totals and state are in LDS
-    bool any_oor = false;
     if (t < WAVE) {
+      hv = s_hv;
+      dec = hv;
       // the level's raw features, one per lane; range check, then normalise
       bool out_of_range = false;
       float xn = 0.f;
@@ -175,12 +175,11 @@ __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap,
         out_of_range = r < nmin || r > nmax;
         xn = (r - nmean) / nstd;
       }
-      any_oor = __ballot(out_of_range) != 0ull;
-      if (lane() < NF) s_net.x[lane()] = xn;
-    }
-    const float logit = forward_split(nr, s_net);  // every wave
-    if (t < WAVE) {
-      hv = s_hv;
+      const bool any_oor = __ballot(out_of_range) != 0ull;
+      float *s_x = s_net, *h0 = s_net + NF, *h1 = h0 + NH, *h2 = h1 + NH;
+      if (lane() < NF) s_x[lane()] = xn;
+      __builtin_amdgcn_wave_barrier();
+      const float logit = forward_row_regs(nr, s_x, h0, h1, h2);
       int cls;
       float conf;
       argmax_conf(logit, &cls, &conf);
@@ -220,17 +219,17 @@ __global__ __launch_bounds__(NSH) void k_finish_select(RingSlot *slot, int qcap,
 // then the network, as body_select with init), and the totals posted to
 // host memory as k_finish_select does.  One wave; k_reset has cleared the
 // ring.
-__global__ __launch_bounds__(NBLK * WAVE) void k_start_select(const int *rp, const int *cp, int src,
-                                                              RingSlot *slot0, LevelLog *log, LoopCtl *ctl,
-                                                              SelDevice sd, int n, int nnz, int select, int use_net,
-                                                              LevelCtr *host, u64 *host_seq, u64 seq) {
-  __shared__ __align__(16) NetLds s_net;
-  const int l = lane(), t = threadIdx.x;
+__global__ __launch_bounds__(WAVE) void k_start_select(const int *rp, const int *cp, int src, RingSlot *slot0,
+                                                       LevelLog *log, LoopCtl *ctl, SelDevice sd, int n, int nnz,
+                                                       int select, int use_net, LevelCtr *host, u64 *host_seq,
+                                                       u64 seq) {
+  __shared__ __align__(16) float s_net[NF + 3 * NH];
+  const int l = lane();
   const bool net = select && use_net;
-  NetSlice nr;
+  NetRegs nr;
   float nmean = 0.f, nstd = 1.f, nmin = 0.f, nmax = 0.f;
-  if (net) load_net_slice(sd, t / WAVE, nr);
-  if (net && t < WAVE) {
+  if (net) {
+    load_net(sd, nr);
     if (l < NF) {
       nmean = sd.norm[l];
       nstd = sd.norm[NF + l];
@@ -238,7 +237,7 @@ __global__ __launch_bounds__(NBLK * WAVE) void k_start_select(const int *rp, con
       nmax = sd.norm[3 * NF + l];
     }
   }
-  for (int i = t; i < NSH + 2; i += NBLK * WAVE) slot0->seg[i] = (i == 0) ? 0 : 1;
+  for (int i = l; i < NSH + 2; i += WAVE) slot0->seg[i] = (i == 0) ? 0 : 1;
   const int d = rp[src + 1] - rp[src];
   const int di = cp ? cp[src + 1] - cp[src] : d;
   const int lg = ilog2p1(d);
@@ -258,7 +257,7 @@ __global__ __launch_bounds__(NBLK * WAVE) void k_start_select(const int *rp, con
     // and the direction rule from top-down with no previous frontier
     const long long nU = (long long)n - 1, eU = (long long)nnz - di;
     const int dir = (long long)d * HeuristicState::kAlpha > eU ? 1 : 0;
-    if (t == 0) {
+    if (l == 0) {
       long long *st = reinterpret_cast<long long *>(sd.state);
       st[0] = nU;
       st[1] = eU;
@@ -268,30 +267,27 @@ __global__ __launch_bounds__(NBLK * WAVE) void k_start_select(const int *rp, con
     const int hv = dir ? sd.pull_v : sd.push_v;
     dec = hv;
     if (net) {
-      bool any_oor = false;
-      if (t < WAVE) {
-        bool out_of_range = false;
-        float xn = 0.f;
-        if (l < NF) {
-          const float r = level_feature(l, (double)n, (double)nnz, 0.0, 1.0, (double)d, (double)nU, (double)eU,
-                                        (double)lg, (double)(lg * lg), (double)sd.gld, (double)sd.gld2);
-          out_of_range = r < nmin || r > nmax;
-          xn = (r - nmean) / nstd;
-        }
-        any_oor = __ballot(out_of_range) != 0ull;
-        if (l < NF) s_net.x[l] = xn;
+      bool out_of_range = false;
+      float xn = 0.f;
+      if (l < NF) {
+        const float r = level_feature(l, (double)n, (double)nnz, 0.0, 1.0, (double)d, (double)nU, (double)eU,
+                                      (double)lg, (double)(lg * lg), (double)sd.gld, (double)sd.gld2);
+        out_of_range = r < nmin || r > nmax;
+        xn = (r - nmean) / nstd;
       }
-      const float logit = forward_split(nr, s_net);  // every wave
-      if (t < WAVE) {
-        int cls;
-        float conf;
-        argmax_conf(logit, &cls, &conf);
-        fb = any_oor || !(conf >= sd.min_conf);
-        dec = fb ? hv : sd.cls[cls];
-      }
+      const bool any_oor = __ballot(out_of_range) != 0ull;
+      float *s_x = s_net, *h0 = s_net + NF, *h1 = h0 + NH, *h2 = h1 + NH;
+      if (l < NF) s_x[l] = xn;
+      __builtin_amdgcn_wave_barrier();
+      const float logit = forward_row_regs(nr, s_x, h0, h1, h2);
+      int cls;
+      float conf;
+      argmax_conf(logit, &cls, &conf);
+      fb = any_oor || !(conf >= sd.min_conf);
+      dec = fb ? hv : sd.cls[cls];
     }
   }
-  if (t == 0) {
+  if (l == 0) {
     o.decision = dec;
     o.fallback = fb;
     slot0->tot = o;
@@ -319,7 +315,7 @@ __global__ __launch_bounds__(NBLK * WAVE) void k_start_select(const int *rp, con
 hipError_t launch_start_select(const int *rp, const int *cp, int src, RingSlot *slot0, LevelLog *log, LoopCtl *ctl,
                                const SelDevice &sd, int n, int nnz, bool select, bool use_net, LevelCtr *host,
                                u64 *host_seq, u64 seq, hipStream_t s) {
-  hipLaunchKernelGGL(k_start_select, dim3(1), dim3(NBLK * WAVE), 0, s, rp, cp, src, slot0, log, ctl, sd, n, nnz,
+  hipLaunchKernelGGL(k_start_select, dim3(1), dim3(WAVE), 0, s, rp, cp, src, slot0, log, ctl, sd, n, nnz,
                      select ? 1 : 0, (use_net && sd.use_net) ? 1 : 0, host, host_seq, seq);
   return hipGetLastError();
 }

@@ -6,14 +6,10 @@
 //   z1 = b1 + W1 h0, h1 = bf16(relu(z1))
 //   z2 = b2 + W2 h1, h2 = bf16(relu(z2))
 //   logits = b3 + W3 h2
-// with W = bf16(W_master).  Accumulation in fp32, in a fixed order: the
-// first layer from the bias, adding products in ascending input order; the
-// 64-input layers as NBLK partial sums over consecutive blocks of BLK inputs
-// (each from zero, ascending), added to the bias in block order -- so the
-// blocks can be summed by NBLK waves at once and combined bit for bit as one
-// wave summing them in turn would.  A product of two bf16 values is exact in
-// fp32, so a fused multiply-add gives the same result as a separate multiply
-// and add; the order is what makes the result reproducible.
+// with W = bf16(W_master).  Each output is accumulated in fp32 starting from
+// its bias, adding products in ascending input order.  A product of two bf16
+// values is exact in fp32, so a fused multiply-add gives the same result as a
+// separate multiply and add; the order is what makes the result reproducible.
 #pragma once
 #include "common.hpp"
 #include "selector.hpp"
@@ -21,7 +17,6 @@
 namespace bfs {
 
 constexpr int SM_SELECT = (NF + 3 * NH + 1) * 4;
-constexpr int NBLK = 4, BLK = NH / NBLK;  // blocks of the 64-input layers' sums
 
 // fp32 -> bf16 bits, round to nearest even (NaN kept quiet).
 __host__ __device__ inline u16 f2bf(float f) {
@@ -64,22 +59,14 @@ __device__ inline float forward_row(const W &wt, const float *p, const float *x,
   h1[l] = bfr(fmaxf(acc, 0.f));
   __builtin_amdgcn_wave_barrier();
   acc = p[OFF_B2 + l];
-  for (int q = 0; q < NBLK; ++q) {
-    float part = 0.f;
-    for (int k = q * BLK; k < (q + 1) * BLK; ++k) part = part + h1[k] * wt(OFF_W2 + l * NH + k);
-    acc = acc + part;
-  }
+  for (int k = 0; k < NH; ++k) acc = acc + h1[k] * wt(OFF_W2 + l * NH + k);
   z2 = acc;
   h2[l] = bfr(fmaxf(acc, 0.f));
   __builtin_amdgcn_wave_barrier();
   float out = 0.f;
   if (l < NC) {
     acc = p[OFF_B3 + l];
-    for (int q = 0; q < NBLK; ++q) {
-      float part = 0.f;
-      for (int k = q * BLK; k < (q + 1) * BLK; ++k) part = part + h2[k] * wt(OFF_W3 + l * NH + k);
-      acc = acc + part;
-    }
+    for (int k = 0; k < NH; ++k) acc = acc + h2[k] * wt(OFF_W3 + l * NH + k);
     out = acc;
   }
   return out;
@@ -158,124 +145,13 @@ __device__ __forceinline__ float forward_row_regs(const NetRegs &r, const float 
   __builtin_amdgcn_wave_barrier();
   acc = r.b2;
 #pragma unroll
-  for (int q = 0; q < NBLK; ++q) {
-    float part = 0.f;
-#pragma unroll
-    for (int k = q * BLK; k < (q + 1) * BLK; ++k) part = part + h1[k] * bf_at(r.w2, k);
-    acc = acc + part;
-  }
+  for (int k = 0; k < NH; ++k) acc = acc + h1[k] * bf_at(r.w2, k);
   h2[l] = bfr(fmaxf(acc, 0.f));
   __builtin_amdgcn_wave_barrier();
   acc = r.b3;
 #pragma unroll
-  for (int q = 0; q < NBLK; ++q) {
-    float part = 0.f;
-#pragma unroll
-    for (int k = q * BLK; k < (q + 1) * BLK; ++k) part = part + h2[k] * bf_at(r.w3, k);
-    acc = acc + part;
-  }
+  for (int k = 0; k < NH; ++k) acc = acc + h2[k] * bf_at(r.w3, k);
   return l < NC ? acc : 0.f;
-}
-
-// The network split over NBLK waves of one workgroup: wave q keeps block q
-// of each 64-input row (lane j: W2[j][BLK q .. BLK q + BLK), lanes 0..3 also
-// W3[j][..]), wave 0 also the first layer's row and the biases.
-struct NetSlice {
-  u32 w1[NF / 2], w2[BLK / 2], w3[BLK / 2];
-  float b1, b2, b3;
-};
-
-// Loads this wave's slice (every wave of the NBLK-wave workgroup).  Byte
-// offsets of the block: W2 1664 + 128 j + 32 q, W3 9984 + 128 j + 32 q in a
-// 256-byte aligned buffer, so the 16-byte loads are aligned.
-__device__ __forceinline__ void load_net_slice(const SelDevice &sd, int q, NetSlice &r) {
-  const int l = lane();
-  const uint4 *p2 = reinterpret_cast<const uint4 *>(sd.w + OFF_W2 + l * NH + q * BLK);
-#pragma unroll
-  for (int i = 0; i < BLK / 8; ++i) {
-    const uint4 x = p2[i];
-    r.w2[4 * i] = x.x;
-    r.w2[4 * i + 1] = x.y;
-    r.w2[4 * i + 2] = x.z;
-    r.w2[4 * i + 3] = x.w;
-  }
-#pragma unroll
-  for (int i = 0; i < BLK / 2; ++i) r.w3[i] = 0u;
-  if (l < NC) {
-    const uint4 *p3 = reinterpret_cast<const uint4 *>(sd.w + OFF_W3 + l * NH + q * BLK);
-#pragma unroll
-    for (int i = 0; i < BLK / 8; ++i) {
-      const uint4 x = p3[i];
-      r.w3[4 * i] = x.x;
-      r.w3[4 * i + 1] = x.y;
-      r.w3[4 * i + 2] = x.z;
-      r.w3[4 * i + 3] = x.w;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < NF / 2; ++i) r.w1[i] = 0u;
-  r.b1 = r.b2 = r.b3 = 0.f;
-  if (q == 0) {
-    const uint2 *p1 = reinterpret_cast<const uint2 *>(sd.w + OFF_W1 + l * NF);
-#pragma unroll
-    for (int i = 0; i < NF / 4; ++i) {
-      const uint2 x = p1[i];
-      r.w1[2 * i] = x.x;
-      r.w1[2 * i + 1] = x.y;
-    }
-    r.b1 = sd.p[OFF_B1 + l];
-    r.b2 = sd.p[OFF_B2 + l];
-    r.b3 = l < NC ? sd.p[OFF_B3 + l] : 0.f;
-  }
-}
-
-// LDS of forward_split.
-struct NetLds {
-  float x[NF], h0[NF], h1[NH], h2[NH];
-  float p2[NBLK][NH], p3[NBLK][NC];
-};
-
-// The forward of one feature vector by the NBLK waves of a workgroup (every
-// thread calls it; x[] holds the normalised features).  The same arithmetic
-// as forward_row_regs: wave q sums block q, wave 0 adds the partial sums to
-// the biases in block order.  Returns the logits in lanes 0..3 of wave 0.
-__device__ __forceinline__ float forward_split(const NetSlice &r, NetLds &m) {
-  const int l = lane(), q = threadIdx.x / WAVE;
-  if (q == 0) {
-    if (l < NF) m.h0[l] = bfr(m.x[l]);
-    __builtin_amdgcn_wave_barrier();
-    float acc = r.b1;
-#pragma unroll
-    for (int k = 0; k < NF; ++k) acc = acc + m.h0[k] * bf_at(r.w1, k);
-    m.h1[l] = bfr(fmaxf(acc, 0.f));
-  }
-  __syncthreads();
-  float part = 0.f;
-#pragma unroll
-  for (int k = 0; k < BLK; ++k) part = part + m.h1[q * BLK + k] * bf_at(r.w2, k);
-  m.p2[q][l] = part;
-  __syncthreads();
-  if (q == 0) {
-    float acc = r.b2;
-#pragma unroll
-    for (int b = 0; b < NBLK; ++b) acc = acc + m.p2[b][l];
-    m.h2[l] = bfr(fmaxf(acc, 0.f));
-  }
-  __syncthreads();
-  if (l < NC) {
-    float p3 = 0.f;
-#pragma unroll
-    for (int k = 0; k < BLK; ++k) p3 = p3 + m.h2[q * BLK + k] * bf_at(r.w3, k);
-    m.p3[q][l] = p3;
-  }
-  __syncthreads();
-  float out = 0.f;
-  if (q == 0 && l < NC) {
-    out = r.b3;
-#pragma unroll
-    for (int b = 0; b < NBLK; ++b) out = out + m.p3[b][l];
-  }
-  return out;
 }
 
 // Argmax over lanes 0..3 (ties to the lowest index) and the top softmax
