@@ -44,18 +44,36 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of k_ms_pull_tile on this workload: two rocprofv3 --pmc runs of
-# `bench.py --steps 3 --warmup 1 --no-sweep --no-batch --no-cpu --no-input-order` (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch averaged over all the kernel's dispatches in the run),
-# each scaled by what the same counter reads for a plain copy of 1 GiB
-# (`bench.py --copy-calibration 1073741824`: FETCH_SIZE 524300 KiB -> x2.0,
-# WRITE_SIZE 1048576 KiB -> x1.0).  Reported only while the kernel code
-# (comments and whitespace aside) hashes to the values the counters were taken with.
+# `bench.py --steps 3 --warmup 1 --no-sweep --no-batch --no-cpu --no-input-order
+# --multi-config <the configuration below>` (FETCH_SIZE, then WRITE_SIZE, KiB
+# per dispatch averaged over the kernel's 28 dispatches: 7 steps of 4 bottom-up
+# levels), each scaled by what the same counter reads for a plain copy of
+# 1 GiB (`bench.py --copy-calibration 1073741824`: FETCH_SIZE 524300 KiB ->
+# x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  Reported only while the kernel code
+# (comments and whitespace aside) hashes to the values the counters were taken
+# with and the steps run with the same configuration.
 TILE_TRAFFIC = {
     "sources_sha256": {
-        "paper_2607_17106_amd/csrc/msbfs.hip": "319f79bd6009bc3aa4ebbb52917dd2d56144aa7cf6aeefd3a03fe710d06862e8",
-        "paper_2607_17106_amd/csrc/common.hpp": "75fd6210cda1c9516901c13c241ebfdff41a6944840c36e3bbf27a58f0bdc9de",
+        "paper_2607_17106_amd/csrc/msbfs.hip": "41ecc66908a1778e387d98216831fc12c76be205cbf5c5785e925d9ed2b59ace",
+        "paper_2607_17106_amd/csrc/common.hpp": "680997ca0cd797142a5ee549c5999761f8941a188c6a2706211b9097d8d80ac1",
     },
-    "fetch_kib": 171037.1, "write_kib": 107964.9, "fetch_scale": 2.0, "write_scale": 1.0,
+    "multi_config": {"wide_ratio": 16, "split_vpt": 4, "cap0": 32, "tile_alpha": 64, "alpha": 7, "split_lout": 16,
+                     "wide_vpt": 2, "narrow_vpt": 4},
+    "fetch_kib": 180965.4, "write_kib": 107167.6, "fetch_scale": 2.0, "write_scale": 1.0,
+}
+
+# The same for k_batch on the 512-instance mix: `bench.py --steps 1 --warmup 1
+# --no-sweep --no-cpu --no-input-order --multi-config ...` (the autotuner's
+# candidate runs, then the warm-up and timed call of the chosen configuration
+# below, whose two dispatches are averaged), with the copy calibration above.
+BATCH_TRAFFIC = {
+    "sources_sha256": {
+        "paper_2607_17106_amd/csrc/batch.hip": "709d6ea097c5010f9c4e18836405eb3eb655b0f3661347b616c6fec7c019e3cc",
+        "paper_2607_17106_amd/csrc/common.hpp": "680997ca0cd797142a5ee549c5999761f8941a188c6a2706211b9097d8d80ac1",
+    },
+    "config": {"block_threads": 1024, "blocks_per_cu": 2, "small_vertices": 1048576, "team_vertices": 131072,
+               "max_team": 8},
+    "fetch_kib": 16247922.5, "write_kib": 4355134.0, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
@@ -71,13 +89,15 @@ def code_hash(path: str) -> str:
     return hashlib.sha256("".join(text.split()).encode()).hexdigest()
 
 
-def tile_traffic_bytes():
-    """Measured HBM bytes per k_ms_pull_tile launch, or None once the kernel
-    code differs from the code the counters were taken with."""
-    for rel, h in TILE_TRAFFIC["sources_sha256"].items():
+def measured_traffic_bytes(t: dict, config_key: str, config: dict):
+    """Measured HBM bytes per launch from the record t, or None once the
+    kernel code differs from the code the counters were taken with, or the
+    run uses another configuration."""
+    for rel, h in t["sources_sha256"].items():
         if code_hash(os.path.join(ROOT, rel)) != h:
             return None
-    t = TILE_TRAFFIC
+    if t.get(config_key) != config:
+        return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 METRIC = "GTEPS and HBM-roofline fraction at 1 GPU: fixed variant vs learned/batched"
 
@@ -196,6 +216,12 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip single-source modes and fixed variants")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch")
     ap.add_argument("--sweep-sources", type=int, default=16)
+    ap.add_argument("--roofline-sources", type=int, default=4,
+                    help="sources per mode for the single-source per-variant roofline (level-timed searches)")
+    ap.add_argument("--multi-config", default=None, metavar="JSON",
+                    help="bfs_multi_config fields for the 64-lane steps instead of autotuning (as the "
+                         "counter runs use, so every profiled step has the same configuration); the "
+                         "library-defaults comparison is then skipped")
     ap.add_argument("--no-input-order", action="store_true",
                     help="skip the comparison runs on the graph as generated and renumbered by RCM "
                          "(profiles see the timed step only)")
@@ -250,8 +276,16 @@ def main():
 
     # autotuning, like the renumbering, is per-graph preparation outside the
     # timed region; the defaults are timed too, after the tuned steps
-    (tuned, tuned_ms), tune_s = autotune(rg, new_of_old)
-    log(f"[bench] autotuned in {tune_s:.2f} s: {tuned} ({tuned_ms:.3f} ms)")
+    if args.multi_config:
+        tuned, tune_s = B.MultiConfig(**json.loads(args.multi_config)), 0.0
+        given = tuned
+
+        def step(timing, graph=rg, vmap=new_of_old, config=None, _step=step):  # noqa: F811
+            return _step(timing, graph, vmap, given if config is None else config)
+        log(f"[bench] configuration given: {tuned}")
+    else:
+        (tuned, tuned_ms), tune_s = autotune(rg, new_of_old)
+        log(f"[bench] autotuned in {tune_s:.2f} s: {tuned} ({tuned_ms:.3f} ms)")
 
     for _ in range(args.warmup):
         step(0)
@@ -269,18 +303,20 @@ def main():
     stats_lev = [step(2) for _ in range(args.steps)]
     # the library defaults (no tuning), for comparison: the same steps with
     # the same main-kernel events
-    step(1, config=B.MultiConfig())
-    torch.cuda.synchronize()
-    t_d = time.perf_counter()
-    for _ in range(args.steps):
+    default_ms = None
+    if not args.multi_config:
         step(1, config=B.MultiConfig())
-    torch.cuda.synchronize()
-    default_ms = (time.perf_counter() - t_d) * 1e3 / args.steps
-    log(f"[bench] library defaults: {default_ms:.3f} ms per step")
+        torch.cuda.synchronize()
+        t_d = time.perf_counter()
+        for _ in range(args.steps):
+            step(1, config=B.MultiConfig())
+        torch.cuda.synchronize()
+        default_ms = (time.perf_counter() - t_d) * 1e3 / args.steps
+        log(f"[bench] library defaults: {default_ms:.3f} ms per step")
 
     # the same search on the graph as generated (no renumbering), for comparison
     input_order = rcm_order = None
-    if not args.no_input_order:
+    if not args.no_input_order and not args.multi_config:
         (tuned_in, _), tune_in_s = autotune(dg, None)
         step(0, dg, None)
         torch.cuda.synchronize()
@@ -311,7 +347,8 @@ def main():
         log(f"[bench] input order: {input_order}")
         # and on the graph renumbered by reverse Cuthill-McKee
         (cg, cmap, _), rcm_s = timed(lambda: B.reorder_rcm(dg))
-        autotune(cg, cmap)
+        if not args.multi_config:
+            autotune(cg, cmap)
         step(0, cg, cmap)
         torch.cuda.synchronize()
         t_c = time.perf_counter()
@@ -347,7 +384,8 @@ def main():
                 tile_lev += float(st["ms_main"][k])
     achieved = b_tile / (t_tile * 1e-3) / 1e9
     step_level_ms = sum(per_t.values()) / len(stats_lev)
-    traffic = tile_traffic_bytes() if args.workload == "rmat22" and len(sources) == 64 else None
+    traffic = (measured_traffic_bytes(TILE_TRAFFIC, "multi_config", vars(tuned))
+               if args.workload == "rmat22" and len(sources) == 64 else None)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None, "kernel": "k_ms_pull_tile",
@@ -375,7 +413,8 @@ def main():
                       "vertex_order": "renumbered by decreasing out-degree (bfs_reorder_degree, preprocessing, "
                                       "outside the timed region); sources and depths in the original numbering",
                       "reorder_ms": round(reorder_s * 1e3, 2), "multi_config": vars(tuned),
-                      "autotune_s": round(tune_s, 2), "library_defaults_ms_per_step": round(default_ms, 3)},
+                      "autotune_s": round(tune_s, 2),
+                      "library_defaults_ms_per_step": round(default_ms, 3) if default_ms is not None else None},
            "roofline": roof, "input_order": input_order, "rcm_order": rcm_order}
 
     # ------------------------------------------- single-source comparisons
@@ -409,6 +448,23 @@ def main():
         for name, _, _ in modes:
             single[name] = round(edges_of[name] / best[name] / 1e9, 3)
             log(f"[bench] single-source {name}: {single[name]} GTEPS")
+        # per-variant roofline: algorithmic bytes of every level step (the
+        # byte model over the library's per-level counts) over the steps'
+        # device time (HIP events around each level's kernels), on a few
+        # level-timed searches per mode, outside the timed passes above
+        roof_single = {}
+        for name, var, srcs in modes:
+            b_sum = t_sum = 0.0
+            for s_ in srcs[: args.roofline_sources]:
+                _, st = B.bfs_levels(dg, int(s_), variant=var, workspace=ws, levels=lv, flags=B.F_LEVEL_TIMING)
+                b_sum += sum(bytemodel.level_bytes(st, g.n))
+                t_sum += float(st["ms"][: st["num_levels"]].sum())
+            gbs = b_sum / (t_sum * 1e-3) / 1e9
+            roof_single[name] = {"achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                 "bytes_per_search": round(b_sum / max(1, min(len(srcs), args.roofline_sources))),
+                                 "step_ms_per_search": round(t_sum / max(1, min(len(srcs), args.roofline_sources)), 4)}
+        out["single_source_roofline"] = roof_single
+        log(f"[bench] single-source roofline: { {k: v['frac'] for k, v in roof_single.items()} }")
         # the direction heuristic on the degree-renumbered graph (vertex_map)
         run_single(B.AUTO_HEURISTIC, sources[:2], rg, new_of_old)
         ren_t = None
@@ -465,14 +521,17 @@ def main():
         reached = int((lvb >= 0).sum().item())
         bb_bytes = bytemodel.batch_bytes(bb.total_n, reached, int(stb["component_edges"]))
         b_ach = bb_bytes / (stb["elapsed_ms"] * 1e-3) / 1e9
+        bcfg = {"block_threads": cfg.block_threads, "blocks_per_cu": cfg.blocks_per_cu,
+                "small_vertices": cfg.small_vertices, "team_vertices": cfg.team_vertices, "max_team": cfg.max_team}
+        b_traffic = measured_traffic_bytes(BATCH_TRAFFIC, "config", bcfg)
+        b_roof = {"bound": "hbm", "achieved": round(b_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(b_ach / HBM_PEAK_GBS, 4),
+                  "traffic": round(b_traffic) if b_traffic is not None else None,
+                  "kernel": "k_batch", "bytes_per_launch": round(bb_bytes)}
+        if b_traffic is not None:
+            b_roof["traffic_over_algorithmic"] = round(b_traffic / bb_bytes, 2)
         out["batch512"] = {"gteps": round(batch_gteps, 3), "ms": round(dtb * 1e3, 2),
-                           "kernel_ms": round(stb["elapsed_ms"], 3),
-                           "roofline": {"bound": "hbm", "achieved": round(b_ach, 1), "peak": HBM_PEAK_GBS,
-                                        "unit": "GB/s", "frac": round(b_ach / HBM_PEAK_GBS, 4), "traffic": None,
-                                        "kernel": "k_batch", "bytes_per_launch": round(bb_bytes)},
-                           "config": {"block_threads": cfg.block_threads, "blocks_per_cu": cfg.blocks_per_cu,
-                                      "small_vertices": cfg.small_vertices, "team_vertices": cfg.team_vertices,
-                                      "max_team": cfg.max_team},
+                           "kernel_ms": round(stb["elapsed_ms"], 3), "roofline": b_roof, "config": bcfg,
                            "autotune_best_ms": round(tune_ms, 2),
                            "sample_64_instances": {"batched_gteps": round(sts["component_edges"] / 2 / dts / 1e9, 3),
                                                    "one_by_one_gteps": one}}

@@ -360,8 +360,9 @@ int bfs_multi(const bfs_graph *g, const int32_t *sources_host, int32_t k, int32_
 
 /* Tunes bfs_multi's configuration for one graph and source set: runs the
  * search (k sources, the same options otherwise) with candidate values of
- * each bfs_multi_config field in turn, keeping the fastest by device time
- * (best of two runs), starting from options.multi_config or the defaults.
+ * each bfs_multi_config field in turn, keeping a candidate when its device
+ * time (best of two runs) is at least 1% below the current choice's, starting
+ * from options.multi_config or the defaults.
  * The result is returned in *best (and the time in *ms_best, may be NULL)
  * and stored for the graph, so later bfs_multi calls on it with
  * multi_config = NULL use it.  levels: device [k][n] scratch (holds the last

@@ -2122,7 +2122,7 @@ extern "C" int bfs_multi_autotune(const bfs_graph *g, const int32_t *sources, in
       float ms = 0.f;
       rc = time_of(t, &ms);
       if (rc) return rc;
-      if (ms < cur_ms) {
+      if (ms < 0.99f * cur_ms) {  // a clear gain only: run-to-run noise does not move the choice
         cur = t;
         cur_ms = ms;
       }
