@@ -116,6 +116,7 @@ struct MsArgs {
   u64 full;             // mask of the L lanes
   const int *rp, *ci, *cp, *cx;
   int ncx;              // entries of cx (the in-edge count)
+  int sym;              // cp == rp (a symmetric graph passes one array twice)
   const u64 *front;     // F_k words
   const u64 *fbits;     // any-lane bitmap of F_k: bit v%64 of word v/64
   u64 *next;            // F_{k+1} words
@@ -380,19 +381,23 @@ __device__ __forceinline__ void ms_clear_dead(const MsArgs &a) {
 
 // Records the discovery of `nw` lanes at v (owner thread, so the plane
 // updates are plain read-modify-writes): vis, depth planes, stats.
-__device__ __forceinline__ void ms_discover(const MsArgs &a, int v, u64 vis_old, u64 nw, MsStats &st) {
+// in_deg >= 0: v's in-degree, already at hand (the bottom-up tile loaded its
+// in-edge offsets), which is also its out-degree on a symmetric graph; -1:
+// both are read here.
+__device__ __forceinline__ void ms_discover(const MsArgs &a, int v, u64 vis_old, u64 nw, MsStats &st,
+                                            int in_deg = -1) {
   const u64 vnew = vis_old | nw;
   a.vis[v] = vnew;
   for (int r = a.rel, b = 0; r; r >>= 1, ++b)
     if (r & 1) a.planes[(size_t)b * a.n + v] |= nw;
   const int c = __popcll(nw);
-  const int od = a.rp[v + 1] - a.rp[v];
+  const int od = (in_deg >= 0 && a.sym) ? in_deg : a.rp[v + 1] - a.rp[v];
   st.c[C_NEW] += (u32)c;
   st.comp += (u64)c * (u64)od;
   st.c[C_ACTIVE] += 1;
   st.c[C_ACTOUT] += (u32)od;
   if (v >= a.hub_t) st.c[C_LOUT] += (u32)od;
-  if ((vnew & a.full) == a.full) st.c[C_DONEIN] += (u32)(a.cp[v + 1] - a.cp[v]);
+  if ((vnew & a.full) == a.full) st.c[C_DONEIN] += (u32)(in_deg >= 0 ? in_deg : a.cp[v + 1] - a.cp[v]);
 }
 
 // Writes the depth of every lane of v not in `skip`: a.base + r for visited
@@ -1225,7 +1230,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
       if (v < ve) {
         nw = acc[j] & need[j];
         a.next[v] = nw;
-        if (nw) ms_discover(a, v, vw[j], nw, st);
+        if (nw) ms_discover(a, v, vw[j], nw, st, d[j]);
         if (heavy[j] && (need[j] & ~nw)) st.c[C_HPEND] += 1;
       }
       const u64 nb = __ballot(nw != 0ull);
@@ -1753,6 +1758,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     a.cp = g->csc_ptr;
     a.cx = g->csc_idx;
     a.ncx = g->nnz;
+    a.sym = g->row_ptr == g->csc_ptr ? 1 : 0;
     a.vis = W.vis;
     a.planes = W.planes;
     a.flushed = W.flushed;
