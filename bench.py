@@ -230,8 +230,8 @@ def main():
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md, 'Sharding' describes "
-              "how the search would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the search runs on one "
+              "device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

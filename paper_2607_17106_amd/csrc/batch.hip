@@ -185,21 +185,27 @@ __device__ __forceinline__ int choose_bottom_up(long long nU, long long eU, long
 }
 
 // ------------------------------------------- single workgroup, LDS visited
-// Per-instance state in global memory: two frontier queues (n each) and, when
-// it does not fit in LDS beside the visited bitmap, the bottom-up frontier
-// bitmap.  Only this workgroup touches them, so plain accesses are coherent.
+// Per-instance state in global memory: two frontier queues (n entries each)
+// and, when it does not fit in LDS beside the visited bitmap, the bottom-up
+// frontier bitmap.  Only this workgroup touches them, so plain accesses are
+// coherent.  A queue entry is the vertex with its row offsets (three int
+// arrays), read when its finder records it: expanding it then reads the entry
+// with coalesced loads instead of a second scattered rp access.
+struct SQueue {
+  int *v, *b, *e;  // vertex, rp[v], rp[v + 1]
+};
 __host__ __device__ inline size_t single_state_bytes(long long n, bool fr_global) {
   const size_t qb = ((size_t)n * 4 + 255) & ~(size_t)255;
   const size_t wb = ((size_t)((n + 63) / 64) * 8 + 255) & ~(size_t)255;
-  return 2 * qb + (fr_global ? wb : 0);
+  return 6 * qb + (fr_global ? wb : 0);
 }
 
 // Appends the candidates of one round (won[j] per lane) to q at slots taken
 // from the LDS counter *cnt with one reservation per wave; records depth k+1
 // and the new vertices' out-edges.  Called by every lane of the wave.
 template <int U>
-__device__ __forceinline__ void single_found(const int *rp, int *lv, const bool *won, const int *v, int k, int *q,
-                                             int *cnt, u64 &efn) {
+__device__ __forceinline__ void single_found(const int *rp, int *lv, const bool *won, const int *v, int k,
+                                             const SQueue &q, int *cnt, u64 &efn) {
   u64 mk[U];
   int tot = 0;
 #pragma unroll
@@ -209,14 +215,11 @@ __device__ __forceinline__ void single_found(const int *rp, int *lv, const bool 
     tot += __popcll(mk[j]);
   }
   if (!tot) return;
-  int d[U];
+  int2 r[U];
 #pragma unroll
   for (int j = 0; j < U; ++j) {
-    d[j] = 0;
-    if (won[j]) {
-      const int2 r = rp_pair(rp, v[j]);
-      d[j] = r.y - r.x;
-    }
+    r[j] = make_int2(0, 0);
+    if (won[j]) r[j] = rp_pair(rp, v[j]);
   }
   int base = 0;
   if (lane() == 0) base = atomicAdd(cnt, tot);
@@ -224,10 +227,82 @@ __device__ __forceinline__ void single_found(const int *rp, int *lv, const bool 
 #pragma unroll
   for (int j = 0; j < U; ++j) {
     if (won[j]) {
-      q[base + __popcll(mk[j] & __lanemask_lt())] = v[j];
-      efn += (u64)d[j];
+      const int slot = base + __popcll(mk[j] & __lanemask_lt());
+      q.v[slot] = v[j];
+      q.b[slot] = r[j].x;
+      q.e[slot] = r[j].y;
+      efn += (u64)(r[j].y - r[j].x);
     }
     base += __popcll(mk[j]);
+  }
+}
+
+// Light top-down rounds stage their finds per wave in LDS (STAGE vertices per
+// wave), so that recording them takes dense wave instructions: a lane's 16
+// candidates are found by few lanes each, and a per-candidate masked store or
+// load costs the texture unit about as much as a full one.
+constexpr int STAGE = 256;
+
+// Records the wave's staged finds stg[0, cnt) (cnt <= STAGE): depth k+1 and
+// queue entries with their row offsets, one queue reservation, 64 per round.
+// Called by every lane of the wave.
+__device__ __forceinline__ void stage_flush(const int *rp, int *lv, const int *stg, int cnt, int k, const SQueue &q,
+                                            int *qcnt, u64 &efn) {
+  if (cnt == 0) return;  // uniform per wave
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  int base = 0;
+  if (lane() == 0) base = atomicAdd(qcnt, cnt);
+  base = __shfl(base, 0);
+  constexpr int R = STAGE / WAVE;
+  int w[R];
+  int2 r[R];
+#pragma unroll
+  for (int o = 0; o < R; ++o) {
+    const int i = o * WAVE + lane();
+    w[o] = i < cnt ? stg[i] : -1;
+  }
+#pragma unroll
+  for (int o = 0; o < R; ++o) r[o] = w[o] >= 0 ? rp_pair(rp, w[o]) : make_int2(0, 0);
+#pragma unroll
+  for (int o = 0; o < R; ++o) {
+    if (w[o] < 0) continue;
+    const int slot = base + o * WAVE + lane();
+    lv[w[o]] = k + 1;
+    q.v[slot] = w[o];
+    q.b[slot] = r[o].x;
+    q.e[slot] = r[o].y;
+    efn += (u64)(r[o].y - r[o].x);
+  }
+  // the stage is written again only after every lane has read it
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Adds the wave's finds of one group of G candidates per lane (won[j]) to the
+// stage, first flushing it when they would not fit (G * WAVE <= STAGE).
+template <int G>
+__device__ __forceinline__ void stage_add(const int *rp, int *lv, int *stg, int &scnt, const bool *won, const int *v,
+                                          int k, const SQueue &q, int *qcnt, u64 &efn) {
+  static_assert(G * WAVE <= STAGE, "a group fits the stage");
+  u64 mk[G];
+  int gt = 0;
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    mk[j] = __ballot(won[j]);
+    gt += __popcll(mk[j]);
+  }
+  if (gt == 0) return;  // uniform per wave
+  if (scnt + gt > STAGE) {
+    stage_flush(rp, lv, stg, scnt, k, q, qcnt, efn);
+    scnt = 0;
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    if (won[j]) stg[scnt + __popcll(mk[j] & __lanemask_lt())] = v[j];
+    scnt += __popcll(mk[j]);
   }
 }
 
@@ -239,6 +314,8 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
   constexpr int HCAP = 2 * BT;       // heavy lists flattened per half pass
   constexpr int U = 4;               // heavy edges per lane per round
   const int wv = threadIdx.x / WAVE, nwv = BT / WAVE;
+  static_assert(4 * BT >= STAGE * (BT / WAVE), "s_off and s_incl hold every wave's stage");
+  int *stg = s_off + wv * STAGE;  // this wave's stage: s_off and s_incl are contiguous (light rounds only)
   const int V0 = A.v_off[b];
   const int n = A.v_off[b + 1] - V0;
   const int *rp = A.rp + V0;
@@ -246,9 +323,11 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
   const int W = (n + 63) / 64;
   char *st = A.team + A.toff[b];
   const size_t qb = ((size_t)n * 4 + 255) & ~(size_t)255;
-  int *qc = reinterpret_cast<int *>(st), *qn = reinterpret_cast<int *>(st + qb);
+  SQueue qc = {reinterpret_cast<int *>(st), reinterpret_cast<int *>(st + qb), reinterpret_cast<int *>(st + 2 * qb)};
+  SQueue qn = {reinterpret_cast<int *>(st + 3 * qb), reinterpret_cast<int *>(st + 4 * qb),
+               reinterpret_cast<int *>(st + 5 * qb)};
   u64 *vis = reinterpret_cast<u64 *>(dyn);
-  u64 *fr = A.fr_lds ? vis + (A.small_n + 63) / 64 : reinterpret_cast<u64 *>(st + 2 * qb);
+  u64 *fr = A.fr_lds ? vis + (A.small_n + 63) / 64 : reinterpret_cast<u64 *>(st + 6 * qb);
   const int src = A.src[b];
   for (int v = threadIdx.x; v < n; v += BT) lv[v] = (v == src) ? 0 : -1;
   for (int w = threadIdx.x; w < W; w += BT) {
@@ -257,9 +336,12 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
     vis[w] = x;
   }
   if (threadIdx.x == 0) {
-    qc[0] = src;
+    const int2 r = rp_pair(rp, src);
+    qc.v[0] = src;
+    qc.b[0] = r.x;
+    qc.e[0] = r.y;
     *s_qn = 1;
-    *s_efn = (unsigned long long)(rp[src + 1] - rp[src]);
+    *s_efn = (unsigned long long)(r.y - r.x);
   }
   __syncthreads();
   long long nF = *s_qn, eF = (long long)*s_efn;
@@ -278,30 +360,30 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
     u64 efn = 0;  // out-edges of the vertices this lane discovers (reduced per wave below)
     if (dir == 0) {
       // ---- top-down, CAP queue vertices per pass: lists of out-degree <= LIGHT
-      // expanded by their own lane in rounds of 4 edges (no search), longer
-      // ones flattened over the workgroup (U consecutive edges per lane per
-      // round, one owner search then a linear walk); claims are LDS atomics
+      // expanded by their own lane in rounds of 4 edges (no search), every
+      // wave on its own (no barrier between passes); then, if the level has
+      // longer lists, a second sweep flattens them over the workgroup (U
+      // consecutive edges per lane per round, one owner search then a linear
+      // walk); claims are LDS atomics
+      bool lheavy = false;
       for (int p0 = 0; p0 < nF; p0 += CAP) {
-        int uu[VPT], beg[VPT], dd[VPT];
+        int beg[VPT], dd[VPT];
 #pragma unroll
         for (int r = 0; r < VPT; ++r) {
           const int i = p0 + r * BT + (int)threadIdx.x;
-          uu[r] = i < nF ? qc[i] : -1;
-        }
-#pragma unroll
-        for (int r = 0; r < VPT; ++r) {
           beg[r] = dd[r] = 0;
-          if (uu[r] >= 0) {
-            const int2 x = rp_pair(rp, uu[r]);
-            beg[r] = x.x;
-            dd[r] = x.y - x.x;
+          if (i < nF) {
+            beg[r] = qc.b[i];
+            dd[r] = qc.e[i] - beg[r];
           }
+          lheavy |= dd[r] > LIGHT;
         }
         int lmax = 0;
 #pragma unroll
         for (int r = 0; r < VPT; ++r)
           if (dd[r] <= LIGHT) lmax = max(lmax, dd[r]);
         for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
+        int scnt = 0;  // staged finds of this wave (stg)
         for (int t0 = 0; t0 < lmax; t0 += 4) {
           int v[4 * VPT];
           bool won[4 * VPT];
@@ -315,7 +397,24 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
               if (!(vis[v[j] >> 6] & bit)) won[j] = !(or_wg(vis + (v[j] >> 6), bit) & bit);
             }
           }
-          single_found<4 * VPT>(rp, lv, won, v, k, qn, s_qn, efn);
+#pragma unroll
+          for (int r = 0; r < VPT; ++r) stage_add<4>(rp, lv, stg, scnt, won + 4 * r, v + 4 * r, k, qn, s_qn, efn);
+        }
+        stage_flush(rp, lv, stg, scnt, k, qn, s_qn, efn);
+      }
+      // (the barrier also ends every wave's use of its stage: the heavy sweep
+      // writes s_off and s_incl)
+      const bool any_heavy = __syncthreads_or(lheavy);
+      for (int p0 = 0; any_heavy && p0 < nF; p0 += CAP) {  // uniform per workgroup
+        int beg[VPT], dd[VPT];
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) {
+          const int i = p0 + r * BT + (int)threadIdx.x;
+          beg[r] = dd[r] = 0;
+          if (i < nF) {
+            beg[r] = qc.b[i];
+            dd[r] = qc.e[i] - beg[r];
+          }
         }
         // heavy lists, two halves of the pass (HCAP list entries each)
         bool heavy = false;
@@ -374,7 +473,7 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
       for (int w = threadIdx.x; w < W; w += BT) fr[w] = 0ull;
       __syncthreads();
       for (int i = threadIdx.x; i < nF; i += BT) {
-        const int u = qc[i];
+        const int u = qc.v[i];
         or_wg(fr + (u >> 6), 1ull << (u & 63));
       }
       __syncthreads();
@@ -428,7 +527,7 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
     eU -= eF;  // symmetric instances: in-edges = out-edges of the new vertices
     nU -= nF;
     comp += eF;
-    int *tq = qc;
+    const SQueue tq = qc;
     qc = qn;
     qn = tq;
     if (nF == 0) break;
@@ -795,7 +894,8 @@ template <int BT>
 __global__ __launch_bounds__(BT) void k_batch(BatchArgs A) {
   extern __shared__ __align__(16) char dyn[];
   constexpr int CHMAX = 2 * BT;
-  __shared__ int s_off[CHMAX], s_incl[CHMAX], s_w[BT / WAVE];
+  __shared__ int s_buf[2 * CHMAX], s_w[BT / WAVE];  // s_off | s_incl, contiguous (the light rounds' stages)
+  int *s_off = s_buf, *s_incl = s_buf + CHMAX;
   __shared__ int s_task[2], s_qn, s_flag;
   __shared__ u32 s_cnt;
   __shared__ unsigned long long s_efn;
