@@ -178,9 +178,10 @@ def ms_fixed_bytes(n: int, lanes: int, planes: int) -> float:
 
 def batch_bytes(total_n: int, reached: int, comp_edges: int) -> float:
     """The batched launch over all its instances: every depth written once
-    (4 per vertex), and per reached vertex its row_ptr pair read when it is
-    expanded and again when it is found (16), its queue slot written and read
-    (8), and its out-edges' column ids read once (4 per edge of the traversed
-    components, comp_edges).  Bottom-up levels read fewer column ids (early
+    (4 per vertex), and per reached vertex its row_ptr pair read once (8) and
+    its queue slot written and read (8), and its out-edges' column ids read
+    once (4 per edge of the traversed components, comp_edges) -- the
+    push-queue bytes per level summed over the search, with the visited
+    status in on-chip memory.  Bottom-up levels read fewer column ids (early
     exit), so this is the top-down cost of the method."""
-    return 4.0 * total_n + 24.0 * reached + 4.0 * comp_edges
+    return 4.0 * total_n + 16.0 * reached + 4.0 * comp_edges
