@@ -54,12 +54,12 @@ HBM_PEAK_GBS = 8000.0
 # with and the steps run with the same configuration.
 TILE_TRAFFIC = {
     "sources_sha256": {
-        "paper_2607_17106_amd/csrc/msbfs.hip": "41ecc66908a1778e387d98216831fc12c76be205cbf5c5785e925d9ed2b59ace",
+        "paper_2607_17106_amd/csrc/msbfs.hip": "7a6e3b18309f03c2d2e9eb45bd3ff1eb965365d34befdd2e1853a55bb7366de7",
         "paper_2607_17106_amd/csrc/common.hpp": "680997ca0cd797142a5ee549c5999761f8941a188c6a2706211b9097d8d80ac1",
     },
     "multi_config": {"wide_ratio": 16, "split_vpt": 4, "cap0": 32, "tile_alpha": 64, "alpha": 7, "split_lout": 16,
                      "wide_vpt": 2, "narrow_vpt": 4},
-    "fetch_kib": 180965.4, "write_kib": 107167.6, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 177267.5, "write_kib": 107147.4, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 # The same for k_batch on the 512-instance mix: `bench.py --steps 1 --warmup 1
@@ -68,12 +68,12 @@ TILE_TRAFFIC = {
 # below, whose two dispatches are averaged), with the copy calibration above.
 BATCH_TRAFFIC = {
     "sources_sha256": {
-        "paper_2607_17106_amd/csrc/batch.hip": "709d6ea097c5010f9c4e18836405eb3eb655b0f3661347b616c6fec7c019e3cc",
+        "paper_2607_17106_amd/csrc/batch.hip": "124645b73dd142d593a4d3a90b6c04557d106372acfcc326252925573de3a334",
         "paper_2607_17106_amd/csrc/common.hpp": "680997ca0cd797142a5ee549c5999761f8941a188c6a2706211b9097d8d80ac1",
     },
     "config": {"block_threads": 1024, "blocks_per_cu": 2, "small_vertices": 1048576, "team_vertices": 131072,
                "max_team": 8},
-    "fetch_kib": 16247922.5, "write_kib": 4355134.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 12061964.8, "write_kib": 5278854.0, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
