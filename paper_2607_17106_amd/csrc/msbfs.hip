@@ -43,9 +43,9 @@ constexpr int MS_T = 4;   // out-edges per lane before the wave-cooperative walk
 constexpr int MS_HEAD = 8; // in-edges a light vertex's own thread reads before the merged walk (pull)
 static_assert(MS_HEAD % 4 == 0, "the head is read in 16-byte pieces");
 constexpr int MS_PLANES = 8;       // relative depths 0..255 per window
-constexpr int MS_HEAVY = 1024;     // in-degree above which a vertex's in-edges are split over waves
+constexpr int MS_HEAVY = 2048;     // in-degree above which a vertex's in-edges are split over waves
 constexpr int MS_HCHUNK = 1024;    // in-edges per wave in the heavy pass (<= MS_HEAVY)
-constexpr int MS_EPT = 8;          // in-edges per thread per tile iteration (a multiple of 4)
+constexpr int MS_EPT = 4;          // in-edges per thread per tile iteration (a multiple of 4)
 struct __attribute__((packed, aligned(4))) I4u {  // four ints at any 4-byte-aligned address
   int x, y, z, w;
 };
@@ -1094,7 +1094,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
           }
           int own[MS_EPT], u[MS_EPT];
           if (o >= 0 && e0 + MS_EPT <= next_off) {
-            // all MS_EPT positions in owner o's list: two 16-byte loads
+            // all MS_EPT positions in owner o's list: MS_EPT / 4 16-byte loads
             // (4-byte aligned) instead of MS_EPT scalar ones
   #pragma unroll
             for (int i = 0; i < MS_EPT; ++i) own[i] = o;

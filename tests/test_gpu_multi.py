@@ -98,7 +98,7 @@ def test_directed_hubs(variant):
     g = gg.from_edge_list(n, np.stack([src, dst], 1), False)
     deg_out = np.diff(g.row_ptr)
     deg_in = np.diff(g.csc_ptr)
-    assert deg_out[7] > 1024 and deg_in[4242] > 1024 and deg_in[7] < 1024 and deg_out[4242] < 1024
+    assert deg_out[7] > 2048 and deg_in[4242] > 2048 and deg_in[7] < 2048 and deg_out[4242] < 2048
     _check(g, np.array([7, 4242, 1, 2, 3, 100, 7]), variant, level_stats=True)
 
 
@@ -263,7 +263,7 @@ def test_heavy_chunks_beyond_owner_table(variant):
     path = np.array([[i, i + 1] for i in range(39, 47)])
     e = np.concatenate([np.stack([src, dst], 1), path])
     g = gg.from_edge_list(n, e, False)
-    hchunks = int(np.sum(np.where(np.diff(g.csc_ptr) > 1024, (np.diff(g.csc_ptr) + 1023) // 1024, 0)))
+    hchunks = int(np.sum(np.where(np.diff(g.csc_ptr) > 2048, (np.diff(g.csc_ptr) + 1023) // 1024, 0)))
     assert hchunks > 2 * n + 1024
     _check(g, np.array([0, 5, 39, 40, 47, 3, 3]), variant, level_stats=True)
 
