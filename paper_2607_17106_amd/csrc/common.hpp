@@ -172,13 +172,17 @@ __device__ __forceinline__ u64 wave_sum_u64(u64 x) {
   return x;
 }
 
+// Inclusive sum over the wave (every lane active).  DPP moves, no LDS: shifts
+// by 1, 2, 4 and 8 inside each 16-lane row (a lane with no source adds the
+// move's old value, 0), then the last lane of rows 0 and 2 into rows 1 and 3,
+// then lane 31 into rows 2 and 3.
 __device__ __forceinline__ int wave_incl_scan(int x) {
-  const int l = lane();
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    int y = __shfl_up(x, (unsigned)o);
-    if (l >= o) x += y;
-  }
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1 and 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2 and 3
   return x;
 }
 

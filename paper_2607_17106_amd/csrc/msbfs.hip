@@ -921,6 +921,36 @@ __device__ __forceinline__ void ms_multi_scan(const int (&x)[VPT], int (&off)[VP
   __syncthreads();
 }
 
+// Inclusive segmented OR over the wave: lane l gets the OR of x over the lanes
+// l' <= l with key[l'] == key[l], for keys that never decrease from lane to
+// lane (a key's lanes are contiguous).  DPP moves instead of LDS permutes:
+// shifts by 1, 2, 4 and 8 inside each 16-lane row, then the last lane of row
+// 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3; a lane takes a
+// moved value only when its key is the lane's own (a lane with no source
+// keeps ~key, which never matches).  *tail: the lane is its key's last.
+__device__ __forceinline__ u64 ms_seg_or(u64 x, int key, bool *tail) {
+  u32 lo = (u32)x, hi = (u32)(x >> 32);
+#define MS_SEG_STEP(CTRL, ROWS)                                                       \
+  {                                                                                   \
+    const int yk = __builtin_amdgcn_update_dpp(~key, key, CTRL, ROWS, 0xf, false);    \
+    const u32 yl = (u32)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xf, false); \
+    const u32 yh = (u32)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, ROWS, 0xf, false); \
+    if (yk == key) {                                                                  \
+      lo |= yl;                                                                       \
+      hi |= yh;                                                                       \
+    }                                                                                 \
+  }
+  MS_SEG_STEP(0x111, 0xf)  // row_shr:1
+  MS_SEG_STEP(0x112, 0xf)  // row_shr:2
+  MS_SEG_STEP(0x114, 0xf)  // row_shr:4
+  MS_SEG_STEP(0x118, 0xf)  // row_shr:8
+  MS_SEG_STEP(0x142, 0xa)  // row_bcast:15, rows 1 and 3
+  MS_SEG_STEP(0x143, 0xc)  // row_bcast:31, rows 2 and 3
+#undef MS_SEG_STEP
+  *tail = __builtin_amdgcn_update_dpp(~key, key, 0x130, 0xf, 0xf, false) != key;  // wave_shl:1: lane l + 1's key
+  return ((u64)hi << 32) | lo;
+}
+
 // Bottom-up, tile part: one workgroup per tile of VPT * BLOCK consecutive
 // vertices (slot j of thread t holds vertex tile_base + j * BLOCK + t, so
 // every load and store of a slot is coalesced and a wave's slot is one word of
@@ -1155,14 +1185,8 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
             run |= f;
           }
           if (__ballot(run != 0ull)) {
-  #pragma unroll
-            for (int dd = 1; dd < WAVE; dd <<= 1) {
-              const u64 y = __shfl_up(run, (unsigned)dd);
-              const int oy = __shfl_up(ro, (unsigned)dd);
-              if (lane() >= dd && oy == ro) run |= y;
-            }
-            const int on = __shfl_down(ro, 1u);
-            const bool tail = lane() == WAVE - 1 || on != ro;
+            bool tail;
+            run = ms_seg_or(run, ro, &tail);
             if (tail && run) atomicOr(&s_acc[ro], run);
           }
         }
@@ -1199,14 +1223,8 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
             st.c[C_HITS] += hit[i] ? 1 : 0;
             if (__ballot(f != 0ull)) {
               const int oi = own[i];
-  #pragma unroll
-              for (int dd = 1; dd < WAVE; dd <<= 1) {
-                const u64 y = __shfl_up(f, (unsigned)dd);
-                const int oy = __shfl_up(oi, (unsigned)dd);
-                if (lane() >= dd && oy == oi) f |= y;
-              }
-              const int on = __shfl_down(oi, 1u);
-              const bool tail = lane() == WAVE - 1 || on != oi;
+              bool tail;
+              f = ms_seg_or(f, oi, &tail);
               if (tail && f) atomicOr(&s_acc[oi], f);
             }
           }
