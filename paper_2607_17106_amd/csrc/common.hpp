@@ -166,10 +166,26 @@ int hip_fail(hipError_t e, const char *what);
 // ------------------------------------------------------- device helpers
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
 
+// Sum over the wave (every lane active), returned in every lane: the DPP
+// inclusive scan of wave_incl_scan below on 64-bit values (two 32-bit moves
+// per step), then lane 63's total read into every lane.
 __device__ __forceinline__ u64 wave_sum_u64(u64 x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
+#define WAVE_SUM_STEP(CTRL, ROWS)                                                              \
+  {                                                                                            \
+    const u32 lo = (u32)__builtin_amdgcn_update_dpp(0, (int)(u32)x, CTRL, ROWS, 0xf, false);   \
+    const u32 hi = (u32)__builtin_amdgcn_update_dpp(0, (int)(u32)(x >> 32), CTRL, ROWS, 0xf, false); \
+    x += ((u64)hi << 32) | lo;                                                                 \
+  }
+  WAVE_SUM_STEP(0x111, 0xf)  // row_shr:1
+  WAVE_SUM_STEP(0x112, 0xf)  // row_shr:2
+  WAVE_SUM_STEP(0x114, 0xf)  // row_shr:4
+  WAVE_SUM_STEP(0x118, 0xf)  // row_shr:8
+  WAVE_SUM_STEP(0x142, 0xa)  // row_bcast:15, rows 1 and 3
+  WAVE_SUM_STEP(0x143, 0xc)  // row_bcast:31, rows 2 and 3
+#undef WAVE_SUM_STEP
+  const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)x, WAVE - 1);
+  const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(x >> 32), WAVE - 1);
+  return ((u64)hi << 32) | lo;
 }
 
 // Inclusive sum over the wave (every lane active).  DPP moves, no LDS: shifts
