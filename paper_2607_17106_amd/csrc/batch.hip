@@ -223,7 +223,7 @@ __device__ __forceinline__ void single_found(const int *rp, int *lv, const bool 
   }
   int base = 0;
   if (lane() == 0) base = atomicAdd(cnt, tot);
-  base = __shfl(base, 0);
+  base = lane_bcast(base, 0);
 #pragma unroll
   for (int j = 0; j < U; ++j) {
     if (won[j]) {
@@ -254,7 +254,7 @@ __device__ __forceinline__ void stage_flush(const int *rp, int *lv, const int *s
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   int base = 0;
   if (lane() == 0) base = atomicAdd(qcnt, cnt);
-  base = __shfl(base, 0);
+  base = lane_bcast(base, 0);
   constexpr int R = STAGE / WAVE;
   int w[R];
   int2 r[R];
@@ -382,7 +382,7 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
 #pragma unroll
         for (int r = 0; r < VPT; ++r)
           if (dd[r] <= LIGHT) lmax = max(lmax, dd[r]);
-        for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
+        lmax = wave_max_nonneg(lmax);
         int scnt = 0;  // staged finds of this wave (stg)
         for (int t0 = 0; t0 < lmax; t0 += 4) {
           int v[4 * VPT];
@@ -499,7 +499,7 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
         while (pm) {
           const int l = __ffsll((long long)pm) - 1;
           pm &= pm - 1;
-          const int vb = __shfl(bb, l), ve = __shfl(ee, l);
+          const int vb = lane_bcast(bb, l), ve = lane_bcast(ee, l);
           for (int base = vb; base < ve; base += WAVE) {
             const int j = base + lane();
             bool hit = false;
@@ -745,7 +745,7 @@ __device__ void search_team(const BatchArgs &A, int b, int m, char *dyn, int *s_
 #pragma unroll
           for (int r = 0; r < VPT; ++r)
             if (dd[r] <= LIGHT) lmax = max(lmax, dd[r]);
-          for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
+          lmax = wave_max_nonneg(lmax);
           for (int t0 = 0; t0 < lmax; t0 += 4) {
             int v[4 * VPT];
 #pragma unroll
@@ -828,7 +828,7 @@ __device__ void search_team(const BatchArgs &A, int b, int m, char *dyn, int *s_
         while (pm) {
           const int l = __ffsll((long long)pm) - 1;
           pm &= pm - 1;
-          const int vb = __shfl(bb, l), ve = __shfl(ee, l);
+          const int vb = lane_bcast(bb, l), ve = lane_bcast(ee, l);
           for (int base = vb; base < ve; base += WAVE) {
             const int j = base + lane();
             bool hit = false;

@@ -166,26 +166,73 @@ int hip_fail(hipError_t e, const char *what);
 // ------------------------------------------------------- device helpers
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
 
-// Sum over the wave (every lane active), returned in every lane: the DPP
-// inclusive scan of wave_incl_scan below on 64-bit values (two 32-bit moves
-// per step), then lane 63's total read into every lane.
-__device__ __forceinline__ u64 wave_sum_u64(u64 x) {
-#define WAVE_SUM_STEP(CTRL, ROWS)                                                              \
+// Inclusive 64-bit sum over the wave (every lane active): the DPP steps of
+// wave_incl_scan below with two 32-bit moves per step.
+__device__ __forceinline__ u64 wave_incl_scan_u64(u64 x) {
+#define WAVE_SCAN_STEP(CTRL, ROWS)                                                             \
   {                                                                                            \
     const u32 lo = (u32)__builtin_amdgcn_update_dpp(0, (int)(u32)x, CTRL, ROWS, 0xf, false);   \
     const u32 hi = (u32)__builtin_amdgcn_update_dpp(0, (int)(u32)(x >> 32), CTRL, ROWS, 0xf, false); \
     x += ((u64)hi << 32) | lo;                                                                 \
   }
-  WAVE_SUM_STEP(0x111, 0xf)  // row_shr:1
-  WAVE_SUM_STEP(0x112, 0xf)  // row_shr:2
-  WAVE_SUM_STEP(0x114, 0xf)  // row_shr:4
-  WAVE_SUM_STEP(0x118, 0xf)  // row_shr:8
-  WAVE_SUM_STEP(0x142, 0xa)  // row_bcast:15, rows 1 and 3
-  WAVE_SUM_STEP(0x143, 0xc)  // row_bcast:31, rows 2 and 3
-#undef WAVE_SUM_STEP
+  WAVE_SCAN_STEP(0x111, 0xf)  // row_shr:1
+  WAVE_SCAN_STEP(0x112, 0xf)  // row_shr:2
+  WAVE_SCAN_STEP(0x114, 0xf)  // row_shr:4
+  WAVE_SCAN_STEP(0x118, 0xf)  // row_shr:8
+  WAVE_SCAN_STEP(0x142, 0xa)  // row_bcast:15, rows 1 and 3
+  WAVE_SCAN_STEP(0x143, 0xc)  // row_bcast:31, rows 2 and 3
+#undef WAVE_SCAN_STEP
+  return x;
+}
+
+// Sum over the wave (every lane active), returned in every lane: the
+// inclusive scan above, then lane 63's total read into every lane.
+__device__ __forceinline__ u64 wave_sum_u64(u64 x) {
+  x = wave_incl_scan_u64(x);
   const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)x, WAVE - 1);
   const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(x >> 32), WAVE - 1);
   return ((u64)hi << 32) | lo;
+}
+
+// Lane l's value in every lane: a scalar read of one lane (l the same in every
+// lane, e.g. derived from a ballot; lane l need not be active now, only have
+// written x).
+__device__ __forceinline__ u32 lane_bcast(u32 x, int l) { return (u32)__builtin_amdgcn_readlane((int)x, l); }
+__device__ __forceinline__ int lane_bcast(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ u64 lane_bcast(u64 x, int l) {
+  return ((u64)lane_bcast((u32)(x >> 32), l) << 32) | lane_bcast((u32)x, l);
+}
+__device__ __forceinline__ float lane_bcast(float x, int l) { return __int_as_float(lane_bcast(__float_as_int(x), l)); }
+
+// OR over the wave (every lane active), in every lane: a DPP inclusive scan
+// on each 32-bit half (as wave_incl_scan below), then lane 63's result.
+__device__ __forceinline__ u64 wave_or_u64(u64 x) {
+  u32 lo = (u32)x, hi = (u32)(x >> 32);
+#define WAVE_OR_STEP(CTRL, ROWS)                                            \
+  {                                                                         \
+    lo |= (u32)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xf, false); \
+    hi |= (u32)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, ROWS, 0xf, false); \
+  }
+  WAVE_OR_STEP(0x111, 0xf)  // row_shr:1
+  WAVE_OR_STEP(0x112, 0xf)  // row_shr:2
+  WAVE_OR_STEP(0x114, 0xf)  // row_shr:4
+  WAVE_OR_STEP(0x118, 0xf)  // row_shr:8
+  WAVE_OR_STEP(0x142, 0xa)  // row_bcast:15, rows 1 and 3
+  WAVE_OR_STEP(0x143, 0xc)  // row_bcast:31, rows 2 and 3
+#undef WAVE_OR_STEP
+  return ((u64)lane_bcast(hi, WAVE - 1) << 32) | lane_bcast(lo, WAVE - 1);
+}
+
+// Maximum over the wave of non-negative ints (every lane active), in every
+// lane (a lane with no source in a step takes 0).
+__device__ __forceinline__ int wave_max_nonneg(int x) {
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
+  return lane_bcast(x, WAVE - 1);
 }
 
 // Inclusive sum over the wave (every lane active).  DPP moves, no LDS: shifts
@@ -229,7 +276,7 @@ __device__ __forceinline__ int wave_append(bool pred, u32 *counter) {
   int leader = __ffsll((long long)m) - 1;
   u32 base = 0;
   if (lane() == leader) base = atomicAdd(counter, (u32)__popcll(m));
-  base = __shfl(base, leader);
+  base = lane_bcast(base, leader);
   return pred ? (int)(base + (u32)__popcll(m & __lanemask_lt())) : -1;
 }
 
@@ -243,7 +290,7 @@ __device__ __forceinline__ void queue_push(bool pred, int v, const StepArgs &a) 
   const int leader = __ffsll((long long)m) - 1;
   u32 pos = 0;
   if (lane() == leader) pos = atomicAdd(&a.sh_next[s].count, (u32)__popcll(m));
-  pos = __shfl(pos, leader);
+  pos = lane_bcast(pos, leader);
   const int my = (int)pos + __popcll(m & __lanemask_lt());
   const bool over = pred && my >= a.qcap;
   if (pred && !over) a.q_next[(size_t)s * a.qcap + my] = v;
@@ -252,7 +299,7 @@ __device__ __forceinline__ void queue_push(bool pred, int v, const StepArgs &a) 
     const int l2 = __ffsll((long long)mo) - 1;
     u32 p2 = 0;
     if (lane() == l2) p2 = atomicAdd(&a.sh_next[NSH].count, (u32)__popcll(mo));
-    p2 = __shfl(p2, l2);
+    p2 = lane_bcast(p2, l2);
     if (over) a.q_next[(size_t)NSH * a.qcap + p2 + __popcll(mo & __lanemask_lt())] = v;
   }
 }

@@ -581,12 +581,7 @@ __device__ __forceinline__ long long ms_chunk_weight16(u64 light, int cw, int n,
 
 __device__ __forceinline__ long long block_excl_scan_ll(long long x, long long *total, long long *s_w) {
   const int w = threadIdx.x / WAVE;
-  long long incl = x;
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const long long y = __shfl_up(incl, (unsigned)o);
-    if (lane() >= o) incl += y;
-  }
+  const long long incl = (long long)wave_incl_scan_u64((u64)x);
   if (lane() == WAVE - 1) s_w[w] = incl;
   __syncthreads();
   long long off = 0, tot = 0;
@@ -868,8 +863,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a, int phase) {
           st.c[C_HITS] += 1;  // a gathered word (zero as well, on paths without the probe)
           st.c[C_HHITS] += 1;
         }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
+      f = wave_or_u64(f);
       mine |= f & need;
       if (lane() == 0) {
         st.c[C_SCAN] += (u32)min(MS_HU * WAVE, se - base);
@@ -879,7 +873,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_pull_heavy(MsArgs a, int phase) {
       if (++round % MS_POST == 0 && (mine & ~posted)) {
         u64 old = 0ull;
         if (lane() == 0) old = atomicOr(a.accb + v, mine);
-        known |= __shfl(old, 0);
+        known |= lane_bcast(old, 0);
         posted = mine;
         if (((known | mine) & need) == need) break;
       }
@@ -1286,7 +1280,7 @@ __device__ __forceinline__ void ms_push_or(const MsArgs &a, const int (&v)[NR], 
   if (tot == 0u) return;  // uniform
   u32 pos = 0;
   if (lane() == 0) pos = atomicAdd(a.tqn, tot);
-  pos = __shfl(pos, 0);
+  pos = lane_bcast(pos, 0);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (first[r]) a.tq[pos + __popcll(bm[r] & __lanemask_lt())] = v[r];
@@ -1317,7 +1311,7 @@ __device__ __forceinline__ void ms_clear_dead_sparse(const MsArgs &a) {
     const u64 lines = (y & 0x0101010101010101ull) * 0xFFull;
     for (u64 nz = __ballot(x != 0ull); nz; nz &= nz - 1ull) {
       const int i = __ffsll((long long)nz) - 1;
-      const u64 li = __shfl(lines, i);
+      const u64 li = lane_bcast(lines, i);
       if ((li >> lane()) & 1ull) a.dead[(size_t)(w0 + i) * WAVE + lane()] = 0ull;
     }
   }
@@ -1365,8 +1359,8 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsArgs a) {
     while (pm) {
       const int l = __ffsll((long long)pm) - 1;
       pm &= pm - 1;
-      const int vb = __shfl(b, l), ve = __shfl(e, l);
-      const u64 lf = __shfl(fu, l);
+      const int vb = lane_bcast(b, l), ve = lane_bcast(e, l);
+      const u64 lf = lane_bcast(fu, l);
       for (int base = vb; base < ve; base += MS_HU * WAVE) {  // MS_HU rounds of 64 edges, loads in flight together
         int v[MS_HU];
 #pragma unroll

@@ -158,7 +158,7 @@ __device__ __forceinline__ float forward_row_regs(const NetRegs &r, const float 
 // probability, 1 / sum_j exp(l_j - l_max).
 __device__ inline void argmax_conf(float logit, int *cls, float *conf) {
   static_assert(NC == 4, "four classes");
-  const float l0 = __shfl(logit, 0), l1 = __shfl(logit, 1), l2 = __shfl(logit, 2), l3 = __shfl(logit, 3);
+  const float l0 = lane_bcast(logit, 0), l1 = lane_bcast(logit, 1), l2 = lane_bcast(logit, 2), l3 = lane_bcast(logit, 3);
   int best = 0;
   float mx = l0;
   if (l1 > mx) { best = 1; mx = l1; }
@@ -229,8 +229,8 @@ __device__ __forceinline__ void body_select(const SelDevice &sd, RingSlot *ring,
   // were updated by lane 0 above); range check, then normalise
   bool out_of_range = false;
   float xn = 0.f;
-  const long long nU = ((long long)__shfl((int)(nU0 >> 32), 0) << 32) | (u32)__shfl((int)nU0, 0);
-  const long long eU = ((long long)__shfl((int)(eU0 >> 32), 0) << 32) | (u32)__shfl((int)eU0, 0);
+  const long long nU = (long long)lane_bcast((u64)nU0, 0);
+  const long long eU = (long long)lane_bcast((u64)eU0, 0);
   if (lane() < NF) {
     const float r = level_feature(lane(), (double)n, (double)nnz, (double)k, (double)nF, (double)c->edges,
                                   (double)nU, (double)eU, (double)c->ld, (double)c->ld2, (double)sd.gld,

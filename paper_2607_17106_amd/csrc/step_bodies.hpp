@@ -581,7 +581,7 @@ __device__ __forceinline__ void body_adv_tmp_b(const StepArgs &a, char *smem, in
         d = a.rp[v + 1] - beg;
       }
       const int in = wave_incl_scan(d);
-      const int wt = __shfl(in, WAVE - 1);
+      const int wt = lane_bcast(in, WAVE - 1);
       const int wbase = wend - wt;
       incl[lane()] = in;
       su[lane()] = v;
@@ -641,7 +641,7 @@ __device__ __forceinline__ void body_push_b(const StepArgs &a, char *smem) {
       d = 0;
     }
     int in = wave_incl_scan(d);
-    const int total = __shfl(in, WAVE - 1);
+    const int total = lane_bcast(in, WAVE - 1);
     incl[lane()] = in;
     su[lane()] = v;
     so[lane()] = beg - (in - d);
@@ -716,7 +716,7 @@ __device__ __forceinline__ void body_push_p3(const StepArgs &a, char *smem) {
       d = 0;
     }
     int in = wave_incl_scan(d);
-    const int total = __shfl(in, WAVE - 1);
+    const int total = lane_bcast(in, WAVE - 1);
     incl[lane()] = in;
     su[lane()] = v;
     so[lane()] = beg - (in - d);
@@ -832,7 +832,7 @@ __device__ __forceinline__ void body_pull(const StepArgs &a) {
     while (pm) {
       const int l = __ffsll((long long)pm) - 1;
       pm &= pm - 1;
-      const int vb = __shfl(b, l), ve = __shfl(e, l);
+      const int vb = lane_bcast(b, l), ve = lane_bcast(e, l);
       for (int base = vb; base < ve; base += WAVE) {
         const int j = base + lane();
         int uu = -1;
@@ -845,7 +845,7 @@ __device__ __forceinline__ void body_pull(const StepArgs &a) {
         const u64 hm = __ballot(hit);
         if (hm) {
           const int f = __ffsll((long long)hm) - 1;
-          const int p = __shfl(uu, f);
+          const int p = lane_bcast(uu, f);
           if (lane() == l) {
             found = true;
             par = p;
