@@ -212,7 +212,7 @@ typedef struct bfs_options {
                                     its first entry >= T, and the frontier vertices >= T push
                                     their out-edges first; together they cover every edge, so
                                     the depths do not depend on T.  0: T = the number of
-                                    vertices of out-degree > 1024 when BFS_F_HUB_ORDER is set
+                                    vertices of out-degree > 2048 when BFS_F_HUB_ORDER is set
                                     (they are vertices 0 .. T-1 there), used on the bottom-up
                                     levels where the frontier is sparse and its out-edges from
                                     vertices >= T are few; otherwise no split.  > 0: T =
