@@ -962,8 +962,11 @@ __device__ __forceinline__ u64 ms_seg_or(u64 x, int key, bool *tail) {
 // done-check, one segmented scan per position.  Heavy vertices take the heavy pass's result from accb.  Also
 // writes next, the next bitmap and the discoveries, and clears the dead
 // frontier buffer.  SPLIT: a split level (MsArgs::split_t).
+// At least 5 waves per SIMD: the four-vertex forms fit 96 registers without
+// spilling (4 waves at their unconstrained 102-106), and the extra wave hides
+// more of the load chain (tile pass 133 -> 126 us per launch); 6 would spill.
 template <int VPT, bool SUM, bool CONSEC, bool SPLIT = false, bool PROBE = true>
-__global__ __launch_bounds__(BLOCK) void k_ms_pull_tile(MsArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_ms_pull_tile(MsArgs a) {
   constexpr int TV = VPT * BLOCK;
   extern __shared__ u32 s_sum[];
   __shared__ int s_off[TV + 1];
