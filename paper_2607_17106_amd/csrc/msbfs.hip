@@ -1749,11 +1749,14 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
     if (pend_r < 0) return BFS_OK;
     const hipEvent_t *P = hc.lev_ev + 4 * (pend_slot % 16);
     float ms = 0.f;
+    // the level's post can be seen before the runtime has marked its events done
     if (st->level_ms_main) {
+      BFS_HIP(hipEventSynchronize(P[2]));
       BFS_HIP(hipEventElapsedTime(&ms, P[1], P[2]));
       st->level_ms_main[pend_r] = ms;
     }
     if (st->level_ms && timing) {
+      BFS_HIP(hipEventSynchronize(P[3]));
       BFS_HIP(hipEventElapsedTime(&ms, P[0], P[3]));
       st->level_ms[pend_r] = ms;
     }

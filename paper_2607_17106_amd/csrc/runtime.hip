@@ -517,6 +517,8 @@ static int run_single(const bfs_graph *g, int src, int *levels, int *parents, co
       ++syncs;
       if (timing) {
         float ms = 0.f;
+        // the post can be seen before the runtime has marked the event done
+        BFS_HIP(hipEventSynchronize(hc.ev[3]));
         BFS_HIP(hipEventElapsedTime(&ms, hc.ev[2], hc.ev[3]));
         level_ms.push_back(ms);
       }

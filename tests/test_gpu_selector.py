@@ -58,8 +58,10 @@ def test_trained_selector_gain_over_heuristic(weights):
     direction heuristic alone:
     * the gain the network is trained for -- the device time of the steps its
       schedule runs, summed over the searches (each level timed by HIP events
-      around its step), must not exceed the heuristic schedule's, with no
-      slack;
+      around its step; a schedule is the same on every run of a source, so
+      each level step counts with the fastest of three runs, interference
+      only ever adding time), must not exceed the heuristic schedule's, with
+      no slack;
     * end to end (wall time of whole searches, median of 5 passes taken in
       turns) the per-level evaluation of the network is paid as well: the
       measured ratio is printed, and the learned mode must stay within 10% of
@@ -74,8 +76,12 @@ def test_trained_selector_gain_over_heuristic(weights):
     for name, mode in (("learned", B.AUTO_LEARNED), ("heuristic", B.AUTO_HEURISTIC)):
         tot = 0.0
         for s in srcs:
-            _, st = B.bfs_levels(dg, int(s), variant=mode, flags=B.F_LEVEL_TIMING, workspace=ws, levels=lv)
-            tot += float(st["ms"].sum())
+            runs = []
+            for _ in range(3):
+                _, st = B.bfs_levels(dg, int(s), variant=mode, flags=B.F_LEVEL_TIMING, workspace=ws, levels=lv)
+                runs.append(np.asarray(st["ms"][: st["num_levels"]], dtype=np.float64))
+            assert len({len(r) for r in runs}) == 1  # the same levels on every run
+            tot += float(np.min(np.stack(runs), axis=0).sum())
         step_ms[name] = tot
     wall = {"learned": [], "heuristic": []}
     for _ in range(5):
