@@ -1398,7 +1398,10 @@ __global__ __launch_bounds__(MS_PQ_BLOCK) void k_ms_push_split(MsArgs a) {
   __shared__ u64 s_hub[MS_PQ_HUB];
   __shared__ int s_q[WAVE * WAVE];  // one round: up to 64 words of 64 vertices
   __shared__ int s_qn;
-  const int nh = min(a.push_lo, MS_PQ_HUB);
+  // the first MS_PQ_HUB targets, hubs or not: on a graph numbered by degree
+  // they take the most pushes (the pull that follows starts from these
+  // unmasked words and keeps only the lanes each vertex misses)
+  const int nh = min(a.n, MS_PQ_HUB);
   for (int i = threadIdx.x; i < nh; i += MS_PQ_BLOCK) s_hub[i] = 0ull;
   MsStats st;
   constexpr int WPB = MS_PQ_BLOCK / WAVE;
@@ -1459,10 +1462,10 @@ __global__ __launch_bounds__(MS_PQ_BLOCK) void k_ms_push_split(MsArgs a) {
 }
 
 // Merges the MS_PQ_GRID staging rows of k_ms_push_split into `next` for the
-// targets below min(push_lo, MS_PQ_HUB): thread (i, g) ORs rows
+// targets below min(n, MS_PQ_HUB): thread (i, g) ORs rows
 // g * MS_PQ_ROWS .. + MS_PQ_ROWS - 1 of column i.
 __global__ __launch_bounds__(BLOCK) void k_ms_hub_or(MsArgs a) {
-  const int nh = min(a.push_lo, MS_PQ_HUB);
+  const int nh = min(a.n, MS_PQ_HUB);
   const int i = blockIdx.x * BLOCK + threadIdx.x, g = blockIdx.y;
   if (i >= nh) return;
   const u64 *col = a.hubst + (size_t)g * MS_PQ_ROWS * MS_PQ_HUB + i;
@@ -1934,7 +1937,7 @@ extern "C" int bfs_multi(const bfs_graph *g, const int32_t *sources, int32_t k, 
           ap.zplane = nullptr;
           ap.push_lo = a.hub_t;
           hipLaunchKernelGGL(k_ms_push_split, dim3(MS_PQ_GRID), dim3(MS_PQ_BLOCK), 0, s, ap);
-          hipLaunchKernelGGL(k_ms_hub_or, dim3((std::min(a.hub_t, MS_PQ_HUB) + BLOCK - 1) / BLOCK,
+          hipLaunchKernelGGL(k_ms_hub_or, dim3((std::min(a.n, MS_PQ_HUB) + BLOCK - 1) / BLOCK,
                                                MS_PQ_GRID / MS_PQ_ROWS), dim3(BLOCK), 0, s, ap);
           a.split_t = a.hub_t;
         }
