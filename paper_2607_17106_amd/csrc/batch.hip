@@ -14,14 +14,16 @@
 // (gfx950's 160 KB hold it for 2^20 vertices), so every claim is an LDS
 // atomic; device-wide 64-bit atomics run at about 27 G/s on this chip, loads
 // at ten times that, so a per-edge global atomic would bound the batch.  The
-// frontier is a queue in the instance's global state, and all
-// synchronisation is workgroup barriers.
+// frontier is a queue in the instance's global state (each entry the vertex
+// with its row offsets), and all synchronisation is workgroup barriers.
 //   top-down: 4 x block_threads queue vertices per pass.  A list of at most
 //     LIGHT edges is expanded by its vertex's own lane in rounds of 4 edges
-//     (the lane's 4 vertices at once); longer lists are flattened with a
+//     (the lane's 4 vertices at once), each wave on its own; the winners of
+//     unvisited targets' LDS atomicOr are staged per wave in LDS and recorded
+//     64 at a time (depth, row offsets, queue entry; one reservation per
+//     flush).  On levels with longer lists a second sweep flattens them with a
 //     workgroup scan (Table 3, variant 1 at workgroup scale), each lane taking
-//     U consecutive edges per round.  The winner of an unvisited target's LDS
-//     atomicOr records its depth and appends it (one reservation per wave).
+//     U consecutive edges per round.
 //   bottom-up (symmetric instances): the queue is scattered into a frontier
 //     bitmap (LDS when it fits, else global); each wave owns 64 consecutive
 //     vertices, tests the first in-edges of every unvisited one (loads issued
