@@ -16,9 +16,9 @@
 // at ten times that, so a per-edge global atomic would bound the batch.  The
 // frontier is a queue in the instance's global state (each entry the vertex
 // with its row offsets), and all synchronisation is workgroup barriers.
-//   top-down: 4 x block_threads queue vertices per pass.  A list of at most
+//   top-down: 2 x block_threads queue vertices per pass.  A list of at most
 //     LIGHT edges is expanded by its vertex's own lane in rounds of 4 edges
-//     (the lane's 4 vertices at once), each wave on its own; the winners of
+//     (the lane's 2 vertices at once), each wave on its own; the winners of
 //     unvisited targets' LDS atomicOr are staged per wave in LDS and recorded
 //     64 at a time (depth, row offsets, queue entry; one reservation per
 //     flush).  On levels with longer lists a second sweep flattens them with a
@@ -311,7 +311,10 @@ __device__ __forceinline__ void stage_add(const int *rp, int *lv, int *stg, int 
 template <int BT>
 __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, int *s_incl, int *s_w, int *s_qn,
                               unsigned long long *s_efn) {
-  constexpr int VPT = 4;             // queue vertices per lane per pass
+  // queue vertices per lane per pass: 2 keeps the 1024-thread form within its
+  // 128 registers with less spilling than 4 (20 bytes a lane against 60;
+  // a side-1024 lattice 4.6 -> 4.45 ms)
+  constexpr int VPT = 2;
   constexpr int CAP = VPT * BT;      // queue vertices per pass
   constexpr int HCAP = 2 * BT;       // heavy lists flattened per half pass
   constexpr int U = 4;               // heavy edges per lane per round
