@@ -313,7 +313,8 @@ __device__ void search_single(const BatchArgs &A, int b, char *dyn, int *s_off, 
                               unsigned long long *s_efn) {
   // queue vertices per lane per pass: 2 keeps the 1024-thread form within its
   // 128 registers with less spilling than 4 (20 bytes a lane against 60;
-  // a side-1024 lattice 4.6 -> 4.45 ms)
+  // a side-1024 lattice 4.6 -> 4.45 ms).  Even: the long-list sweep takes a
+  // lane's vertices in pairs.
   constexpr int VPT = 2;
   constexpr int CAP = VPT * BT;      // queue vertices per pass
   constexpr int HCAP = 2 * BT;       // heavy lists flattened per half pass
